@@ -1,0 +1,244 @@
+"""Benchmark of the sparse-grid MPM step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload landslide|collapse_3d]
+
+Prints ONE JSON line.  A step is one pass of the whole hot path -- active-node
+indexing (bin, radix sort, hash insert, compaction), P2G, grid update and G2P --
+over the workload's particles, all resident in HBM before timing starts.
+
+* value      particle-steps/s of the sparse step (N_p x K / wall time of K steps,
+             HIP events on the compute stream, bracketed by synchronisation);
+* dense      the same step with the dense background grid (every block of the
+             potential domain cleared and updated each step), same kernels;
+* roofline   the dominant kernel's algorithmic bytes per launch over its
+             average event-timed duration, against the 8 TB/s HBM peak;
+* cpu_baseline  the FP64 oracle on a bounded sample of the same workload on the
+             host (one thread).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "particle-steps/s (sparse vs dense, 1 GPU); adjoint/forward step time ratio"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="landslide", choices=["landslide", "collapse_3d"])
+    ap.add_argument("--dense-steps", type=int, default=10)
+    ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--block-capacity", type=int, default=0)
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    from paper_2605_28525_amd import workloads as wl
+    if name == "landslide":
+        return wl.landslide()
+    return wl.collapse_3d()
+
+
+def time_steps(sim, steps, stream, phases=True):
+    """Time `steps` full steps on `stream` with HIP events: one event pair around
+    the whole run (wall time) and, with ``phases``, events between the four calls
+    of every step (per-call durations, which for P2G, grid update and G2P are
+    single-kernel launches).  Returns (seconds, {phase: mean ms})."""
+    import torch
+    from paper_2605_28525_amd import mpm as M
+    torch.cuda.synchronize()
+    if not phases:
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step(steps, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3, {}
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    for k in range(steps):
+        a, b = sim.a.view(), sim.b.view()
+        e = ev[k]
+        e[0].record(stream)
+        M.mpm_sparse_build(sim.ctx, a, stream)
+        e[1].record(stream)
+        M.mpm_p2g(sim.ctx, a, stream)
+        e[2].record(stream)
+        M.mpm_grid_update(sim.ctx, stream)
+        e[3].record(stream)
+        M.mpm_g2p(sim.ctx, a, b, stream)
+        e[4].record(stream)
+        sim.a, sim.b = sim.b, sim.a
+    torch.cuda.synchronize()
+    t = np.array([[ev[k][i].elapsed_time(ev[k][i + 1]) for i in range(4)] for k in range(steps)])
+    total = ev[0][0].elapsed_time(ev[-1][4]) / 1e3
+    return total, dict(zip(["build", "p2g", "grid_update", "g2p"], t.mean(axis=0).tolist()))
+
+
+def src_digest(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2605_28525_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload, digest):
+    """HBM traffic per launch from a committed rocprofv3 --pmc summary, only if it
+    was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("src_digest") != digest:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(w_name, budget_s):
+    """FP64 oracle on a bounded sample of the workload, single thread."""
+    from oracle import mpm as om
+    from paper_2605_28525_amd import workloads as wl
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        limiter = None
+    if w_name == "landslide":
+        w = wl.landslide_crop()
+        sample = "landslide window 64x64x256 cells (same terrain, dx = 1 m), 16,384 particles"
+    else:
+        w = wl.collapse_3d(scale=2)
+        sample = "3D collapse at 1/8 volume, 262,144 particles"
+    p = om.Params.from_workload(w)
+    st = om.state_from_soa(w.state(), w.dim)
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        st = om.step(st, p)
+        steps += 1
+    dt = time.perf_counter() - t0
+    if limiter is not None:
+        limiter.unregister() if hasattr(limiter, "unregister") else None
+    return {"value": w.n * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample}, {steps} steps in {dt:.1f} s, float64 numpy, 1 of {os.cpu_count()} host cores"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design "
+                                   "(see DESIGN.md), not an implemented path", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_2605_28525_amd import mpm as M
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    log(f"bench: generating {args.workload}")
+    w = make_workload(args.workload)
+    n = w.n
+    d = w.dim
+    log(f"bench: {w.name} n={n} cells={w.cells}")
+    cap = args.block_capacity or (1 << 18 if args.workload == "landslide" else 1 << 16)
+    sim = M.Simulation(w, block_capacity=cap)
+    log("bench: warmup")
+    if args.warmup:
+        sim.step(args.warmup, stream=stream)
+    rc, flags = sim.status()
+    if rc != 0:
+        raise SystemExit(f"device status after warmup: {rc} flags={flags}")
+    nb, nt = M.mpm_active_count(sim.ctx)
+    log(f"bench: timed {args.steps} steps (active blocks {nb})")
+    t, ph = time_steps(sim, args.steps, stream)
+    rc, flags = sim.status()
+    if rc != 0:
+        raise SystemExit(f"device status after timing: {rc} flags={flags}")
+    value = n * args.steps / t
+    ms_per_step = 1e3 * t / args.steps
+    nb, nt = M.mpm_active_count(sim.ctx)
+    npb = 4 ** d
+    n_slot = nb * npb
+    n_dense_nodes = int(np.prod([c + 1 for c in w.cells[:d]]))
+    # algorithmic bytes (counted once per field per kernel of the dataflow)
+    g2p_bytes = n * (4 * d + 4 * d * d + 4 + 4 * (d + d + d * d + d * d + (3 if d == 2 else 6)) + 8) + 16 * n_slot
+    p2g_bytes = n * (4 * (d + d + d * d + (3 if d == 2 else 6)) + 4) + 16 * n_slot
+    kernels = {"g2p": (g2p_bytes, ph["g2p"]), "p2g": (p2g_bytes, ph["p2g"])}
+    dom = max(kernels, key=lambda k: kernels[k][1])
+    dom_bytes, dom_ms = kernels[dom]
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    digest = src_digest("transfer.hip", "internal.h")
+    traffic = measured_traffic(dom, args.workload, digest)
+    build_bytes = n * 16 + 24 * (1 << max(10, int(np.ceil(np.log2(2 * cap))))) + 16 * nb
+    step_bytes = (276 if d == 3 else 148) * n + (72 if d == 3 else 52) * n_slot
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "particles": n, "cells": list(w.cells[:d]), "dx_m": w.dx,
+                   "block": "4^3", "grid": "sparse"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "phases_ms": ph,
+        "build_ms_per_step": ph["build"],
+        "build_roofline_frac": build_bytes / (ph["build"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "step_roofline_frac": step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "active_blocks": nb,
+        "active_fraction": n_slot / n_dense_nodes,
+    }
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    if not args.no_dense:
+        log("bench: dense baseline")
+        simd = M.Simulation(w, grid_mode=M.MPM_GRID_DENSE)
+        simd.step(2, stream=stream)
+        td, _ = time_steps(simd, args.dense_steps, stream, phases=False)
+        rc, flags = simd.status()
+        if rc != 0:
+            raise SystemExit(f"dense status: {rc} flags={flags}")
+        dense_value = n * args.dense_steps / td
+        out["dense"] = {"value": dense_value, "ms_per_step": 1e3 * td / args.dense_steps,
+                        "steps": args.dense_steps}
+        out["speedup_vs_dense"] = value / dense_value
+        simd.close()
+        del simd
+        torch.cuda.empty_cache()
+    if not args.no_cpu:
+        log("bench: cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

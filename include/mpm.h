@@ -1,0 +1,210 @@
+/*
+ * mpm.h -- C ABI of the sparse-grid explicit material point method step
+ * (HIP, gfx950).
+ *
+ * One explicit step (Methods 3.1 of "Unified sparse framework for large-scale
+ * simulations using the material point method") on a background grid whose
+ * storage is restricted to the active nodes A = union_p S(p) (Eqs. 4-5):
+ *
+ *   mpm_sparse_build   active-node indexing: the active blocks of B^d nodes
+ *                      (B = 4), their compact indices Phi and the compact node
+ *                      map phi(n) = Phi(b(n)) B^d + l(n) (Methods 3.2-3.3,
+ *                      Algorithms 1 and 5-7, Eqs. 18, 22-25);
+ *   mpm_p2g            particle-to-grid transfer onto the compact storage
+ *                      (Eqs. 6-7 mass and APIC momentum, Eq. 9 internal force);
+ *   mpm_grid_update    nodal velocity normalisation and explicit Euler update
+ *                      (Eqs. 8, 10-12) followed by boundary conditions;
+ *   mpm_g2p            grid-to-particle APIC gather, position, affine matrix
+ *                      and deformation-gradient update (Eqs. 13-17) and the
+ *                      constitutive update (Hencky elasticity or a
+ *                      Drucker-Prager return map on Hencky strain);
+ *   mpm_step           n_steps x (build; p2g; grid update; g2p).
+ *
+ * Conventions
+ * -----------
+ * - All particle arrays are DEVICE pointers owned by the caller, float32,
+ *   structure-of-arrays and component-major with plane stride n:
+ *     x[a*n + p], v[a*n + p]               a < d
+ *     C[(r*d + c)*n + p], F[(r*d + c)*n + p] row-major d x d
+ *     tau[k*n + p]  Kirchhoff stress, 2D (xx, yy, xy), 3D (xx, yy, zz, xy, yz, xz)
+ *     id[p]         optional uint32 particle identity carried along (may be NULL)
+ * - Nodes sit at x_n = n * dx, n = (i, j[, k]) with 0 <= n_a <= cells[a]
+ *   (Eq. 3).  A particle's support is the 3^d stencil from its base node
+ *   floor(x/dx - 1/2); every stencil node must lie inside the grid, otherwise the
+ *   step raises MPM_FLAG_DOMAIN (positions are clamped so no access leaves the
+ *   grid).
+ * - The library REORDERS particles: mpm_g2p reads the input set through the
+ *   sort permutation of the last build and writes the output set in sorted
+ *   (block-key) order; id[] travels with each particle.
+ * - stream is a hipStream_t (NULL = the default stream).  Every call only
+ *   enqueues work on it, except where stated ("synchronises").
+ * - Every call returns an MPM_* status and never aborts.  Argument errors are
+ *   reported synchronously.  Conditions found on the device (hash overflow,
+ *   domain exit, inverted deformation, non-finite values) are latched in a
+ *   sticky device status word read by mpm_get_status.
+ * - One context per stream; a context is not thread-safe across host threads.
+ */
+#ifndef MPM_H
+#define MPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mpm_ctx mpm_ctx;
+
+/* return codes */
+#define MPM_OK            0
+#define MPM_ERR_ARG       1   /* invalid argument (null pointer, size, capacity) */
+#define MPM_ERR_HIP       2   /* a HIP runtime call failed */
+#define MPM_ERR_NOMEM     3   /* device allocation failed */
+#define MPM_ERR_OVERFLOW  4   /* hash table or block capacity exceeded */
+#define MPM_ERR_DOMAIN    5   /* a particle support left the grid */
+#define MPM_ERR_INVERTED  6   /* a trial deformation gradient has det <= 0 */
+#define MPM_ERR_NAN       7   /* a non-finite value was produced */
+#define MPM_ERR_STATE     8   /* call out of order (e.g. p2g before a build) */
+
+/* bits of the sticky device status word */
+#define MPM_FLAG_OVERFLOW 1u
+#define MPM_FLAG_DOMAIN   2u
+#define MPM_FLAG_INVERTED 4u
+#define MPM_FLAG_NAN      8u
+
+/* boundary condition of one grid face (nodes within `bound` of the face) */
+#define MPM_BC_NONE     0   /* no constraint */
+#define MPM_BC_STICKY   1   /* v = 0 */
+#define MPM_BC_SLIP     2   /* normal component set to 0 */
+#define MPM_BC_SEPARATE 3   /* normal component may only point away from the face */
+
+/* constitutive models */
+#define MPM_MODEL_ELASTIC 0   /* Hencky (logarithmic-strain) elasticity */
+#define MPM_MODEL_DP      1   /* cohesionless Drucker-Prager return map on Hencky strain */
+
+/* grid storage */
+#define MPM_GRID_SPARSE 0     /* active blocks only (the method) */
+#define MPM_GRID_DENSE  1     /* every block of the potential domain (baseline) */
+
+/* flags */
+#define MPM_FLAG_SYNC_REBUILD 1  /* mpm_sparse_build synchronises and, on overflow,
+                                    doubles the table and block capacity and rebuilds
+                                    (Algorithm 7) until it fits */
+
+typedef struct mpm_params {
+    int dim;                 /* 2 or 3 */
+    double dx;               /* grid spacing h (Eq. 3), metres */
+    int cells[3];            /* cells per axis; nodes per axis = cells + 1 */
+    float gravity[3];        /* body force per unit mass g (Eq. 10) */
+    float dt;                /* time step (Eqs. 11-17) */
+    int bound;               /* wall thickness in nodes (default 3 when 0) */
+    int bc[3][2];            /* MPM_BC_* per axis, [0] low face, [1] high face */
+    const float* heightmap;  /* HOST pointer, (cells[0]+1) x (cells[1]+1) node heights,
+                                x-major (h[i*(cells[1]+1) + j]); 3D only, z up; copied at
+                                create; NULL = no terrain */
+    float mu_terrain;        /* Coulomb friction of the terrain */
+    int model;               /* MPM_MODEL_* */
+    float E, nu;             /* Young's modulus (Pa) and Poisson ratio */
+    float friction_deg;      /* Drucker-Prager friction angle (degrees) */
+    float p_mass;            /* particle mass m_p (kg) */
+    float p_vol0;            /* initial particle volume V0_p */
+    int max_particles;       /* capacity of every per-particle buffer */
+    int block_capacity;      /* max active blocks (0 = default) */
+    int hash_capacity_log2;  /* log2 H of the block hash table (0 = default) */
+    int grid_mode;           /* MPM_GRID_* */
+    int flags;               /* MPM_FLAG_SYNC_REBUILD ... */
+} mpm_params;
+
+typedef struct mpm_particles {
+    int n;                   /* number of particles (<= max_particles) */
+    float* x;
+    float* v;
+    float* C;
+    float* F;
+    float* tau;
+    uint32_t* id;            /* optional */
+} mpm_particles;
+
+/* Create a context: validates *params, copies the heightmap, allocates every
+ * device buffer (nothing is allocated by later calls except on an Algorithm-7
+ * rebuild).  On success *out owns them; returns MPM_ERR_ARG / MPM_ERR_NOMEM /
+ * MPM_ERR_HIP otherwise and leaves *out NULL. */
+int mpm_create(const mpm_params* params, mpm_ctx** out);
+
+/* Free a context and all its device memory (synchronises the device). */
+int mpm_destroy(mpm_ctx* ctx);
+
+/* Human-readable name of an MPM_* return code (static storage). */
+const char* mpm_status_string(int status);
+
+/* Active-node indexing (Methods 3.3, Algorithms 5-6, Eqs. 22-25, with the
+ * block layout of Methods 3.2): bins the particles by base node, sorts them by
+ * 4^d-block key, inserts every block touched by a stencil into the open-
+ * addressing table (packed key, Eq. 22; 64-bit mixer, Eq. 23; slot h & (H-1),
+ * Eq. 24; linear probing, Eq. 25), records the node-level active mask of each
+ * block, and compacts the occupied slots into Phi in [0, n_blocks) by a prefix
+ * scan.  A pure function of the positions.  If more blocks are touched than
+ * block_capacity, or a probe sequence finds no slot, MPM_FLAG_OVERFLOW is
+ * latched (with MPM_FLAG_SYNC_REBUILD the call rebuilds instead, Algorithm 7).
+ * In MPM_GRID_DENSE mode Phi is the linear block index of the whole domain. */
+int mpm_sparse_build(mpm_ctx* ctx, const mpm_particles* p, void* stream);
+
+/* P2G onto the compact storage (Eqs. 6, 7, 9): clears the active blocks and
+ * accumulates per node m_n and p_n = sum_p N m_p [v_p + C_p (x_n - x_p)]
+ * - dt sum_p V0_p tau_p grad N_n.  Requires a build of the same positions. */
+int mpm_p2g(mpm_ctx* ctx, const mpm_particles* p, void* stream);
+
+/* Grid update (Eqs. 8, 10-12): v_n = p_n / m_n + dt g where m_n > 0, else 0,
+ * then boundary conditions (terrain level set with Coulomb friction, then the
+ * walls).  Operates on the storage filled by mpm_p2g. */
+int mpm_grid_update(mpm_ctx* ctx, void* stream);
+
+/* G2P (Eqs. 13-17) and the constitutive update.  Reads `in` through the sort
+ * permutation of the last build and writes the advanced state to `out` in
+ * sorted order; `in` and `out` must not overlap and must have the same n. */
+int mpm_g2p(mpm_ctx* ctx, const mpm_particles* in, const mpm_particles* out, void* stream);
+
+/* n_steps explicit steps ping-ponging between a and b: step 0 reads a and
+ * writes b, step 1 reads b and writes a, ...  The final state is in a when
+ * n_steps is even and in b when it is odd. */
+int mpm_step(mpm_ctx* ctx, const mpm_particles* a, const mpm_particles* b, int n_steps, void* stream);
+
+/* Synchronises `stream` and returns the sticky MPM_FLAG_* word in *flags;
+ * the return code is MPM_OK when no flag is set, else the MPM_ERR_* of the
+ * lowest flag set. */
+int mpm_get_status(mpm_ctx* ctx, void* stream, uint32_t* flags);
+
+/* Clears the sticky status word (enqueued). */
+int mpm_clear_status(mpm_ctx* ctx, void* stream);
+
+/* Synchronises `stream` and reports the number of active blocks of the last
+ * build (n_blocks) and the number of occupied hash slots before the capacity
+ * check (n_touched, > n_blocks only on overflow). */
+int mpm_active_count(mpm_ctx* ctx, void* stream, int* n_blocks, int* n_touched);
+
+/* Copies, for compact blocks 0..min(n_blocks, capacity)-1 in Phi order, the
+ * packed block key of Eq. 22 (m = 21, bias 2^20; 2D packs (i, j) in the low
+ * 42 bits) into keys[] and the node-level active mask (bit l(n) =
+ * i_l + 4 (j_l + 4 k_l) set iff node n is in A) into masks[].  Device pointers
+ * owned by the caller.  Sparse mode only. */
+int mpm_get_active(mpm_ctx* ctx, uint64_t* keys, uint64_t* masks, int capacity, void* stream);
+
+/* Copies the compact grid, 4 floats per node, blocks 0..min(n_blocks,
+ * capacity)-1 in Phi order, nodes in l(n) order within a block: after mpm_p2g
+ * (p_x, p_y, p_z, m); after mpm_grid_update (v_x, v_y, v_z, m) (2D: z = 0).
+ * Device pointer owned by the caller, capacity * 4^d * 4 floats. */
+int mpm_get_grid(mpm_ctx* ctx, float* out, int capacity_blocks, void* stream);
+
+/* Copies the sort permutation of the last build: order[i] = index in the input
+ * set of the particle written to position i by mpm_g2p.  Device pointer. */
+int mpm_get_order(mpm_ctx* ctx, uint32_t* order, int n, void* stream);
+
+/* Replaces the material constants (E, nu, friction angle) and dt of a live
+ * context without reallocating. */
+int mpm_set_material(mpm_ctx* ctx, float E, float nu, float friction_deg, float dt);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPM_H */

@@ -1,0 +1,400 @@
+// Active-node indexing on the GPU (Methods 3.3, Algorithms 5-6; Eqs. 22-25).
+//
+//   k_bin           base node per particle (float64 index arithmetic), owner
+//                   block and a u32 sort key = linear block id << 2d | local
+//                   cell of the base node;
+//   radix sort      (sort.hip) groups particles by owner block;
+//   k_hash_clear    keys <- EMPTY, masks <- 0 (Algorithm 5, initialisation);
+//   k_hash_insert   per sorted particle: the stencil touches its owner block and
+//                   only the upper neighbours it spills into (base local index
+//                   >= 2 on an axis), so at most 2^d blocks.  Lanes of a wave64
+//                   that share an owner block are merged (ballot/readlane loop)
+//                   and their node masks OR-reduced, then one lane per touched
+//                   block claims or finds the slot: packed key (Eq. 22), mixer
+//                   (Eq. 23), slot h & (H - 1) (Eq. 24), linear probing (Eq. 25)
+//                   with a compare-and-swap on EMPTY (Algorithm 6), and ORs the
+//                   node mask into the slot.  The owner run boundaries of the
+//                   sorted order are recorded per slot.
+//   compaction      prefix scan over occupied slots -> Phi in slot order; block
+//                   keys, masks and owner segments in Phi order; overflow when
+//                   more than block_capacity slots are occupied (the counter
+//                   check of Algorithm 6).
+//   block setup     upper-neighbour compact indices (so P2G/G2P never probe),
+//                   chunking of owner segments into work items, grid clear.
+#include "internal.h"
+#include "../../include/mpm.h"
+
+namespace mpmx {
+
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_bin(DevParams P, const float* __restrict__ x, int n,
+                                            uint32_t* __restrict__ keys) {
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= n) return;
+    int b[3] = {0, 0, 0};
+    unsigned bad = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        double f = floor(index_arg(x[(size_t)a * n + i], P.inv_dx));
+        if (!(f == f)) {
+            bad |= MPM_FLAG_NAN;
+            f = 0.0;
+        } else if (f < 0.0 || f + 2.0 > (double)P.cells[a]) {
+            bad |= MPM_FLAG_DOMAIN;
+            f = fmin(fmax(f, 0.0), (double)(P.cells[a] - 2));
+        }
+        b[a] = (int)f;
+    }
+    if (bad) raise_flag(P.ctr, bad);
+    uint32_t bl, cell;
+    if (DIM == 3) {
+        bl = ((uint32_t)(b[2] >> 2) * (uint32_t)P.nblk[1] + (uint32_t)(b[1] >> 2)) * (uint32_t)P.nblk[0] +
+             (uint32_t)(b[0] >> 2);
+        cell = (b[0] & 3) | ((b[1] & 3) << 2) | ((b[2] & 3) << 4);
+    } else {
+        bl = (uint32_t)(b[1] >> 2) * (uint32_t)P.nblk[0] + (uint32_t)(b[0] >> 2);
+        cell = (b[0] & 3) | ((b[1] & 3) << 2);
+    }
+    keys[i] = (bl << (2 * DIM)) | cell;
+}
+
+__device__ int hash_insert(const DevParams& P, uint64_t K) {
+    unsigned s = (unsigned)mix64(K) & P.h_mask_bits;
+    for (int r = 0; r < P.n_probe; ++r) {
+        uint64_t cur = __hip_atomic_load(&P.h_keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == K) return (int)s;
+        if (cur == EMPTY_KEY) {
+            uint64_t old = atomicCAS((unsigned long long*)&P.h_keys[s], (unsigned long long)EMPTY_KEY,
+                                     (unsigned long long)K);
+            if (old == EMPTY_KEY || old == K) return (int)s;
+        }
+        s = (s + 1) & P.h_mask_bits;
+    }
+    raise_flag(P.ctr, MPM_FLAG_OVERFLOW);
+    return -1;
+}
+
+__device__ int hash_lookup(const DevParams& P, uint64_t K) {
+    unsigned s = (unsigned)mix64(K) & P.h_mask_bits;
+    for (int r = 0; r < P.n_probe; ++r) {
+        uint64_t cur = P.h_keys[s];
+        if (cur == K) return P.h_vals[s];
+        if (cur == EMPTY_KEY) return -1;
+        s = (s + 1) & P.h_mask_bits;
+    }
+    return -1;
+}
+
+__global__ __launch_bounds__(WG) void k_hash_clear(DevParams P, unsigned H) {
+    for (unsigned s = blockIdx.x * WG + threadIdx.x; s < H; s += gridDim.x * WG) {
+        P.h_keys[s] = EMPTY_KEY;
+        P.h_mask[s] = 0ull;
+        P.h_start[s] = -1;
+        P.h_end[s] = -1;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        P.ctr->nb = 0;
+        P.ctr->n_touched = 0;
+        P.ctr->n_work = 0;
+    }
+}
+
+// spread a 4-bit row mask to the j-rows (stride 4) / k-planes (stride 16) of a 4^d block
+__device__ __forceinline__ uint64_t spread_j(unsigned r) {
+    return (uint64_t)((r & 1u) | ((r & 2u) << 3) | ((r & 4u) << 6) | ((r & 8u) << 9));
+}
+__device__ __forceinline__ uint64_t spread_k(unsigned r) {
+    return (uint64_t)(r & 1u) | ((uint64_t)(r & 2u) << 15) | ((uint64_t)(r & 4u) << 30) | ((uint64_t)(r & 8u) << 45);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_hash_insert(DevParams P, const uint32_t* __restrict__ skeys, int n) {
+    constexpr int NB = 1 << DIM;
+    constexpr int CB = 2 * DIM;
+    const int i = blockIdx.x * WG + threadIdx.x;
+    const int lane = __lane_id();
+    const bool valid = i < n;
+    const uint32_t key = valid ? skeys[i] : 0u;
+    const uint32_t bl = key >> CB;
+    int l[3] = {(int)(key & 3u), (int)((key >> 2) & 3u), DIM == 3 ? (int)((key >> 4) & 3u) : 0};
+    int bc[3];
+    linear_to_block<DIM>(P, bl, bc);
+    // rows of the stencil [l, l+2] inside the owner block (lo) and spilled into the upper block (hi)
+    unsigned lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int top = min(l[a] + 2, 3);
+        lo[a] = ((1u << (top + 1)) - 1u) & ~((1u << l[a]) - 1u);
+        hi[a] = l[a] >= 2 ? ((1u << (l[a] - 1)) - 1u) : 0u;
+    }
+    uint64_t m[NB];
+#pragma unroll
+    for (int d = 0; d < NB; ++d) {
+        const unsigned rx = (d & 1) ? hi[0] : lo[0];
+        const unsigned ry = (d & 2) ? hi[1] : lo[1];
+        if (DIM == 3) {
+            const unsigned rz = (d & 4) ? hi[2] : lo[2];
+            m[d] = (uint64_t)rx * spread_j(ry) * spread_k(rz);
+        } else {
+            m[d] = (uint64_t)rx * spread_j(ry);
+        }
+        if (!valid) m[d] = 0ull;
+    }
+    const uint64_t ko = pack_key<DIM>(bc[0], bc[1], bc[2]);
+    const bool is_start = valid && (i == 0 || (skeys[i - 1] >> CB) != bl);
+    const bool is_end = valid && (i == n - 1 || (skeys[i + 1] >> CB) != bl);
+
+    unsigned long long todo = __ballot(valid);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const uint64_t K = readlane64(ko, leader);
+        const bool mine = valid && ko == K;
+        const unsigned long long grp = __ballot(mine);
+        const int lbx = readlane32(bc[0], leader), lby = readlane32(bc[1], leader), lbz = readlane32(bc[2], leader);
+        uint64_t mymask = 0ull;
+#pragma unroll
+        for (int d = 0; d < NB; ++d) {
+            const unsigned long long any = __ballot(mine && m[d] != 0ull);
+            if (any) {
+                const uint64_t r = wave_or64(mine ? m[d] : 0ull);
+                if (lane == d) mymask = r;
+            }
+        }
+        int slot = -1;
+        if (lane < NB && mymask != 0ull) {
+            const uint64_t Kd = pack_key<DIM>(lbx + (lane & 1), lby + ((lane >> 1) & 1), lbz + ((lane >> 2) & 1));
+            slot = hash_insert(P, Kd);
+            if (slot >= 0) atomicOr((unsigned long long*)&P.h_mask[slot], (unsigned long long)mymask);
+        }
+        const int so = readlane32(slot, 0);
+        if (mine && so >= 0) {
+            if (is_start) P.h_start[so] = i;
+            if (is_end) P.h_end[so] = i + 1;
+        }
+        todo &= ~grp;
+    }
+}
+
+__global__ __launch_bounds__(WG) void k_compact_count(DevParams P, int H, unsigned* __restrict__ partials) {
+    __shared__ unsigned lds[WG / 64];
+    const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    unsigned s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        const int idx = base + j;
+        if (idx < H && P.h_keys[idx] != EMPTY_KEY) ++s;
+    }
+    unsigned tot;
+    wg_excl_scan(s, lds, &tot);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(WG) void k_compact_write(DevParams P, int H, const unsigned* __restrict__ partials) {
+    __shared__ unsigned lds[WG / 64];
+    const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    bool occ[SCAN_ITEMS];
+    unsigned s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        const int idx = base + j;
+        occ[j] = idx < H && P.h_keys[idx] != EMPTY_KEY;
+        s += occ[j];
+    }
+    unsigned tot;
+    unsigned phi = wg_excl_scan(s, lds, &tot) + partials[blockIdx.x];
+    bool over = false;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        if (!occ[j]) continue;
+        const int idx = base + j;
+        if ((int)phi < P.block_cap) {
+            P.b_keys[phi] = P.h_keys[idx];
+            P.b_mask[phi] = P.h_mask[idx];
+            const int st = P.h_start[idx];
+            P.b_start[phi] = st;
+            P.b_count[phi] = st >= 0 ? P.h_end[idx] - st : 0;
+            P.h_vals[idx] = (int)phi;
+        } else {
+            P.h_vals[idx] = -1;
+            over = true;
+        }
+        ++phi;
+    }
+    if (over) raise_flag(P.ctr, MPM_FLAG_OVERFLOW);
+    if (blockIdx.x == 0 && threadIdx.x == 0) P.ctr->nb = min(P.ctr->n_touched, P.block_cap);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_block_setup(DevParams P) {
+    constexpr int NB = 1 << DIM;
+    const int nb = P.ctr->nb;
+    for (int b = blockIdx.x * WG + threadIdx.x; b < nb; b += gridDim.x * WG) {
+        int bc[3];
+        unpack_key<DIM>(P.b_keys[b], bc);
+        P.b_nbr[b * NB] = b;
+#pragma unroll
+        for (int d = 1; d < NB; ++d)
+            P.b_nbr[b * NB + d] = hash_lookup(P, pack_key<DIM>(bc[0] + (d & 1), bc[1] + ((d >> 1) & 1),
+                                                                bc[2] + ((d >> 2) & 1)));
+        P.b_chunks[b] = (unsigned)((P.b_count[b] + P.chunk - 1) / P.chunk);
+    }
+}
+
+__global__ __launch_bounds__(WG) void k_work_write(DevParams P) {
+    const int nb = P.ctr->nb;
+    bool over = false;
+    for (int b = blockIdx.x * WG + threadIdx.x; b < nb; b += gridDim.x * WG) {
+        const int c = (int)P.b_chunks[b];
+        const int off = (int)P.b_chunk_off[b];
+        const int st = P.b_start[b], cnt = P.b_count[b];
+        for (int j = 0; j < c; ++j) {
+            const int w = off + j;
+            if (w >= P.work_cap) {
+                over = true;
+                break;
+            }
+            P.w_block[w] = b;
+            P.w_start[w] = st + j * P.chunk;
+            P.w_end[w] = min(st + (j + 1) * P.chunk, st + cnt);
+        }
+    }
+    if (over) raise_flag(P.ctr, MPM_FLAG_OVERFLOW);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_grid_clear(DevParams P, long long n_nodes_host) {
+    constexpr int NPB = 1 << (2 * DIM);
+    const long long n_nodes = n_nodes_host >= 0 ? n_nodes_host : (long long)P.ctr->nb * NPB;
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (long long s = (long long)blockIdx.x * WG + threadIdx.x; s < n_nodes; s += (long long)gridDim.x * WG)
+        P.grid[s] = z;
+}
+
+// ---- dense baseline: Phi(b) = linear block index over the whole domain ----
+__global__ __launch_bounds__(WG) void k_dense_clear_seg(DevParams P, int n_blocks) {
+    for (int b = blockIdx.x * WG + threadIdx.x; b < n_blocks; b += gridDim.x * WG) {
+        P.b_start[b] = -1;
+        P.b_count[b] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        P.ctr->nb = n_blocks;
+        P.ctr->n_touched = n_blocks;
+        P.ctr->n_work = 0;
+    }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_dense_segments(DevParams P, const uint32_t* __restrict__ skeys, int n) {
+    constexpr int CB = 2 * DIM;
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t bl = skeys[i] >> CB;
+    if (i == 0 || (skeys[i - 1] >> CB) != bl) P.b_start[bl] = i;
+    if (i == n - 1 || (skeys[i + 1] >> CB) != bl) P.b_count[bl] = i + 1;  // end, converted below
+}
+
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_dense_setup(DevParams P, int n_blocks) {
+    constexpr int NB = 1 << DIM;
+    for (int b = blockIdx.x * WG + threadIdx.x; b < n_blocks; b += gridDim.x * WG) {
+        const int st = P.b_start[b];
+        const int cnt = st >= 0 ? P.b_count[b] - st : 0;
+        P.b_count[b] = cnt;
+        P.b_chunks[b] = (unsigned)((cnt + P.chunk - 1) / P.chunk);
+        int bc[3];
+        linear_to_block<DIM>(P, (uint32_t)b, bc);
+#pragma unroll
+        for (int d = 0; d < NB; ++d) {
+            const int x = bc[0] + (d & 1), y = bc[1] + ((d >> 1) & 1), z = bc[2] + ((d >> 2) & 1);
+            const bool in = x < P.nblk[0] && y < P.nblk[1] && (DIM == 2 || z < P.nblk[2]);
+            P.b_nbr[b * NB + d] = in ? (DIM == 3 ? (z * P.nblk[1] + y) * P.nblk[0] + x : y * P.nblk[0] + x) : -1;
+        }
+    }
+}
+
+__global__ __launch_bounds__(WG) void k_copy_active(DevParams P, uint64_t* keys, uint64_t* masks, int cap) {
+    const int nb = min(P.ctr->nb, cap);
+    for (int b = blockIdx.x * WG + threadIdx.x; b < nb; b += gridDim.x * WG) {
+        keys[b] = P.b_keys[b];
+        masks[b] = P.b_mask[b];
+    }
+}
+
+static int grid_for(long long items, int cap_wgs = 8192) {
+    long long g = (items + WG - 1) / WG;
+    if (g < 1) g = 1;
+    if (g > cap_wgs) g = cap_wgs;
+    return (int)g;
+}
+
+hipError_t launch_bin(const DevParams& P, const float* x, int n, uint32_t* keys, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (P.dim == 3)
+        k_bin<3><<<(n + WG - 1) / WG, WG, 0, s>>>(P, x, n, keys);
+    else
+        k_bin<2><<<(n + WG - 1) / WG, WG, 0, s>>>(P, x, n, keys);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_sparse(const DevParams& P, const uint32_t* skeys, int n, unsigned H, unsigned* partials,
+                               hipStream_t s) {
+    k_hash_clear<<<grid_for(H), WG, 0, s>>>(P, H);
+    if (n > 0) {
+        if (P.dim == 3)
+            k_hash_insert<3><<<(n + WG - 1) / WG, WG, 0, s>>>(P, skeys, n);
+        else
+            k_hash_insert<2><<<(n + WG - 1) / WG, WG, 0, s>>>(P, skeys, n);
+    }
+    const int tiles = ((int)H + SCAN_TILE - 1) / SCAN_TILE;
+    k_compact_count<<<tiles, WG, 0, s>>>(P, (int)H, partials);
+    scan_partials(partials, tiles, (unsigned*)&P.ctr->n_touched, s);
+    k_compact_write<<<tiles, WG, 0, s>>>(P, (int)H, partials);
+    const int gb = grid_for(P.block_cap, 2048);
+    if (P.dim == 3)
+        k_block_setup<3><<<gb, WG, 0, s>>>(P);
+    else
+        k_block_setup<2><<<gb, WG, 0, s>>>(P);
+    hipError_t e = scan_exclusive(P.b_chunks, P.b_chunk_off, P.block_cap, &P.ctr->nb, partials,
+                                  (unsigned*)&P.ctr->n_work, s);
+    if (e != hipSuccess) return e;
+    k_work_write<<<gb, WG, 0, s>>>(P);
+    const int NPB = P.dim == 3 ? 64 : 16;
+    if (P.dim == 3)
+        k_grid_clear<3><<<grid_for((long long)P.block_cap * NPB), WG, 0, s>>>(P, -1);
+    else
+        k_grid_clear<2><<<grid_for((long long)P.block_cap * NPB), WG, 0, s>>>(P, -1);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_dense(const DevParams& P, const uint32_t* skeys, int n, int n_blocks, unsigned* partials,
+                              hipStream_t s) {
+    const int gb = grid_for(n_blocks);
+    k_dense_clear_seg<<<gb, WG, 0, s>>>(P, n_blocks);
+    if (n > 0) {
+        if (P.dim == 3)
+            k_dense_segments<3><<<(n + WG - 1) / WG, WG, 0, s>>>(P, skeys, n);
+        else
+            k_dense_segments<2><<<(n + WG - 1) / WG, WG, 0, s>>>(P, skeys, n);
+    }
+    if (P.dim == 3)
+        k_dense_setup<3><<<gb, WG, 0, s>>>(P, n_blocks);
+    else
+        k_dense_setup<2><<<gb, WG, 0, s>>>(P, n_blocks);
+    hipError_t e = scan_exclusive(P.b_chunks, P.b_chunk_off, n_blocks, nullptr, partials,
+                                  (unsigned*)&P.ctr->n_work, s);
+    if (e != hipSuccess) return e;
+    k_work_write<<<gb, WG, 0, s>>>(P);
+    const long long NPB = P.dim == 3 ? 64 : 16;
+    if (P.dim == 3)
+        k_grid_clear<3><<<grid_for((long long)n_blocks * NPB, 65536), WG, 0, s>>>(P, (long long)n_blocks * NPB);
+    else
+        k_grid_clear<2><<<grid_for((long long)n_blocks * NPB, 65536), WG, 0, s>>>(P, (long long)n_blocks * NPB);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_active(const DevParams& P, uint64_t* keys, uint64_t* masks, int cap, hipStream_t s) {
+    k_copy_active<<<grid_for(cap, 2048), WG, 0, s>>>(P, keys, masks, cap);
+    return hipGetLastError();
+}
+
+}  // namespace mpmx

@@ -1,0 +1,224 @@
+// Internal declarations of the sparse-grid MPM library (gfx950, wave64).
+//
+// Device data layout (all in HBM, owned by the context):
+//   sort      key/value ping-pong buffers, u32 x max_particles each; per-tile
+//             digit histograms;
+//   hash      H slots: packed block key (u64, EMPTY = ~0), node mask (u64),
+//             compact index (i32), first/one-past-last sorted particle of the
+//             block's owner segment (i32);
+//   blocks    block_capacity entries in compact order Phi: key, node mask,
+//             2^d neighbour compact indices (upper neighbours), owner segment
+//             start and length, P2G/G2P chunk count and offset;
+//   work      (block, first, last) particle ranges of at most CHUNK particles;
+//   grid      block_capacity * 4^d nodes, one float4 per node (p_x, p_y, p_z, m),
+//             then (v_x, v_y, v_z, m) after the grid update.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mpm.h"
+
+namespace mpmx {
+
+constexpr int WG = 256;            // workgroup size of every kernel (4 wave64s)
+constexpr int BLK = 4;             // block edge B (Methods 3.2)
+constexpr int KEY_M = 21;          // bits per packed coordinate (Eq. 22)
+constexpr int64_t KEY_BIAS = 1 << 20;
+constexpr uint64_t EMPTY_KEY = ~0ull;
+
+constexpr int SORT_ITEMS = 16;                 // keys per thread per radix tile
+constexpr int SORT_TILE = WG * SORT_ITEMS;     // 4096 keys per tile
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = WG * SCAN_ITEMS;     // 2048 values per scan tile
+
+struct DevCounters {
+    int nb;          // active blocks (compact count, <= capacity)
+    int n_touched;   // occupied hash slots (may exceed capacity on overflow)
+    int n_work;      // P2G/G2P work items
+    unsigned flags;  // sticky MPM_FLAG_* bits
+    int pad[4];
+};
+
+struct DevParams {
+    int dim;
+    int cells[3];
+    int nblk[3];          // blocks per axis over the node range [0, cells]
+    int dense;
+    double dx, inv_dx;
+    float dxf, inv_dxf, dt;
+    float g[3];
+    float mu, lam, alpha, dp_coef;   // Lame, DP cone alpha, (d lambda + 2 mu)/(2 mu)
+    int model;
+    float p_mass, p_vol0;
+    int bound;
+    int bc[3][2];
+    const float* heightmap;
+    float mu_terrain;
+    int has_terrain;
+    // hash table
+    uint64_t* h_keys;
+    uint64_t* h_mask;
+    int* h_vals;
+    int* h_start;
+    int* h_end;
+    unsigned h_mask_bits;   // H - 1
+    int n_probe;
+    // compact blocks
+    uint64_t* b_keys;
+    uint64_t* b_mask;
+    int* b_nbr;
+    int* b_start;
+    int* b_count;
+    unsigned* b_chunks;
+    unsigned* b_chunk_off;
+    int block_cap;
+    // work items
+    int* w_block;
+    int* w_start;
+    int* w_end;
+    int work_cap;
+    int chunk;
+    // grid
+    float4* grid;
+    DevCounters* ctr;
+};
+
+// ---------------------------------------------------------------------------
+// device helpers
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    // SplitMix64 output function (Steele, Lea, Flood 2014), a 64-bit mixer of
+    // the kind cited for Eq. 23.
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <int DIM>
+__device__ __forceinline__ uint64_t pack_key(int bx, int by, int bz) {
+    // Eq. 22: ((i + b) << 2m) | ((j + b) << m) | (k + b); 2D packs (i, j) low.
+    if (DIM == 3)
+        return ((uint64_t)(bx + KEY_BIAS) << (2 * KEY_M)) | ((uint64_t)(by + KEY_BIAS) << KEY_M) |
+               (uint64_t)(bz + KEY_BIAS);
+    return ((uint64_t)(bx + KEY_BIAS) << KEY_M) | (uint64_t)(by + KEY_BIAS);
+}
+
+template <int DIM>
+__device__ __forceinline__ void unpack_key(uint64_t k, int* b) {
+    const uint64_t m = (1ull << KEY_M) - 1;
+    if (DIM == 3) {
+        b[0] = (int)((k >> (2 * KEY_M)) & m) - (int)KEY_BIAS;
+        b[1] = (int)((k >> KEY_M) & m) - (int)KEY_BIAS;
+        b[2] = (int)(k & m) - (int)KEY_BIAS;
+    } else {
+        b[0] = (int)((k >> KEY_M) & m) - (int)KEY_BIAS;
+        b[1] = (int)(k & m) - (int)KEY_BIAS;
+        b[2] = 0;
+    }
+}
+
+// Base node floor(x * (1/dx) - 1/2) in float64, multiply and subtract rounded
+// separately (no contraction), and the fractional offset s - floor(s).
+__device__ __forceinline__ double index_arg(float x, double inv_dx) {
+#pragma clang fp contract(off)
+    double s = (double)x * inv_dx;
+    return s - 0.5;
+}
+
+template <int DIM>
+__device__ __forceinline__ void linear_to_block(const DevParams& P, uint32_t bl, int* bc) {
+    bc[0] = (int)(bl % (uint32_t)P.nblk[0]);
+    uint32_t r = bl / (uint32_t)P.nblk[0];
+    if (DIM == 3) {
+        bc[1] = (int)(r % (uint32_t)P.nblk[1]);
+        bc[2] = (int)(r / (uint32_t)P.nblk[1]);
+    } else {
+        bc[1] = (int)r;
+        bc[2] = 0;
+    }
+}
+
+// Block coordinates of compact block b (sparse: from its packed key; dense: b is
+// the linear block index).
+template <int DIM>
+__device__ __forceinline__ void block_coords(const DevParams& P, int b, int* bc) {
+    if (P.dense)
+        linear_to_block<DIM>(P, (uint32_t)b, bc);
+    else
+        unpack_key<DIM>(P.b_keys[b], bc);
+}
+
+__device__ __forceinline__ unsigned long long wave_ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
+    unsigned lo = __builtin_amdgcn_readlane((unsigned)v, lane);
+    unsigned hi = __builtin_amdgcn_readlane((unsigned)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ int readlane32(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+__device__ __forceinline__ void raise_flag(DevCounters* c, unsigned f) { atomicOr(&c->flags, f); }
+
+// Inclusive scan across a wave64.
+__device__ __forceinline__ unsigned wave_incl_scan(unsigned v) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        unsigned t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan across a 256-thread workgroup; lds needs 4 entries.
+__device__ __forceinline__ unsigned wg_excl_scan(unsigned v, unsigned* lds, unsigned* total) {
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
+    unsigned inc = wave_incl_scan(v);
+    if (lane == 63) lds[w] = inc;
+    __syncthreads();
+    unsigned off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < WG / 64; ++i) {
+        unsigned s = lds[i];
+        off += (i < w) ? s : 0u;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers (each returns hipError_t of the launch)
+hipError_t scan_exclusive(const unsigned* in, unsigned* out, int n, const int* n_dev, unsigned* partials,
+                          unsigned* total_out, hipStream_t s);
+int scan_partials_size(int n);
+hipError_t scan_partials(unsigned* partials, int tiles, unsigned* total_out, hipStream_t s);
+
+hipError_t radix_sort(const uint32_t* keys_in, uint32_t* k0, uint32_t* k1, uint32_t* v0, uint32_t* v1, int n,
+                      int key_bits, unsigned* hist, unsigned* partials, uint32_t** keys_out, uint32_t** vals_out,
+                      hipStream_t s);
+int radix_hist_size(int n);
+
+hipError_t launch_bin(const DevParams& P, const float* x, int n, uint32_t* keys, hipStream_t s);
+hipError_t launch_build_sparse(const DevParams& P, const uint32_t* skeys, int n, unsigned H, unsigned* partials,
+                               hipStream_t s);
+hipError_t launch_build_dense(const DevParams& P, const uint32_t* skeys, int n, int n_blocks, unsigned* partials,
+                              hipStream_t s);
+hipError_t launch_p2g(const DevParams& P, const float* x, const float* v, const float* C, const float* tau, int n,
+                      const uint32_t* order, int grid_blocks, hipStream_t s);
+hipError_t launch_grid_update(const DevParams& P, long long n_nodes_host, int grid_blocks, hipStream_t s);
+hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, const uint32_t* id_in, float* x_out,
+                      float* v_out, float* C_out, float* F_out, float* tau_out, uint32_t* id_out, int n,
+                      const uint32_t* order, int grid_blocks, hipStream_t s);
+hipError_t launch_clear_flags(DevCounters* c, hipStream_t s);
+hipError_t launch_copy_active(const DevParams& P, uint64_t* keys, uint64_t* masks, int cap, hipStream_t s);
+
+}  // namespace mpmx

@@ -1,0 +1,121 @@
+// Stable LSD radix sort of (u32 key, u32 value) pairs, 8-bit digits.
+//
+// Each pass is reduce-then-scan: a per-tile digit histogram, a device scan of
+// the (digit-major, tile-minor) histogram matrix, then a stable scatter.  A tile
+// is 4096 keys; each wave64 owns a contiguous quarter of it and ranks its keys
+// round by round with a wave-wide digit match (8 ballots), keeping per-wave
+// running digit counts in LDS, so no LDS atomics and no intra-tile barriers are
+// needed until the wave offsets are combined.
+#include "internal.h"
+
+namespace mpmx {
+
+__device__ __forceinline__ unsigned long long digit_match(unsigned dg, bool valid) {
+    unsigned long long m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (dg >> b) & 1u;
+        const unsigned long long bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+__global__ __launch_bounds__(WG) void k_radix_hist(const uint32_t* __restrict__ keys, int n, int shift,
+                                                   unsigned* __restrict__ hist, int n_tiles) {
+    __shared__ unsigned cnt[WG / 64][256];
+    for (int t = threadIdx.x; t < (WG / 64) * 256; t += WG) (&cnt[0][0])[t] = 0;
+    __syncthreads();
+    const int w = threadIdx.x >> 6, lane = __lane_id();
+    const int base = blockIdx.x * SORT_TILE + w * (SORT_TILE / (WG / 64));
+#pragma unroll 4
+    for (int r = 0; r < SORT_ITEMS; ++r) {
+        const int pos = base + r * 64 + lane;
+        const bool valid = pos < n;
+        const uint32_t k = valid ? keys[pos] : 0u;
+        const unsigned dg = (k >> shift) & 255u;
+        const unsigned long long m = digit_match(dg, valid);
+        if (valid && (__ffsll((long long)m) - 1) == lane) cnt[w][dg] += (unsigned)__popcll(m);
+    }
+    __syncthreads();
+    const int t = threadIdx.x;  // one digit per thread (WG == 256)
+    hist[(size_t)t * n_tiles + blockIdx.x] = cnt[0][t] + cnt[1][t] + cnt[2][t] + cnt[3][t];
+}
+
+__global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t* __restrict__ kin,
+                                                      const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+                                                      uint32_t* __restrict__ vout, int n, int shift,
+                                                      const unsigned* __restrict__ hist, int n_tiles) {
+    __shared__ unsigned run[WG / 64][256];
+    __shared__ unsigned off[WG / 64][256];
+    for (int t = threadIdx.x; t < (WG / 64) * 256; t += WG) (&run[0][0])[t] = 0;
+    __syncthreads();
+    const int w = threadIdx.x >> 6, lane = __lane_id();
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    const int base = blockIdx.x * SORT_TILE + w * (SORT_TILE / (WG / 64));
+    uint32_t k[SORT_ITEMS], v[SORT_ITEMS];
+    unsigned rk[SORT_ITEMS];
+#pragma unroll
+    for (int r = 0; r < SORT_ITEMS; ++r) {
+        const int pos = base + r * 64 + lane;
+        const bool valid = pos < n;
+        k[r] = valid ? kin[pos] : 0u;
+        v[r] = valid ? (vin ? vin[pos] : (uint32_t)pos) : 0u;
+        const unsigned dg = (k[r] >> shift) & 255u;
+        const unsigned long long m = digit_match(dg, valid);
+        const unsigned cur = run[w][dg];
+        rk[r] = cur + (unsigned)__popcll(m & lt);
+        if (valid && (__ffsll((long long)m) - 1) == lane) run[w][dg] = cur + (unsigned)__popcll(m);
+    }
+    __syncthreads();
+    {
+        const int t = threadIdx.x;
+        unsigned o = hist[(size_t)t * n_tiles + blockIdx.x];
+#pragma unroll
+        for (int ww = 0; ww < WG / 64; ++ww) {
+            off[ww][t] = o;
+            o += run[ww][t];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < SORT_ITEMS; ++r) {
+        const int pos = base + r * 64 + lane;
+        if (pos < n) {
+            const unsigned dg = (k[r] >> shift) & 255u;
+            const unsigned dst = off[w][dg] + rk[r];
+            kout[dst] = k[r];
+            vout[dst] = v[r];
+        }
+    }
+}
+
+int radix_hist_size(int n) { return 256 * ((n + SORT_TILE - 1) / SORT_TILE); }
+
+// Sorts n keys read from keys_in (which must be neither k0 nor ... k0 is the
+// first destination).  Values start as the identity 0..n-1.  Pass p writes
+// (k0, v0) when p is even and (k1, v1) when odd; *keys_out / *vals_out point
+// at the final pair.
+hipError_t radix_sort(const uint32_t* keys_in, uint32_t* k0, uint32_t* k1, uint32_t* v0, uint32_t* v1, int n,
+                      int key_bits, unsigned* hist, unsigned* partials, uint32_t** keys_out, uint32_t** vals_out,
+                      hipStream_t s) {
+    const int n_tiles = (n + SORT_TILE - 1) / SORT_TILE;
+    const int passes = key_bits <= 8 ? 1 : (key_bits + 7) / 8;
+    const uint32_t* kin = keys_in;
+    const uint32_t* vin = nullptr;
+    for (int p = 0; p < passes; ++p) {
+        uint32_t* ko = (p & 1) ? k1 : k0;
+        uint32_t* vo = (p & 1) ? v1 : v0;
+        k_radix_hist<<<n_tiles, WG, 0, s>>>(kin, n, 8 * p, hist, n_tiles);
+        hipError_t e = scan_exclusive(hist, hist, 256 * n_tiles, nullptr, partials, nullptr, s);
+        if (e != hipSuccess) return e;
+        k_radix_scatter<<<n_tiles, WG, 0, s>>>(kin, vin, ko, vo, n, 8 * p, hist, n_tiles);
+        kin = ko;
+        vin = vo;
+    }
+    *keys_out = const_cast<uint32_t*>(kin);
+    *vals_out = const_cast<uint32_t*>(vin);
+    return hipGetLastError();
+}
+
+}  // namespace mpmx

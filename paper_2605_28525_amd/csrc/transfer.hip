@@ -1,0 +1,631 @@
+// P2G, grid update and G2P on the compact block storage (Methods 3.1,
+// Eqs. 6-17), with quadratic B-spline weights.
+//
+// Work is organised by owner block: a work item is a run of at most CHUNK
+// particles (contiguous in sorted order) whose base nodes lie in one block.
+// Their 3^d stencils cover a (4+2)^d node tile anchored at that block's origin,
+// which spans the block and its upper neighbours (2^d blocks).
+//
+//   P2G: a workgroup accumulates mass and momentum of its work item into an LDS
+//        tile (LDS float atomics), then flushes non-zero tile nodes to HBM with
+//        one global float atomic per channel, so global atomics fall from
+//        27 x 4 per particle to at most 4 per tile node.
+//   G2P: a workgroup stages the tile's updated nodal velocities in LDS, then each
+//        thread gathers its 3^d nodes, updates the particle and writes it to its
+//        sorted position (structure-of-arrays, coalesced).
+//
+// Weights: with s = x/dx - 1/2 in float64, b = floor(s), t = s - b and u = 1 - t
+// (both rounded once to float32, so small weights keep their relative accuracy)
+//   w = (u^2/2, 1/2 + t u, t^2/2),  dw/dxi = (-u, u - t, t).
+#include <stdlib.h>
+
+#include "internal.h"
+
+namespace mpmx {
+
+template <int DIM>
+struct Tile {
+    static constexpr int E = BLK + 2;                       // 6 nodes per axis
+    static constexpr int N = DIM == 3 ? E * E * E : E * E;  // 216 / 36
+    static constexpr int NB = 1 << DIM;                     // blocks touched
+    static constexpr int NPB = 1 << (2 * DIM);              // nodes per block
+};
+
+// Per-axis base offset within the owner block, t and u, for one particle.
+template <int DIM>
+__device__ __forceinline__ void particle_frame(const DevParams& P, const float* xp, const int* org, int* lb, float* t,
+                                               float* u) {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const double s = index_arg(xp[a], P.inv_dx);
+        double f = floor(s);
+        f = fmin(fmax(f, 0.0), (double)(P.cells[a] - 2));  // keeps indices in range for flagged particles
+        const double td = s - f;
+        t[a] = fminf(fmaxf((float)td, 0.f), 1.f);
+        u[a] = fminf(fmaxf((float)(1.0 - td), 0.f), 1.f);
+        lb[a] = min(max((int)f - org[a], 0), BLK - 1);
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ void bspline(const float* t, const float* u, float inv_dx, float (*w)[3], float (*dw)[3]) {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        w[a][0] = 0.5f * u[a] * u[a];
+        w[a][1] = 0.5f + t[a] * u[a];
+        w[a][2] = 0.5f * t[a] * t[a];
+        dw[a][0] = -u[a] * inv_dx;
+        dw[a][1] = (u[a] - t[a]) * inv_dx;
+        dw[a][2] = t[a] * inv_dx;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// P2G
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_p2g(DevParams P, const float* __restrict__ x, const float* __restrict__ v,
+                                            const float* __restrict__ C, const float* __restrict__ tau, int n,
+                                            const uint32_t* __restrict__ order) {
+    using T = Tile<DIM>;
+    constexpr int NS = DIM == 3 ? 6 : 3;
+    __shared__ float tile[4][T::N];
+    __shared__ int nbr[T::NB];
+    __shared__ int org[3];
+    const int n_work = min(P.ctr->n_work, P.work_cap);
+    const float mp = P.p_mass;
+    const float dtv = P.dt * P.p_vol0;
+    const float dx = P.dxf, inv_dx = P.inv_dxf;
+    for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
+        const int blk = P.w_block[w], s = P.w_start[w], e = P.w_end[w];
+        for (int t = threadIdx.x; t < 4 * T::N; t += WG) (&tile[0][0])[t] = 0.f;
+        if (threadIdx.x < T::NB) nbr[threadIdx.x] = P.b_nbr[blk * T::NB + threadIdx.x];
+        if (threadIdx.x == 0) {
+            int bc[3];
+            block_coords<DIM>(P, blk, bc);
+            org[0] = bc[0] * BLK;
+            org[1] = bc[1] * BLK;
+            org[2] = bc[2] * BLK;
+        }
+        __syncthreads();
+        // Lane-to-particle map: the run [s, e) is sorted by cell, about ppc
+        // particles per cell, so contiguous lanes would hit the same tile nodes
+        // and serialise their LDS atomics.  Thread r takes run position
+        // (r K) mod L with K coprime to L (a bijection), which puts neighbouring
+        // lanes roughly K/ppc cells apart.
+        const int L = e - s;
+        int K = 9;
+        if (L % 3 == 0) {
+            const int cand[7] = {11, 13, 17, 19, 23, 29, 31};
+            for (int c = 0; c < 7; ++c)
+                if (L % cand[c] != 0) {
+                    K = cand[c];
+                    break;
+                }
+        }
+        int pos = (int)(((long long)threadIdx.x * K) % L);
+        const int step = (int)(((long long)WG * K) % L);
+        for (int r = threadIdx.x; r < L; r += WG) {
+            const size_t q = order[s + pos];
+            pos += step;
+            if (pos >= L) pos -= L;
+            float xp[3], vp[3], Cp[9], tp[6];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                xp[a] = x[(size_t)a * n + q];
+                vp[a] = v[(size_t)a * n + q];
+            }
+#pragma unroll
+            for (int k = 0; k < DIM * DIM; ++k) Cp[k] = C[(size_t)k * n + q];
+#pragma unroll
+            for (int k = 0; k < NS; ++k) tp[k] = tau[(size_t)k * n + q];
+            int lb[3] = {0, 0, 0};
+            float t[3] = {0, 0, 0}, u[3] = {1, 1, 1};
+            particle_frame<DIM>(P, xp, org, lb, t, u);
+            float wt[3][3], dw[3][3];
+            bspline<DIM>(t, u, inv_dx, wt, dw);
+            // momentum pieces: m_p v_p, m_p C_p, dt V0 tau_p (symmetric)
+            float mv[3], A[3][3], G[3][3];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                mv[a] = mp * vp[a];
+#pragma unroll
+                for (int b = 0; b < DIM; ++b) A[a][b] = mp * Cp[a * DIM + b];
+            }
+            if (DIM == 3) {
+                G[0][0] = dtv * tp[0];
+                G[1][1] = dtv * tp[1];
+                G[2][2] = dtv * tp[2];
+                G[0][1] = G[1][0] = dtv * tp[3];
+                G[1][2] = G[2][1] = dtv * tp[4];
+                G[0][2] = G[2][0] = dtv * tp[5];
+            } else {
+                G[0][0] = dtv * tp[0];
+                G[1][1] = dtv * tp[1];
+                G[0][1] = G[1][0] = dtv * tp[2];
+            }
+            // x_n - x_p = (k - 1/2 - t) dx per axis
+            float dxn[3][3];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) dxn[a][k] = ((float)k - 0.5f - t[a]) * dx;
+            if (DIM == 3) {
+#pragma unroll
+                for (int kz = 0; kz < 3; ++kz)
+#pragma unroll
+                    for (int ky = 0; ky < 3; ++ky) {
+                        const float wyz = wt[1][ky] * wt[2][kz];
+                        const float dyz = dw[1][ky] * wt[2][kz];
+                        const float ydz = wt[1][ky] * dw[2][kz];
+#pragma unroll
+                        for (int kx = 0; kx < 3; ++kx) {
+                            const float N = wt[0][kx] * wyz;
+                            const float g0 = dw[0][kx] * wyz, g1 = wt[0][kx] * dyz, g2 = wt[0][kx] * ydz;
+                            const float d0 = dxn[0][kx], d1 = dxn[1][ky], d2 = dxn[2][kz];
+                            float pm[3];
+#pragma unroll
+                            for (int a = 0; a < 3; ++a)
+                                pm[a] = N * (mv[a] + A[a][0] * d0 + A[a][1] * d1 + A[a][2] * d2) -
+                                        (G[a][0] * g0 + G[a][1] * g1 + G[a][2] * g2);
+                            const int idx = (lb[0] + kx) + Tile<3>::E * ((lb[1] + ky) + Tile<3>::E * (lb[2] + kz));
+                            atomicAdd(&tile[0][idx], pm[0]);
+                            atomicAdd(&tile[1][idx], pm[1]);
+                            atomicAdd(&tile[2][idx], pm[2]);
+                            atomicAdd(&tile[3][idx], N * mp);
+                        }
+                    }
+            } else {
+#pragma unroll
+                for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+                    for (int kx = 0; kx < 3; ++kx) {
+                        const float N = wt[0][kx] * wt[1][ky];
+                        const float g0 = dw[0][kx] * wt[1][ky], g1 = wt[0][kx] * dw[1][ky];
+                        const float d0 = dxn[0][kx], d1 = dxn[1][ky];
+                        float pm[2];
+#pragma unroll
+                        for (int a = 0; a < 2; ++a)
+                            pm[a] = N * (mv[a] + A[a][0] * d0 + A[a][1] * d1) - (G[a][0] * g0 + G[a][1] * g1);
+                        const int idx = (lb[0] + kx) + Tile<2>::E * (lb[1] + ky);
+                        atomicAdd(&tile[0][idx], pm[0]);
+                        atomicAdd(&tile[1][idx], pm[1]);
+                        atomicAdd(&tile[3][idx], N * mp);
+                    }
+            }
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < T::N; t += WG) {
+            const float m = tile[3][t], p0 = tile[0][t], p1 = tile[1][t], p2 = DIM == 3 ? tile[2][t] : 0.f;
+            if (m != 0.f || p0 != 0.f || p1 != 0.f || p2 != 0.f) {
+                const int I = t % T::E;
+                const int J = (t / T::E) % T::E;
+                const int K = DIM == 3 ? t / (T::E * T::E) : 0;
+                const int d = (I >> 2) | ((J >> 2) << 1) | ((K >> 2) << 2);
+                const int phi = nbr[d];
+                if (phi >= 0) {
+                    const int l = (I & 3) + BLK * ((J & 3) + BLK * (K & 3));
+                    float* g = reinterpret_cast<float*>(&P.grid[(size_t)phi * T::NPB + l]);
+                    atomicAdd(g + 0, p0);
+                    atomicAdd(g + 1, p1);
+                    if (DIM == 3) atomicAdd(g + 2, p2);
+                    atomicAdd(g + 3, m);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// grid update with boundary conditions
+template <int DIM>
+__device__ __forceinline__ void terrain_bc(const DevParams& P, int i, int j, int k, float* vel) {
+    const int nx = P.cells[0] + 1, ny = P.cells[1] + 1;
+    const float* H = P.heightmap;
+    if (!((double)k * P.dx <= (double)H[(size_t)i * ny + j])) return;
+    const int il = max(i - 1, 0), ih = min(i + 1, nx - 1);
+    const int jl = max(j - 1, 0), jh = min(j + 1, ny - 1);
+    const float hx = (H[(size_t)ih * ny + j] - H[(size_t)il * ny + j]) / ((float)(ih - il) * P.dxf);
+    const float hy = (H[(size_t)i * ny + jh] - H[(size_t)i * ny + jl]) / ((float)(jh - jl) * P.dxf);
+    const float inv = 1.f / sqrtf(hx * hx + hy * hy + 1.f);
+    const float n0 = -hx * inv, n1 = -hy * inv, n2 = inv;
+    const float vn = vel[0] * n0 + vel[1] * n1 + vel[2] * n2;
+    if (vn >= 0.f) return;
+    const float t0 = vel[0] - vn * n0, t1 = vel[1] - vn * n1, t2 = vel[2] - vn * n2;
+    const float tn = sqrtf(t0 * t0 + t1 * t1 + t2 * t2);
+    if (tn <= -P.mu_terrain * vn) {
+        vel[0] = vel[1] = vel[2] = 0.f;
+    } else {
+        const float sc = 1.f + P.mu_terrain * vn / tn;
+        vel[0] = t0 * sc;
+        vel[1] = t1 * sc;
+        vel[2] = t2 * sc;
+    }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_grid_update(DevParams P, long long n_nodes_host) {
+    constexpr int NPB = Tile<DIM>::NPB;
+    const long long n_nodes = n_nodes_host >= 0 ? n_nodes_host : (long long)P.ctr->nb * NPB;
+    for (long long s = (long long)blockIdx.x * WG + threadIdx.x; s < n_nodes; s += (long long)gridDim.x * WG) {
+        const float4 gv = P.grid[s];
+        const float m = gv.w;
+        float vel[3] = {0.f, 0.f, 0.f};
+        if (m > 0.f) {
+            vel[0] = gv.x / m + P.dt * P.g[0];
+            vel[1] = gv.y / m + P.dt * P.g[1];
+            if (DIM == 3) vel[2] = gv.z / m + P.dt * P.g[2];
+            const int b = (int)(s / NPB), l = (int)(s % NPB);
+            int bc[3];
+            block_coords<DIM>(P, b, bc);
+            int node[3] = {bc[0] * BLK + (l & 3), bc[1] * BLK + ((l >> 2) & 3), DIM == 3 ? bc[2] * BLK + (l >> 4) : 0};
+            if (DIM == 3 && P.has_terrain && node[0] <= P.cells[0] && node[1] <= P.cells[1])
+                terrain_bc<DIM>(P, node[0], node[1], node[2], vel);
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    const bool on = side == 0 ? node[a] < P.bound : node[a] > P.cells[a] - P.bound;
+                    if (!on) continue;
+                    const int kind = P.bc[a][side];
+                    if (kind == MPM_BC_STICKY) {
+                        vel[0] = vel[1] = vel[2] = 0.f;
+                    } else if (kind == MPM_BC_SLIP) {
+                        vel[a] = 0.f;
+                    } else if (kind == MPM_BC_SEPARATE) {
+                        vel[a] = side == 0 ? fmaxf(vel[a], 0.f) : fminf(vel[a], 0.f);
+                    }
+                }
+            }
+        }
+        P.grid[s] = make_float4(vel[0], vel[1], vel[2], m);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// constitutive update: Hencky strain from the eigen-decomposition of
+// F F^T - I (cyclic Jacobi), Drucker-Prager return map, Kirchhoff stress.
+template <int DIM>
+__device__ __forceinline__ void jacobi_sym(float (*A)[3], float (*U)[3]) {
+    constexpr int SWEEPS = DIM == 3 ? 4 : 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) U[a][b] = a == b ? 1.f : 0.f;
+#pragma unroll
+    for (int sw = 0; sw < SWEEPS; ++sw) {
+#pragma unroll
+        for (int pr = 0; pr < (DIM == 3 ? 3 : 1); ++pr) {
+            const int p = pr == 2 ? 1 : 0;
+            const int q = pr == 0 ? 1 : 2;
+            const float apq = A[p][q];
+            if (apq != 0.f) {
+                const float th = (A[q][q] - A[p][p]) / (2.f * apq);
+                const float t = copysignf(1.f, th) / (fabsf(th) + sqrtf(th * th + 1.f));
+                const float c = 1.f / sqrtf(t * t + 1.f);
+                const float sn = t * c;
+                A[p][p] -= t * apq;
+                A[q][q] += t * apq;
+                A[p][q] = A[q][p] = 0.f;
+                if (DIM == 3) {
+                    const int r = 3 - p - q;
+                    const float arp = A[r][p], arq = A[r][q];
+                    A[r][p] = A[p][r] = c * arp - sn * arq;
+                    A[r][q] = A[q][r] = sn * arp + c * arq;
+                }
+#pragma unroll
+                for (int r = 0; r < DIM; ++r) {
+                    const float urp = U[r][p], urq = U[r][q];
+                    U[r][p] = c * urp - sn * urq;
+                    U[r][q] = sn * urp + c * urq;
+                }
+            }
+        }
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ unsigned constitutive(const DevParams& P, const float (*Ft)[3], float (*Fn)[3],
+                                                 float* tau6) {
+    unsigned flags = 0;
+    float det;
+    if (DIM == 3)
+        det = Ft[0][0] * (Ft[1][1] * Ft[2][2] - Ft[1][2] * Ft[2][1]) -
+              Ft[0][1] * (Ft[1][0] * Ft[2][2] - Ft[1][2] * Ft[2][0]) +
+              Ft[0][2] * (Ft[1][0] * Ft[2][1] - Ft[1][1] * Ft[2][0]);
+    else
+        det = Ft[0][0] * Ft[1][1] - Ft[0][1] * Ft[1][0];
+    if (!(det > 0.f)) flags |= MPM_FLAG_INVERTED;
+    // M = F F^T - I = H + H^T + H H^T with H = F - I
+    float Hm[3][3], M[3][3], U[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Hm[a][b] = (a < DIM && b < DIM) ? Ft[a][b] - (a == b ? 1.f : 0.f) : 0.f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            float s = Hm[a][b] + Hm[b][a];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) s += Hm[a][c] * Hm[b][c];
+            M[a][b] = s;
+        }
+    jacobi_sym<DIM>(M, U);
+    float eps[3], e2[3];
+    float tr = 0.f;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        eps[a] = 0.5f * log1pf(fmaxf(M[a][a], -0.999999f));
+        tr += eps[a];
+    }
+    bool plastic = false;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) e2[a] = eps[a];
+    if (P.model == MPM_MODEL_DP) {
+        if (tr > 0.f) {
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) e2[a] = 0.f;
+            plastic = true;
+        } else {
+            float dev[3], nd2 = 0.f;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                dev[a] = eps[a] - tr / (float)DIM;
+                nd2 += dev[a] * dev[a];
+            }
+            const float nd = sqrtf(nd2);
+            const float dg = nd + P.dp_coef * tr * P.alpha;
+            if (dg > 0.f) {
+                const float sc = dg / nd;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) e2[a] = eps[a] - sc * dev[a];
+                plastic = true;
+            }
+        }
+    }
+    float tr2 = 0.f;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) tr2 += e2[a];
+    float sig[3], gam[3];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        sig[a] = 2.f * P.mu * e2[a] + P.lam * tr2;
+        gam[a] = expm1f(e2[a] - eps[a]);
+    }
+    float T[3][3], W[3][3];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            float st = 0.f, sw = 0.f;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                st += U[a][c] * sig[c] * U[b][c];
+                sw += U[a][c] * gam[c] * U[b][c];
+            }
+            T[a][b] = st;
+            W[a][b] = sw;
+        }
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            float s = Ft[a][b];
+            if (plastic) {
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) s += W[a][c] * Ft[c][b];
+            }
+            Fn[a][b] = s;
+        }
+    if (DIM == 3) {
+        tau6[0] = T[0][0];
+        tau6[1] = T[1][1];
+        tau6[2] = T[2][2];
+        tau6[3] = T[0][1];
+        tau6[4] = T[1][2];
+        tau6[5] = T[0][2];
+    } else {
+        tau6[0] = T[0][0];
+        tau6[1] = T[1][1];
+        tau6[2] = T[0][1];
+    }
+    return flags;
+}
+
+struct G2PIn {
+    const float* x;
+    const float* F;
+    const uint32_t* id;
+};
+struct G2POut {
+    float* x;
+    float* v;
+    float* C;
+    float* F;
+    float* tau;
+    uint32_t* id;
+};
+
+template <int DIM, int WAVES>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_g2p(
+    DevParams P, G2PIn in, G2POut out, int n, const uint32_t* __restrict__ order) {
+    using T = Tile<DIM>;
+    constexpr int NS = DIM == 3 ? 6 : 3;
+    __shared__ float4 vt[T::N];
+    __shared__ int nbr[T::NB];
+    __shared__ int org[3];
+    const int n_work = min(P.ctr->n_work, P.work_cap);
+    const float dt = P.dt, dx = P.dxf, inv_dx = P.inv_dxf;
+    const float cscale = 4.f * inv_dx * inv_dx;  // D_p^{-1} = (4/dx^2) I for quadratic B-splines
+    for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
+        const int blk = P.w_block[w], s = P.w_start[w], e = P.w_end[w];
+        if (threadIdx.x < T::NB) nbr[threadIdx.x] = P.b_nbr[blk * T::NB + threadIdx.x];
+        if (threadIdx.x == 0) {
+            int bc[3];
+            block_coords<DIM>(P, blk, bc);
+            org[0] = bc[0] * BLK;
+            org[1] = bc[1] * BLK;
+            org[2] = bc[2] * BLK;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < T::N; t += WG) {
+            const int I = t % T::E, J = (t / T::E) % T::E, K = DIM == 3 ? t / (T::E * T::E) : 0;
+            const int d = (I >> 2) | ((J >> 2) << 1) | ((K >> 2) << 2);
+            const int phi = nbr[d];
+            const int l = (I & 3) + BLK * ((J & 3) + BLK * (K & 3));
+            vt[t] = phi >= 0 ? P.grid[(size_t)phi * T::NPB + l] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        __syncthreads();
+        for (int i = s + (int)threadIdx.x; i < e; i += WG) {
+            const size_t q = order[i];
+            float xp[3] = {0, 0, 0}, Fp[3][3];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) xp[a] = in.x[(size_t)a * n + q];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                for (int b = 0; b < DIM; ++b) Fp[a][b] = in.F[(size_t)(a * DIM + b) * n + q];
+            int lb[3] = {0, 0, 0};
+            float t[3] = {0, 0, 0}, u[3] = {1, 1, 1};
+            particle_frame<DIM>(P, xp, org, lb, t, u);
+            float wt[3][3], dw[3][3];
+            bspline<DIM>(t, u, inv_dx, wt, dw);
+            float dxn[3][3];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) dxn[a][k] = ((float)k - 0.5f - t[a]) * dx;
+            float vp[3] = {0, 0, 0}, B[3][3] = {{0}}, gv[3][3] = {{0}};
+            if (DIM == 3) {
+#pragma unroll
+                for (int kz = 0; kz < 3; ++kz)
+#pragma unroll
+                    for (int ky = 0; ky < 3; ++ky) {
+                        const float wyz = wt[1][ky] * wt[2][kz];
+                        const float dyz = dw[1][ky] * wt[2][kz];
+                        const float ydz = wt[1][ky] * dw[2][kz];
+#pragma unroll
+                        for (int kx = 0; kx < 3; ++kx) {
+                            const int idx = (lb[0] + kx) + T::E * ((lb[1] + ky) + T::E * (lb[2] + kz));
+                            const float4 g = vt[idx];
+                            const float vn[3] = {g.x, g.y, g.z};
+                            const float N = wt[0][kx] * wyz;
+                            const float gr[3] = {dw[0][kx] * wyz, wt[0][kx] * dyz, wt[0][kx] * ydz};
+                            const float dd[3] = {dxn[0][kx], dxn[1][ky], dxn[2][kz]};
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                const float nv = N * vn[a];
+                                vp[a] += nv;
+#pragma unroll
+                                for (int b = 0; b < 3; ++b) {
+                                    B[a][b] += nv * dd[b];
+                                    gv[a][b] += vn[a] * gr[b];
+                                }
+                            }
+                        }
+                    }
+            } else {
+#pragma unroll
+                for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+                    for (int kx = 0; kx < 3; ++kx) {
+                        const int idx = (lb[0] + kx) + T::E * (lb[1] + ky);
+                        const float4 g = vt[idx];
+                        const float vn[2] = {g.x, g.y};
+                        const float N = wt[0][kx] * wt[1][ky];
+                        const float gr[2] = {dw[0][kx] * wt[1][ky], wt[0][kx] * dw[1][ky]};
+                        const float dd[2] = {dxn[0][kx], dxn[1][ky]};
+#pragma unroll
+                        for (int a = 0; a < 2; ++a) {
+                            const float nv = N * vn[a];
+                            vp[a] += nv;
+#pragma unroll
+                            for (int b = 0; b < 2; ++b) {
+                                B[a][b] += nv * dd[b];
+                                gv[a][b] += vn[a] * gr[b];
+                            }
+                        }
+                    }
+            }
+            // F_trial = (I + dt grad v) F  (Eq. 17)
+            float Ft[3][3], Fn[3][3], tau6[6];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                for (int b = 0; b < DIM; ++b) {
+                    float s2 = 0.f;
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) s2 += gv[a][c] * Fp[c][b];
+                    Ft[a][b] = Fp[a][b] + dt * s2;
+                }
+            unsigned flags = constitutive<DIM>(P, Ft, Fn, tau6);
+            const size_t o = (size_t)i;
+            bool finite = true;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                const float xn = xp[a] + dt * vp[a];
+                finite = finite && isfinite(xn) && isfinite(vp[a]);
+                out.x[(size_t)a * n + o] = xn;
+                out.v[(size_t)a * n + o] = vp[a];
+            }
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                for (int b = 0; b < DIM; ++b) {
+                    out.C[(size_t)(a * DIM + b) * n + o] = cscale * B[a][b];
+                    out.F[(size_t)(a * DIM + b) * n + o] = Fn[a][b];
+                }
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                finite = finite && isfinite(tau6[k]);
+                out.tau[(size_t)k * n + o] = tau6[k];
+            }
+            if (out.id) out.id[o] = in.id ? in.id[q] : (uint32_t)q;
+            if (!finite) flags |= MPM_FLAG_NAN;
+            if (flags) raise_flag(P.ctr, flags);
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_p2g(const DevParams& P, const float* x, const float* v, const float* C, const float* tau, int n,
+                      const uint32_t* order, int grid_blocks, hipStream_t s) {
+    if (P.dim == 3)
+        k_p2g<3><<<grid_blocks, WG, 0, s>>>(P, x, v, C, tau, n, order);
+    else
+        k_p2g<2><<<grid_blocks, WG, 0, s>>>(P, x, v, C, tau, n, order);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid_update(const DevParams& P, long long n_nodes_host, int grid_blocks, hipStream_t s) {
+    if (P.dim == 3)
+        k_grid_update<3><<<grid_blocks, WG, 0, s>>>(P, n_nodes_host);
+    else
+        k_grid_update<2><<<grid_blocks, WG, 0, s>>>(P, n_nodes_host);
+    return hipGetLastError();
+}
+
+hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, const uint32_t* id_in, float* x_out,
+                      float* v_out, float* C_out, float* F_out, float* tau_out, uint32_t* id_out, int n,
+                      const uint32_t* order, int grid_blocks, hipStream_t s) {
+    G2PIn in{x_in, F_in, id_in};
+    G2POut out{x_out, v_out, C_out, F_out, tau_out, id_out};
+    static int variant = [] {
+        const char* v = getenv("MPMX_G2P_WAVES");
+        return v ? atoi(v) : 0;
+    }();
+    if (P.dim == 3) {
+        if (variant == 3)
+            k_g2p<3, 3><<<grid_blocks, WG, 0, s>>>(P, in, out, n, order);
+        else if (variant == 4)
+            k_g2p<3, 4><<<grid_blocks, WG, 0, s>>>(P, in, out, n, order);
+        else
+            k_g2p<3, 1><<<grid_blocks, WG, 0, s>>>(P, in, out, n, order);
+    } else {
+        k_g2p<2, 1><<<grid_blocks, WG, 0, s>>>(P, in, out, n, order);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mpmx

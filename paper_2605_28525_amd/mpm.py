@@ -1,0 +1,293 @@
+"""ctypes binding of ``libmpm.so`` (the C ABI declared in include/mpm.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Particle arrays are torch CUDA tensors (device memory); their ``data_ptr()``
+and the raw HIP stream handle are passed straight through.  If the library is
+not built, importing this module raises ImportError -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_float, c_int, c_uint32, c_uint64, c_void_p
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmpm.so")
+
+MPM_OK, MPM_ERR_ARG, MPM_ERR_HIP, MPM_ERR_NOMEM = 0, 1, 2, 3
+MPM_ERR_OVERFLOW, MPM_ERR_DOMAIN, MPM_ERR_INVERTED, MPM_ERR_NAN, MPM_ERR_STATE = 4, 5, 6, 7, 8
+MPM_FLAG_OVERFLOW, MPM_FLAG_DOMAIN, MPM_FLAG_INVERTED, MPM_FLAG_NAN = 1, 2, 4, 8
+MPM_BC = {"none": 0, "sticky": 1, "slip": 2, "separate": 3}
+MPM_MODEL = {"elastic": 0, "dp": 1}
+MPM_GRID_SPARSE, MPM_GRID_DENSE = 0, 1
+MPM_FLAG_SYNC_REBUILD = 1
+
+
+class mpm_params(ctypes.Structure):
+    _fields_ = [
+        ("dim", c_int),
+        ("dx", c_double),
+        ("cells", c_int * 3),
+        ("gravity", c_float * 3),
+        ("dt", c_float),
+        ("bound", c_int),
+        ("bc", (c_int * 2) * 3),
+        ("heightmap", POINTER(c_float)),
+        ("mu_terrain", c_float),
+        ("model", c_int),
+        ("E", c_float),
+        ("nu", c_float),
+        ("friction_deg", c_float),
+        ("p_mass", c_float),
+        ("p_vol0", c_float),
+        ("max_particles", c_int),
+        ("block_capacity", c_int),
+        ("hash_capacity_log2", c_int),
+        ("grid_mode", c_int),
+        ("flags", c_int),
+    ]
+
+
+class mpm_particles(ctypes.Structure):
+    _fields_ = [
+        ("n", c_int),
+        ("x", c_void_p),
+        ("v", c_void_p),
+        ("C", c_void_p),
+        ("F", c_void_p),
+        ("tau", c_void_p),
+        ("id", c_void_p),
+    ]
+
+
+_PCTX = c_void_p
+_SIGS = {
+    "mpm_create": (c_int, [POINTER(mpm_params), POINTER(_PCTX)]),
+    "mpm_destroy": (c_int, [_PCTX]),
+    "mpm_status_string": (ctypes.c_char_p, [c_int]),
+    "mpm_sparse_build": (c_int, [_PCTX, POINTER(mpm_particles), c_void_p]),
+    "mpm_p2g": (c_int, [_PCTX, POINTER(mpm_particles), c_void_p]),
+    "mpm_grid_update": (c_int, [_PCTX, c_void_p]),
+    "mpm_g2p": (c_int, [_PCTX, POINTER(mpm_particles), POINTER(mpm_particles), c_void_p]),
+    "mpm_step": (c_int, [_PCTX, POINTER(mpm_particles), POINTER(mpm_particles), c_int, c_void_p]),
+    "mpm_get_status": (c_int, [_PCTX, c_void_p, POINTER(c_uint32)]),
+    "mpm_clear_status": (c_int, [_PCTX, c_void_p]),
+    "mpm_active_count": (c_int, [_PCTX, c_void_p, POINTER(c_int), POINTER(c_int)]),
+    "mpm_get_active": (c_int, [_PCTX, c_void_p, c_void_p, c_int, c_void_p]),
+    "mpm_get_grid": (c_int, [_PCTX, c_void_p, c_int, c_void_p]),
+    "mpm_get_order": (c_int, [_PCTX, c_void_p, c_int, c_void_p]),
+    "mpm_set_material": (c_int, [_PCTX, c_float, c_float, c_float, c_float]),
+}
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is not built; run `python -m paper_2605_28525_amd.build`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+class MPMError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {lib.mpm_status_string(code).decode()}")
+
+
+def _check(rc: int, where: str):
+    if rc != MPM_OK:
+        raise MPMError(rc, where)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return c_void_p(stream)
+    return c_void_p(stream.cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# same names as the C ABI
+def mpm_create(params: mpm_params) -> c_void_p:
+    ctx = _PCTX()
+    _check(lib.mpm_create(ctypes.byref(params), ctypes.byref(ctx)), "mpm_create")
+    return ctx
+
+
+def mpm_destroy(ctx):
+    _check(lib.mpm_destroy(ctx), "mpm_destroy")
+
+
+def mpm_sparse_build(ctx, p: mpm_particles, stream=None):
+    _check(lib.mpm_sparse_build(ctx, ctypes.byref(p), _stream(stream)), "mpm_sparse_build")
+
+
+def mpm_p2g(ctx, p: mpm_particles, stream=None):
+    _check(lib.mpm_p2g(ctx, ctypes.byref(p), _stream(stream)), "mpm_p2g")
+
+
+def mpm_grid_update(ctx, stream=None):
+    _check(lib.mpm_grid_update(ctx, _stream(stream)), "mpm_grid_update")
+
+
+def mpm_g2p(ctx, pin: mpm_particles, pout: mpm_particles, stream=None):
+    _check(lib.mpm_g2p(ctx, ctypes.byref(pin), ctypes.byref(pout), _stream(stream)), "mpm_g2p")
+
+
+def mpm_step(ctx, a: mpm_particles, b: mpm_particles, n_steps: int, stream=None):
+    _check(lib.mpm_step(ctx, ctypes.byref(a), ctypes.byref(b), int(n_steps), _stream(stream)), "mpm_step")
+
+
+def mpm_get_status(ctx, stream=None):
+    """Returns (return code, flags); synchronises the stream."""
+    f = c_uint32(0)
+    rc = lib.mpm_get_status(ctx, _stream(stream), ctypes.byref(f))
+    if rc in (MPM_ERR_ARG, MPM_ERR_HIP):
+        raise MPMError(rc, "mpm_get_status")
+    return rc, int(f.value)
+
+
+def mpm_clear_status(ctx, stream=None):
+    _check(lib.mpm_clear_status(ctx, _stream(stream)), "mpm_clear_status")
+
+
+def mpm_active_count(ctx, stream=None):
+    nb, nt = c_int(0), c_int(0)
+    _check(lib.mpm_active_count(ctx, _stream(stream), ctypes.byref(nb), ctypes.byref(nt)), "mpm_active_count")
+    return int(nb.value), int(nt.value)
+
+
+def mpm_get_active(ctx, keys, masks, capacity: int, stream=None):
+    _check(lib.mpm_get_active(ctx, c_void_p(keys.data_ptr()), c_void_p(masks.data_ptr()), int(capacity),
+                              _stream(stream)), "mpm_get_active")
+
+
+def mpm_get_grid(ctx, out, capacity_blocks: int, stream=None):
+    _check(lib.mpm_get_grid(ctx, c_void_p(out.data_ptr()), int(capacity_blocks), _stream(stream)), "mpm_get_grid")
+
+
+def mpm_get_order(ctx, order, n: int, stream=None):
+    _check(lib.mpm_get_order(ctx, c_void_p(order.data_ptr()), int(n), _stream(stream)), "mpm_get_order")
+
+
+def mpm_set_material(ctx, E: float, nu: float, friction_deg: float, dt: float):
+    _check(lib.mpm_set_material(ctx, E, nu, friction_deg, dt), "mpm_set_material")
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+def params_from_workload(w, *, max_particles=None, grid_mode=MPM_GRID_SPARSE, block_capacity=0,
+                         hash_capacity_log2=0, flags=0):
+    """Build an ``mpm_params`` from a workload description.  The returned object
+    keeps the heightmap array alive until mpm_create has copied it."""
+    p = mpm_params()
+    p.dim = w.dim
+    p.dx = float(w.dx)
+    for a in range(3):
+        p.cells[a] = int(w.cells[a]) if a < w.dim else 0
+        p.gravity[a] = float(w.gravity[a])
+        for s in range(2):
+            p.bc[a][s] = MPM_BC[w.bc[a][s]] if a < w.dim else 0
+    p.dt = float(w.dt)
+    p.bound = int(w.bound)
+    if w.heightmap is not None:
+        hm = np.ascontiguousarray(w.heightmap, dtype=np.float32)
+        p._hm_keepalive = hm
+        p.heightmap = hm.ctypes.data_as(POINTER(c_float))
+    p.mu_terrain = float(w.mu_terrain)
+    p.model = MPM_MODEL[w.model]
+    p.E, p.nu, p.friction_deg = float(w.E), float(w.nu), float(w.friction_deg)
+    p.p_mass, p.p_vol0 = float(w.p_mass), float(w.p_vol0)
+    p.max_particles = int(max_particles or w.n)
+    p.block_capacity = int(block_capacity)
+    p.hash_capacity_log2 = int(hash_capacity_log2)
+    p.grid_mode = int(grid_mode)
+    p.flags = int(flags)
+    return p
+
+
+class ParticleSet:
+    """Device SoA particle state as torch tensors plus its ``mpm_particles`` view."""
+
+    def __init__(self, dim: int, n: int, device="cuda"):
+        import torch
+        d = dim
+        self.dim, self.n = dim, n
+        self.x = torch.zeros((d, n), dtype=torch.float32, device=device)
+        self.v = torch.zeros((d, n), dtype=torch.float32, device=device)
+        self.C = torch.zeros((d * d, n), dtype=torch.float32, device=device)
+        self.F = torch.zeros((d * d, n), dtype=torch.float32, device=device)
+        self.tau = torch.zeros((3 if d == 2 else 6, n), dtype=torch.float32, device=device)
+        self.id = torch.zeros((n,), dtype=torch.int32, device=device)
+
+    @classmethod
+    def from_arrays(cls, st: dict, ids=None, device="cuda"):
+        import torch
+        d, n = st["x"].shape
+        ps = cls(d, n, device)
+        for k in ("x", "v", "C", "F", "tau"):
+            getattr(ps, k).copy_(torch.from_numpy(np.ascontiguousarray(st[k], dtype=np.float32)))
+        ids = np.arange(n, dtype=np.int32) if ids is None else np.asarray(ids, dtype=np.int32)
+        ps.id.copy_(torch.from_numpy(ids))
+        return ps
+
+    def to_arrays(self) -> dict:
+        return {k: getattr(self, k).detach().cpu().numpy() for k in ("x", "v", "C", "F", "tau")}
+
+    def ids(self) -> np.ndarray:
+        return self.id.detach().cpu().numpy().view(np.uint32)
+
+    def view(self) -> mpm_particles:
+        p = mpm_particles()
+        p.n = self.n
+        p.x, p.v, p.C = self.x.data_ptr(), self.v.data_ptr(), self.C.data_ptr()
+        p.F, p.tau, p.id = self.F.data_ptr(), self.tau.data_ptr(), self.id.data_ptr()
+        return p
+
+
+class Simulation:
+    """A context plus two particle buffers it ping-pongs between."""
+
+    def __init__(self, w, *, grid_mode=MPM_GRID_SPARSE, block_capacity=0, hash_capacity_log2=0, flags=0,
+                 device="cuda"):
+        self.w = w
+        self.params = params_from_workload(w, grid_mode=grid_mode, block_capacity=block_capacity,
+                                           hash_capacity_log2=hash_capacity_log2, flags=flags)
+        self.ctx = mpm_create(self.params)
+        self.a = ParticleSet.from_arrays(w.state(), device=device)
+        self.b = ParticleSet(w.dim, w.n, device)
+
+    def set_state(self, st: dict, ids=None):
+        import torch
+        for k in ("x", "v", "C", "F", "tau"):
+            getattr(self.a, k).copy_(torch.from_numpy(np.ascontiguousarray(st[k], dtype=np.float32)))
+        ids = np.arange(self.a.n, dtype=np.int32) if ids is None else np.asarray(ids, dtype=np.int32)
+        self.a.id.copy_(torch.from_numpy(ids))
+
+    def step(self, n_steps: int = 1, stream=None):
+        mpm_step(self.ctx, self.a.view(), self.b.view(), n_steps, stream)
+        if n_steps % 2 == 1:
+            self.a, self.b = self.b, self.a
+
+    def status(self):
+        return mpm_get_status(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            mpm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,95 @@
+"""The C-ABI library loads and exports every entry point include/mpm.h
+declares, and the ctypes structures match the C layout (no GPU needed)."""
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(mpm_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary_calls():
+    names = declared_functions()
+    for required in ("mpm_sparse_build", "mpm_p2g", "mpm_grid_update", "mpm_g2p", "mpm_step",
+                     "mpm_create", "mpm_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2605_28525_amd import mpm as M
+    lib = ctypes.CDLL(M._LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert M.lib.mpm_status_string(4).startswith(b"MPM_ERR_OVERFLOW")
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
+def test_struct_layout_matches_c():
+    from paper_2605_28525_amd import mpm as M
+    src = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "mpm.h"
+#define O(s, f) printf("%s.%s %zu\n", #s, #f, offsetof(s, f))
+int main(void) {
+  printf("sizeof.mpm_params %zu\nsizeof.mpm_particles %zu\n", sizeof(mpm_params), sizeof(mpm_particles));
+  O(mpm_params, dim); O(mpm_params, dx); O(mpm_params, cells); O(mpm_params, gravity); O(mpm_params, dt);
+  O(mpm_params, bound); O(mpm_params, bc); O(mpm_params, heightmap); O(mpm_params, mu_terrain);
+  O(mpm_params, model); O(mpm_params, E); O(mpm_params, nu); O(mpm_params, friction_deg);
+  O(mpm_params, p_mass); O(mpm_params, p_vol0); O(mpm_params, max_particles); O(mpm_params, block_capacity);
+  O(mpm_params, hash_capacity_log2); O(mpm_params, grid_mode); O(mpm_params, flags);
+  O(mpm_particles, n); O(mpm_particles, x); O(mpm_particles, v); O(mpm_particles, C); O(mpm_particles, F);
+  O(mpm_particles, tau); O(mpm_particles, id);
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.strip().splitlines():
+        k, v = line.split()
+        got[k] = int(v)
+    assert got["sizeof.mpm_params"] == ctypes.sizeof(M.mpm_params)
+    assert got["sizeof.mpm_particles"] == ctypes.sizeof(M.mpm_particles)
+    for struct in (M.mpm_params, M.mpm_particles):
+        for name, _ in struct._fields_:
+            assert got[f"{struct.__name__}.{name}"] == getattr(struct, name).offset, name
+
+
+def test_constants_match_header():
+    from paper_2605_28525_amd import mpm as M
+    text = open(HEADER).read()
+    defs = dict(re.findall(r"#define\s+(MPM_\w+)\s+(\d+)u?", text))
+    assert int(defs["MPM_ERR_OVERFLOW"]) == M.MPM_ERR_OVERFLOW
+    assert int(defs["MPM_FLAG_NAN"]) == M.MPM_FLAG_NAN
+    assert int(defs["MPM_GRID_DENSE"]) == M.MPM_GRID_DENSE
+    for k, v in M.MPM_BC.items():
+        assert int(defs["MPM_BC_" + k.upper()]) == v
+    assert int(defs["MPM_MODEL_DP"]) == M.MPM_MODEL["dp"]
+    assert int(defs["MPM_MODEL_ELASTIC"]) == M.MPM_MODEL["elastic"]
+
+
+def test_create_rejects_bad_arguments_without_touching_the_device():
+    """Argument errors are reported before any device call."""
+    from paper_2605_28525_amd import mpm as M
+    p = M.mpm_params()
+    p.dim = 4
+    ctx = ctypes.c_void_p()
+    assert M.lib.mpm_create(ctypes.byref(p), ctypes.byref(ctx)) == M.MPM_ERR_ARG
+    assert not ctx.value
+    assert M.lib.mpm_create(None, ctypes.byref(ctx)) == M.MPM_ERR_ARG
