@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--block-capacity", type=int, default=0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="also run one device-to-device copy of this many MiB (a kernel of known traffic "
+                         "for scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -156,6 +159,13 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.copy_probe:
+        a = torch.ones(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"bench: copy probe of {args.copy_probe} MiB done")
+        del a, b
     log(f"bench: generating {args.workload}")
     w = make_workload(args.workload)
     n = w.n

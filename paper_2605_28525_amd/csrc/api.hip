@@ -318,7 +318,7 @@ int mpm_create(const mpm_params* q, mpm_ctx** out) {
     }
     if (const char* ch = getenv("MPMX_CHUNK")) {
         int v = atoi(ch);
-        if (v >= 32 && v <= 8192) c->chunk = v;
+        if (v >= 32 && v <= 512) c->chunk = v;
     }
     if (const char* pw = getenv("MPMX_WGS")) {
         int v = atoi(pw);
@@ -414,7 +414,7 @@ int mpm_p2g(mpm_ctx* c, const mpm_particles* p, void* stream) {
     if (!c->built || p->n != c->built_n) return MPM_ERR_STATE;
     if (p->n == 0) return MPM_OK;
     const int wgs = std::min(c->persistent_wgs, c->work_cap);
-    return hip_status(launch_p2g(c->P, p->x, p->v, p->C, p->tau, p->n, c->order, wgs, (hipStream_t)stream));
+    return hip_status(launch_p2g(c->P, p->x, p->v, p->C, p->tau, p->n, c->order, c->skeys, wgs, (hipStream_t)stream));
 }
 
 int mpm_grid_update(mpm_ctx* c, void* stream) {

@@ -23,6 +23,9 @@
 
 namespace mpmx {
 
+constexpr int G2P_MAX_ITEM = 512;     // particles per G2P work item (LDS staging)
+constexpr int P2G_ORDER_STAGE = 1024; // sort permutation entries staged per P2G block
+
 template <int DIM>
 struct Tile {
     static constexpr int E = BLK + 2;                       // 6 nodes per axis
@@ -61,147 +64,188 @@ __device__ __forceinline__ void bspline(const float* t, const float* u, float in
 }
 
 // ---------------------------------------------------------------------------
-// P2G
+// P2G, one wave64 per owner block and one lane per base cell.
+//
+// Inside a block the sorted order groups particles by the local index of their
+// base node (the low 2d bits of the sort key), and every particle with the same
+// base node scatters to the same 3^d nodes.  A lane therefore sums its cell's
+// particles into 27 x 4 registers and issues the LDS atomics once per cell, not
+// once per particle; the tile is then flushed to HBM as above.
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_p2g(DevParams P, const float* __restrict__ x, const float* __restrict__ v,
-                                            const float* __restrict__ C, const float* __restrict__ tau, int n,
-                                            const uint32_t* __restrict__ order) {
+__global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __restrict__ x,
+                                                 const float* __restrict__ v, const float* __restrict__ C,
+                                                 const float* __restrict__ tau, int n,
+                                                 const uint32_t* __restrict__ order,
+                                                 const uint32_t* __restrict__ skeys) {
     using T = Tile<DIM>;
     constexpr int NS = DIM == 3 ? 6 : 3;
+    constexpr int NC = T::NPB;  // base cells per block
+    constexpr int NK = DIM == 3 ? 27 : 9;
     __shared__ float tile[4][T::N];
-    __shared__ int nbr[T::NB];
-    __shared__ int org[3];
-    const int n_work = min(P.ctr->n_work, P.work_cap);
+    __shared__ int cs[NC], ce[NC];
+    __shared__ uint32_t ord[P2G_ORDER_STAGE];
+    const int lane = threadIdx.x;
+    const int nb = min(P.ctr->nb, P.block_cap);
     const float mp = P.p_mass;
     const float dtv = P.dt * P.p_vol0;
     const float dx = P.dxf, inv_dx = P.inv_dxf;
-    for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
-        const int blk = P.w_block[w], s = P.w_start[w], e = P.w_end[w];
-        for (int t = threadIdx.x; t < 4 * T::N; t += WG) (&tile[0][0])[t] = 0.f;
-        if (threadIdx.x < T::NB) nbr[threadIdx.x] = P.b_nbr[blk * T::NB + threadIdx.x];
-        if (threadIdx.x == 0) {
-            int bc[3];
-            block_coords<DIM>(P, blk, bc);
-            org[0] = bc[0] * BLK;
-            org[1] = bc[1] * BLK;
-            org[2] = bc[2] * BLK;
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        const int cnt = P.b_count[b];
+        if (cnt <= 0) continue;
+        const int st = P.b_start[b], en = st + cnt;
+        for (int t = lane; t < 4 * T::N; t += 64) (&tile[0][0])[t] = 0.f;
+        for (int c = lane; c < NC; c += 64) cs[c] = ce[c] = 0;
+        int bc[3];
+        block_coords<DIM>(P, b, bc);
+        const int org[3] = {bc[0] * BLK, bc[1] * BLK, bc[2] * BLK};
+        __syncthreads();
+        for (int i = st + lane; i < en; i += 64) {
+            if (i - st < P2G_ORDER_STAGE) ord[i - st] = order[i];
+            const uint32_t c = skeys[i] & (NC - 1);
+            if (i == st || (skeys[i - 1] & (NC - 1)) != c) cs[c] = i;
+            if (i == en - 1 || (skeys[i + 1] & (NC - 1)) != c) ce[c] = i + 1;
         }
         __syncthreads();
-        // Lane-to-particle map: the run [s, e) is sorted by cell, about ppc
-        // particles per cell, so contiguous lanes would hit the same tile nodes
-        // and serialise their LDS atomics.  Thread r takes run position
-        // (r K) mod L with K coprime to L (a bijection), which puts neighbouring
-        // lanes roughly K/ppc cells apart.
-        const int L = e - s;
-        int K = 9;
-        if (L % 3 == 0) {
-            const int cand[7] = {11, 13, 17, 19, 23, 29, 31};
-            for (int c = 0; c < 7; ++c)
-                if (L % cand[c] != 0) {
-                    K = cand[c];
-                    break;
-                }
-        }
-        int pos = (int)(((long long)threadIdx.x * K) % L);
-        const int step = (int)(((long long)WG * K) % L);
-        for (int r = threadIdx.x; r < L; r += WG) {
-            const size_t q = order[s + pos];
-            pos += step;
-            if (pos >= L) pos -= L;
+        float acc[NK][4];
+#pragma unroll
+        for (int k = 0; k < NK; ++k) acc[k][0] = acc[k][1] = acc[k][2] = acc[k][3] = 0.f;
+        int lb[3] = {lane & 3, (lane >> 2) & 3, DIM == 3 ? (lane >> 4) & 3 : 0};
+        bool has = false;
+        if (lane < NC) {
+            const int c0 = cs[lane], c1 = ce[lane];
+            has = c1 > c0;
+            // software pipeline: the loads of particle i+1 are issued before the
+            // 3^d-node accumulation of particle i
             float xp[3], vp[3], Cp[9], tp[6];
+            float xq[3], vq[3], Cq[9], tq[6];
+            auto load_particle = [&](int i, float* xo, float* vo, float* Co, float* to) {
+                const size_t q = i - st < P2G_ORDER_STAGE ? ord[i - st] : order[i];
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                xp[a] = x[(size_t)a * n + q];
-                vp[a] = v[(size_t)a * n + q];
-            }
+                for (int a = 0; a < DIM; ++a) {
+                    xo[a] = x[(size_t)a * n + q];
+                    vo[a] = v[(size_t)a * n + q];
+                }
 #pragma unroll
-            for (int k = 0; k < DIM * DIM; ++k) Cp[k] = C[(size_t)k * n + q];
+                for (int k = 0; k < DIM * DIM; ++k) Co[k] = C[(size_t)k * n + q];
 #pragma unroll
-            for (int k = 0; k < NS; ++k) tp[k] = tau[(size_t)k * n + q];
-            int lb[3] = {0, 0, 0};
-            float t[3] = {0, 0, 0}, u[3] = {1, 1, 1};
-            particle_frame<DIM>(P, xp, org, lb, t, u);
-            float wt[3][3], dw[3][3];
-            bspline<DIM>(t, u, inv_dx, wt, dw);
-            // momentum pieces: m_p v_p, m_p C_p, dt V0 tau_p (symmetric)
-            float mv[3], A[3][3], G[3][3];
+                for (int k = 0; k < NS; ++k) to[k] = tau[(size_t)k * n + q];
+            };
+            if (has) load_particle(c0, xp, vp, Cp, tp);
+            for (int i = c0; i < c1; ++i) {
+                const bool more = i + 1 < c1;
+                if (more) load_particle(i + 1, xq, vq, Cq, tq);
+                float t[3] = {0, 0, 0}, u[3] = {1, 1, 1};
+                particle_frame<DIM>(P, xp, org, lb, t, u);
+                float wt[3][3], dw[3][3];
+                bspline<DIM>(t, u, inv_dx, wt, dw);
+                float mv[3], A[3][3], G[3][3];
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                mv[a] = mp * vp[a];
+                for (int a = 0; a < DIM; ++a) {
+                    mv[a] = mp * vp[a];
 #pragma unroll
-                for (int b = 0; b < DIM; ++b) A[a][b] = mp * Cp[a * DIM + b];
-            }
-            if (DIM == 3) {
-                G[0][0] = dtv * tp[0];
-                G[1][1] = dtv * tp[1];
-                G[2][2] = dtv * tp[2];
-                G[0][1] = G[1][0] = dtv * tp[3];
-                G[1][2] = G[2][1] = dtv * tp[4];
-                G[0][2] = G[2][0] = dtv * tp[5];
-            } else {
-                G[0][0] = dtv * tp[0];
-                G[1][1] = dtv * tp[1];
-                G[0][1] = G[1][0] = dtv * tp[2];
-            }
-            // x_n - x_p = (k - 1/2 - t) dx per axis
-            float dxn[3][3];
+                    for (int bb = 0; bb < DIM; ++bb) A[a][bb] = mp * Cp[a * DIM + bb];
+                }
+                if (DIM == 3) {
+                    G[0][0] = dtv * tp[0];
+                    G[1][1] = dtv * tp[1];
+                    G[2][2] = dtv * tp[2];
+                    G[0][1] = G[1][0] = dtv * tp[3];
+                    G[1][2] = G[2][1] = dtv * tp[4];
+                    G[0][2] = G[2][0] = dtv * tp[5];
+                } else {
+                    G[0][0] = dtv * tp[0];
+                    G[1][1] = dtv * tp[1];
+                    G[0][1] = G[1][0] = dtv * tp[2];
+                }
+                float dxn[3][3];
 #pragma unroll
-            for (int a = 0; a < DIM; ++a)
+                for (int a = 0; a < DIM; ++a)
 #pragma unroll
-                for (int k = 0; k < 3; ++k) dxn[a][k] = ((float)k - 0.5f - t[a]) * dx;
-            if (DIM == 3) {
+                    for (int k = 0; k < 3; ++k) dxn[a][k] = ((float)k - 0.5f - t[a]) * dx;
+                // Tensor-product factorisation along x: with a = w_y w_z, the
+                // contribution to node k is w_x b + A_0 (a w_x dx_x) - G_0 (a dw_x)
+                // where b = a (m v + A_1 dx_y + A_2 dx_z) - G_1 dw_y w_z - G_2 w_y dw_z
+                // (A = m_p C_p, G = dt V0 tau_p, columns A_j, G_j).
+                if (DIM == 3) {
 #pragma unroll
-                for (int kz = 0; kz < 3; ++kz)
+                    for (int kz = 0; kz < 3; ++kz)
 #pragma unroll
-                    for (int ky = 0; ky < 3; ++ky) {
-                        const float wyz = wt[1][ky] * wt[2][kz];
-                        const float dyz = dw[1][ky] * wt[2][kz];
-                        const float ydz = wt[1][ky] * dw[2][kz];
-#pragma unroll
-                        for (int kx = 0; kx < 3; ++kx) {
-                            const float N = wt[0][kx] * wyz;
-                            const float g0 = dw[0][kx] * wyz, g1 = wt[0][kx] * dyz, g2 = wt[0][kx] * ydz;
-                            const float d0 = dxn[0][kx], d1 = dxn[1][ky], d2 = dxn[2][kz];
-                            float pm[3];
+                        for (int ky = 0; ky < 3; ++ky) {
+                            const float al = wt[1][ky] * wt[2][kz];
+                            const float gy = dw[1][ky] * wt[2][kz], gz = wt[1][ky] * dw[2][kz];
+                            const float dy = dxn[1][ky], dz = dxn[2][kz];
+                            float be[3];
 #pragma unroll
                             for (int a = 0; a < 3; ++a)
-                                pm[a] = N * (mv[a] + A[a][0] * d0 + A[a][1] * d1 + A[a][2] * d2) -
-                                        (G[a][0] * g0 + G[a][1] * g1 + G[a][2] * g2);
-                            const int idx = (lb[0] + kx) + Tile<3>::E * ((lb[1] + ky) + Tile<3>::E * (lb[2] + kz));
-                            atomicAdd(&tile[0][idx], pm[0]);
-                            atomicAdd(&tile[1][idx], pm[1]);
-                            atomicAdd(&tile[2][idx], pm[2]);
-                            atomicAdd(&tile[3][idx], N * mp);
+                                be[a] = al * (mv[a] + A[a][1] * dy + A[a][2] * dz) - G[a][1] * gy - G[a][2] * gz;
+#pragma unroll
+                            for (int kx = 0; kx < 3; ++kx) {
+                                const int k = kx + 3 * (ky + 3 * kz);
+                                const float wx = wt[0][kx];
+                                const float ca = al * wx * dxn[0][kx], cg = al * dw[0][kx];
+#pragma unroll
+                                for (int a = 0; a < 3; ++a) acc[k][a] += wx * be[a] + A[a][0] * ca - G[a][0] * cg;
+                                acc[k][3] += al * wx * mp;
+                            }
+                        }
+                } else {
+#pragma unroll
+                    for (int ky = 0; ky < 3; ++ky) {
+                        const float al = wt[1][ky];
+                        const float gy = dw[1][ky];
+                        const float dy = dxn[1][ky];
+                        float be[2];
+#pragma unroll
+                        for (int a = 0; a < 2; ++a) be[a] = al * (mv[a] + A[a][1] * dy) - G[a][1] * gy;
+#pragma unroll
+                        for (int kx = 0; kx < 3; ++kx) {
+                            const int k = kx + 3 * ky;
+                            const float wx = wt[0][kx];
+                            const float ca = al * wx * dxn[0][kx], cg = al * dw[0][kx];
+#pragma unroll
+                            for (int a = 0; a < 2; ++a) acc[k][a] += wx * be[a] + A[a][0] * ca - G[a][0] * cg;
+                            acc[k][3] += al * wx * mp;
                         }
                     }
-            } else {
+                }
+                if (more) {
 #pragma unroll
-                for (int ky = 0; ky < 3; ++ky)
-#pragma unroll
-                    for (int kx = 0; kx < 3; ++kx) {
-                        const float N = wt[0][kx] * wt[1][ky];
-                        const float g0 = dw[0][kx] * wt[1][ky], g1 = wt[0][kx] * dw[1][ky];
-                        const float d0 = dxn[0][kx], d1 = dxn[1][ky];
-                        float pm[2];
-#pragma unroll
-                        for (int a = 0; a < 2; ++a)
-                            pm[a] = N * (mv[a] + A[a][0] * d0 + A[a][1] * d1) - (G[a][0] * g0 + G[a][1] * g1);
-                        const int idx = (lb[0] + kx) + Tile<2>::E * (lb[1] + ky);
-                        atomicAdd(&tile[0][idx], pm[0]);
-                        atomicAdd(&tile[1][idx], pm[1]);
-                        atomicAdd(&tile[3][idx], N * mp);
+                    for (int a = 0; a < 3; ++a) {
+                        xp[a] = xq[a];
+                        vp[a] = vq[a];
                     }
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) Cp[k] = Cq[k];
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) tp[k] = tq[k];
+                }
             }
         }
+        // Merge the cell sums into the tile.  For a fixed offset k, distinct
+        // cells address distinct nodes, so each offset is a conflict-free
+        // read-add-write; the barrier orders successive offsets, which may hit
+        // the same node from neighbouring cells.
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            const int kx = k % 3, ky = (k / 3) % 3, kz = DIM == 3 ? k / 9 : 0;
+            const int idx = (lb[0] + kx) + T::E * ((lb[1] + ky) + (DIM == 3 ? T::E * (lb[2] + kz) : 0));
+            if (has) {
+                tile[0][idx] += acc[k][0];
+                tile[1][idx] += acc[k][1];
+                if (DIM == 3) tile[2][idx] += acc[k][2];
+                tile[3][idx] += acc[k][3];
+            }
+            __syncthreads();
+        }
         __syncthreads();
-        for (int t = threadIdx.x; t < T::N; t += WG) {
+        for (int t = lane; t < T::N; t += 64) {
             const float m = tile[3][t], p0 = tile[0][t], p1 = tile[1][t], p2 = DIM == 3 ? tile[2][t] : 0.f;
             if (m != 0.f || p0 != 0.f || p1 != 0.f || p2 != 0.f) {
                 const int I = t % T::E;
                 const int J = (t / T::E) % T::E;
                 const int K = DIM == 3 ? t / (T::E * T::E) : 0;
                 const int d = (I >> 2) | ((J >> 2) << 1) | ((K >> 2) << 2);
-                const int phi = nbr[d];
+                const int phi = P.b_nbr[(size_t)b * T::NB + d];
                 if (phi >= 0) {
                     const int l = (I & 3) + BLK * ((J & 3) + BLK * (K & 3));
                     float* g = reinterpret_cast<float*>(&P.grid[(size_t)phi * T::NPB + l]);
@@ -300,9 +344,13 @@ __device__ __forceinline__ void jacobi_sym(float (*A)[3], float (*U)[3]) {
             const int q = pr == 0 ? 1 : 2;
             const float apq = A[p][q];
             if (apq != 0.f) {
-                const float th = (A[q][q] - A[p][p]) / (2.f * apq);
-                const float t = copysignf(1.f, th) / (fabsf(th) + sqrtf(th * th + 1.f));
-                const float c = 1.f / sqrtf(t * t + 1.f);
+                // rotation angle with hardware reciprocal / square root (about
+                // 1 ulp): any rotation that zeroes a_pq to that accuracy and
+                // keeps c^2 + s^2 = 1 to float precision serves the iteration
+                float th = (A[q][q] - A[p][p]) * (0.5f * __builtin_amdgcn_rcpf(apq));
+                th = fminf(fmaxf(th, -1e18f), 1e18f);
+                const float t = copysignf(__builtin_amdgcn_rcpf(fabsf(th) + __builtin_amdgcn_sqrtf(th * th + 1.f)), th);
+                const float c = __builtin_amdgcn_rsqf(t * t + 1.f);
                 const float sn = t * c;
                 A[p][p] -= t * apq;
                 A[q][q] += t * apq;
@@ -356,7 +404,9 @@ __device__ __forceinline__ unsigned constitutive(const DevParams& P, const float
     float tr = 0.f;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        eps[a] = 0.5f * log1pf(fmaxf(M[a][a], -0.999999f));
+        // Hencky strain 0.5 ln(1 + delta) via the hardware log2 (absolute error
+        // ~1e-7, below the float32 resolution of F itself)
+        eps[a] = (0.5f * 0.69314718f) * __builtin_amdgcn_logf(1.f + fmaxf(M[a][a], -0.999999f));
         tr += eps[a];
     }
     bool plastic = false;
@@ -377,7 +427,7 @@ __device__ __forceinline__ unsigned constitutive(const DevParams& P, const float
             const float nd = sqrtf(nd2);
             const float dg = nd + P.dp_coef * tr * P.alpha;
             if (dg > 0.f) {
-                const float sc = dg / nd;
+                const float sc = dg * __builtin_amdgcn_rcpf(nd);
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) e2[a] = eps[a] - sc * dev[a];
                 plastic = true;
@@ -391,7 +441,7 @@ __device__ __forceinline__ unsigned constitutive(const DevParams& P, const float
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         sig[a] = 2.f * P.mu * e2[a] + P.lam * tr2;
-        gam[a] = expm1f(e2[a] - eps[a]);
+        gam[a] = __builtin_amdgcn_exp2f((e2[a] - eps[a]) * 1.44269504f) - 1.f;
     }
     float T[3][3], W[3][3];
 #pragma unroll
@@ -447,19 +497,23 @@ struct G2POut {
     uint32_t* id;
 };
 
-template <int DIM, int WAVES>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_g2p(
-    DevParams P, G2PIn in, G2POut out, int n, const uint32_t* __restrict__ order) {
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_g2p(DevParams P, G2PIn in, G2POut out, int n,
+                                            const uint32_t* __restrict__ order) {
     using T = Tile<DIM>;
     constexpr int NS = DIM == 3 ? 6 : 3;
+    constexpr int DD = DIM * DIM;
     __shared__ float4 vt[T::N];
+    __shared__ float xs[DIM][G2P_MAX_ITEM];
+    __shared__ float fs[DD][G2P_MAX_ITEM];
     __shared__ int nbr[T::NB];
     __shared__ int org[3];
     const int n_work = min(P.ctr->n_work, P.work_cap);
     const float dt = P.dt, dx = P.dxf, inv_dx = P.inv_dxf;
     const float cscale = 4.f * inv_dx * inv_dx;  // D_p^{-1} = (4/dx^2) I for quadratic B-splines
     for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
-        const int blk = P.w_block[w], s = P.w_start[w], e = P.w_end[w];
+        const int blk = P.w_block[w], s = P.w_start[w];
+        const int L = min(P.w_end[w] - s, G2P_MAX_ITEM);
         if (threadIdx.x < T::NB) nbr[threadIdx.x] = P.b_nbr[blk * T::NB + threadIdx.x];
         if (threadIdx.x == 0) {
             int bc[3];
@@ -467,6 +521,17 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WAVES))) voi
             org[0] = bc[0] * BLK;
             org[1] = bc[1] * BLK;
             org[2] = bc[2] * BLK;
+        }
+        // phase 0: issue every global gather of the work item up front
+        // (positions, deformation gradients, ids) and stage them in LDS
+#pragma unroll 2
+        for (int r = threadIdx.x; r < L; r += WG) {
+            const size_t q = order[s + r];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) xs[a][r] = in.x[(size_t)a * n + q];
+#pragma unroll
+            for (int k = 0; k < DD; ++k) fs[k][r] = in.F[(size_t)k * n + q];
+            if (out.id) out.id[s + r] = in.id ? in.id[q] : (uint32_t)q;
         }
         __syncthreads();
         for (int t = threadIdx.x; t < T::N; t += WG) {
@@ -477,15 +542,13 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WAVES))) voi
             vt[t] = phi >= 0 ? P.grid[(size_t)phi * T::NPB + l] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
         __syncthreads();
-        for (int i = s + (int)threadIdx.x; i < e; i += WG) {
-            const size_t q = order[i];
-            float xp[3] = {0, 0, 0}, Fp[3][3];
+        // phase 1: grid gather, new position, velocity and affine matrix,
+        // F_trial = (I + dt grad v) F (Eq. 17) kept in LDS
+#pragma unroll 1
+        for (int r = threadIdx.x; r < L; r += WG) {
+            float xp[3] = {0, 0, 0};
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) xp[a] = in.x[(size_t)a * n + q];
-#pragma unroll
-            for (int a = 0; a < DIM; ++a)
-#pragma unroll
-                for (int b = 0; b < DIM; ++b) Fp[a][b] = in.F[(size_t)(a * DIM + b) * n + q];
+            for (int a = 0; a < DIM; ++a) xp[a] = xs[a][r];
             int lb[3] = {0, 0, 0};
             float t[3] = {0, 0, 0}, u[3] = {1, 1, 1};
             particle_frame<DIM>(P, xp, org, lb, t, u);
@@ -496,71 +559,55 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WAVES))) voi
             for (int a = 0; a < DIM; ++a)
 #pragma unroll
                 for (int k = 0; k < 3; ++k) dxn[a][k] = ((float)k - 0.5f - t[a]) * dx;
+            // Tensor-product factorisation along x: per (ky, kz) row sum
+            // S0 = sum w_x v, S1 = sum w_x dx_x v, S2 = sum dw_x v, then
+            // v_p += a S0, B = [a S1 | a dx_y S0 | a dx_z S0],
+            // grad v = [a S2 | dw_y w_z S0 | w_y dw_z S0] with a = w_y w_z.
             float vp[3] = {0, 0, 0}, B[3][3] = {{0}}, gv[3][3] = {{0}};
-            if (DIM == 3) {
 #pragma unroll
-                for (int kz = 0; kz < 3; ++kz)
+            for (int kz = 0; kz < (DIM == 3 ? 3 : 1); ++kz)
 #pragma unroll
-                    for (int ky = 0; ky < 3; ++ky) {
-                        const float wyz = wt[1][ky] * wt[2][kz];
-                        const float dyz = dw[1][ky] * wt[2][kz];
-                        const float ydz = wt[1][ky] * dw[2][kz];
-#pragma unroll
-                        for (int kx = 0; kx < 3; ++kx) {
-                            const int idx = (lb[0] + kx) + T::E * ((lb[1] + ky) + T::E * (lb[2] + kz));
-                            const float4 g = vt[idx];
-                            const float vn[3] = {g.x, g.y, g.z};
-                            const float N = wt[0][kx] * wyz;
-                            const float gr[3] = {dw[0][kx] * wyz, wt[0][kx] * dyz, wt[0][kx] * ydz};
-                            const float dd[3] = {dxn[0][kx], dxn[1][ky], dxn[2][kz]};
-#pragma unroll
-                            for (int a = 0; a < 3; ++a) {
-                                const float nv = N * vn[a];
-                                vp[a] += nv;
-#pragma unroll
-                                for (int b = 0; b < 3; ++b) {
-                                    B[a][b] += nv * dd[b];
-                                    gv[a][b] += vn[a] * gr[b];
-                                }
-                            }
-                        }
-                    }
-            } else {
-#pragma unroll
-                for (int ky = 0; ky < 3; ++ky)
+                for (int ky = 0; ky < 3; ++ky) {
+                    float S0[3] = {0, 0, 0}, S1[3] = {0, 0, 0}, S2[3] = {0, 0, 0};
 #pragma unroll
                     for (int kx = 0; kx < 3; ++kx) {
-                        const int idx = (lb[0] + kx) + T::E * (lb[1] + ky);
+                        const int idx = (lb[0] + kx) + T::E * ((lb[1] + ky) + (DIM == 3 ? T::E * (lb[2] + kz) : 0));
                         const float4 g = vt[idx];
-                        const float vn[2] = {g.x, g.y};
-                        const float N = wt[0][kx] * wt[1][ky];
-                        const float gr[2] = {dw[0][kx] * wt[1][ky], wt[0][kx] * dw[1][ky]};
-                        const float dd[2] = {dxn[0][kx], dxn[1][ky]};
+                        const float vn[3] = {g.x, g.y, g.z};
+                        const float wx = wt[0][kx], wdx = wt[0][kx] * dxn[0][kx], dwx = dw[0][kx];
 #pragma unroll
-                        for (int a = 0; a < 2; ++a) {
-                            const float nv = N * vn[a];
-                            vp[a] += nv;
-#pragma unroll
-                            for (int b = 0; b < 2; ++b) {
-                                B[a][b] += nv * dd[b];
-                                gv[a][b] += vn[a] * gr[b];
-                            }
+                        for (int a = 0; a < DIM; ++a) {
+                            S0[a] += wx * vn[a];
+                            S1[a] += wdx * vn[a];
+                            S2[a] += dwx * vn[a];
                         }
                     }
-            }
-            // F_trial = (I + dt grad v) F  (Eq. 17)
-            float Ft[3][3], Fn[3][3], tau6[6];
+                    const float wz = DIM == 3 ? wt[2][kz] : 1.f;
+                    const float al = wt[1][ky] * wz;
+                    const float b1 = al * dxn[1][ky];
+                    const float g1 = dw[1][ky] * wz;
 #pragma unroll
-            for (int a = 0; a < DIM; ++a)
+                    for (int a = 0; a < DIM; ++a) {
+                        vp[a] += al * S0[a];
+                        B[a][0] += al * S1[a];
+                        B[a][1] += b1 * S0[a];
+                        gv[a][0] += al * S2[a];
+                        gv[a][1] += g1 * S0[a];
+                    }
+                    if (DIM == 3) {
+                        const float b2 = al * dxn[2][kz];
+                        const float g2 = wt[1][ky] * dw[2][kz];
 #pragma unroll
-                for (int b = 0; b < DIM; ++b) {
-                    float s2 = 0.f;
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) s2 += gv[a][c] * Fp[c][b];
-                    Ft[a][b] = Fp[a][b] + dt * s2;
+                        for (int a = 0; a < 3; ++a) {
+                            B[a][2] += b2 * S0[a];
+                            gv[a][2] += g2 * S0[a];
+                        }
+                    }
+                    // keep the LDS gathers of one row in flight at a time
+                    // (bounds register pressure, hence raises occupancy)
+                    __builtin_amdgcn_sched_barrier(0);
                 }
-            unsigned flags = constitutive<DIM>(P, Ft, Fn, tau6);
-            const size_t o = (size_t)i;
+            const size_t o = (size_t)(s + r);
             bool finite = true;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
@@ -572,16 +619,44 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WAVES))) voi
 #pragma unroll
             for (int a = 0; a < DIM; ++a)
 #pragma unroll
+                for (int b = 0; b < DIM; ++b) out.C[(size_t)(a * DIM + b) * n + o] = cscale * B[a][b];
+            float Fp[3][3];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                for (int b = 0; b < DIM; ++b) Fp[a][b] = fs[a * DIM + b][r];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+#pragma unroll
                 for (int b = 0; b < DIM; ++b) {
-                    out.C[(size_t)(a * DIM + b) * n + o] = cscale * B[a][b];
-                    out.F[(size_t)(a * DIM + b) * n + o] = Fn[a][b];
+                    float s2 = 0.f;
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) s2 += gv[a][c] * Fp[c][b];
+                    fs[a * DIM + b][r] = Fp[a][b] + dt * s2;
                 }
+            if (!finite) raise_flag(P.ctr, MPM_FLAG_NAN);
+        }
+        __syncthreads();
+        // phase 2: constitutive update (its register live range is separate)
+#pragma unroll 1
+        for (int r = threadIdx.x; r < L; r += WG) {
+            const size_t o = (size_t)(s + r);
+            float Ft[3][3], Fn[3][3], tau6[6];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                for (int b = 0; b < DIM; ++b) Ft[a][b] = fs[a * DIM + b][r];
+            unsigned flags = constitutive<DIM>(P, Ft, Fn, tau6);
+            bool finite = true;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                for (int b = 0; b < DIM; ++b) out.F[(size_t)(a * DIM + b) * n + o] = Fn[a][b];
 #pragma unroll
             for (int k = 0; k < NS; ++k) {
                 finite = finite && isfinite(tau6[k]);
                 out.tau[(size_t)k * n + o] = tau6[k];
             }
-            if (out.id) out.id[o] = in.id ? in.id[q] : (uint32_t)q;
             if (!finite) flags |= MPM_FLAG_NAN;
             if (flags) raise_flag(P.ctr, flags);
         }
@@ -590,11 +665,12 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WAVES))) voi
 }
 
 hipError_t launch_p2g(const DevParams& P, const float* x, const float* v, const float* C, const float* tau, int n,
-                      const uint32_t* order, int grid_blocks, hipStream_t s) {
+                      const uint32_t* order, const uint32_t* skeys, int grid_blocks, hipStream_t s) {
+    const int g = P.dense ? 65536 : grid_blocks * 4;
     if (P.dim == 3)
-        k_p2g<3><<<grid_blocks, WG, 0, s>>>(P, x, v, C, tau, n, order);
+        k_p2g_cell<3><<<g, 64, 0, s>>>(P, x, v, C, tau, n, order, skeys);
     else
-        k_p2g<2><<<grid_blocks, WG, 0, s>>>(P, x, v, C, tau, n, order);
+        k_p2g_cell<2><<<g, 64, 0, s>>>(P, x, v, C, tau, n, order, skeys);
     return hipGetLastError();
 }
 
@@ -611,20 +687,10 @@ hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, 
                       const uint32_t* order, int grid_blocks, hipStream_t s) {
     G2PIn in{x_in, F_in, id_in};
     G2POut out{x_out, v_out, C_out, F_out, tau_out, id_out};
-    static int variant = [] {
-        const char* v = getenv("MPMX_G2P_WAVES");
-        return v ? atoi(v) : 0;
-    }();
-    if (P.dim == 3) {
-        if (variant == 3)
-            k_g2p<3, 3><<<grid_blocks, WG, 0, s>>>(P, in, out, n, order);
-        else if (variant == 4)
-            k_g2p<3, 4><<<grid_blocks, WG, 0, s>>>(P, in, out, n, order);
-        else
-            k_g2p<3, 1><<<grid_blocks, WG, 0, s>>>(P, in, out, n, order);
-    } else {
-        k_g2p<2, 1><<<grid_blocks, WG, 0, s>>>(P, in, out, n, order);
-    }
+    if (P.dim == 3)
+        k_g2p<3><<<grid_blocks, WG, 0, s>>>(P, in, out, n, order);
+    else
+        k_g2p<2><<<grid_blocks, WG, 0, s>>>(P, in, out, n, order);
     return hipGetLastError();
 }
 
