@@ -90,6 +90,10 @@ typedef struct mpm_ctx mpm_ctx;
 #define MPM_FLAG_SYNC_REBUILD 1  /* mpm_sparse_build synchronises and, on overflow,
                                     doubles the table and block capacity and rebuilds
                                     (Algorithm 7) until it fits */
+#define MPM_FLAG_ADJOINT      2  /* allocate the reverse-mode buffers (pre-boundary
+                                    nodal velocity, grid adjoint, per-particle
+                                    scratch); the grid update then also records u.
+                                    Walls only: not allowed with a heightmap. */
 
 typedef struct mpm_params {
     int dim;                 /* 2 or 3 */
@@ -198,6 +202,30 @@ int mpm_get_grid(mpm_ctx* ctx, float* out, int capacity_blocks, void* stream);
 /* Copies the sort permutation of the last build: order[i] = index in the input
  * set of the particle written to position i by mpm_g2p.  Device pointer. */
 int mpm_get_order(mpm_ctx* ctx, uint32_t* order, int n, void* stream);
+
+/* ---- reverse mode (contexts created with MPM_FLAG_ADJOINT) -------------
+ * The adjoints are those of the discrete step above (not in the paper; they
+ * differentiate P2G, the grid update with wall boundaries, G2P and the
+ * constitutive map, with the active set held fixed).  Adjoint particle sets use
+ * the same SoA layout as states: x_bar, v_bar, C_bar, F_bar (full d x d) and
+ * tau_bar for the stored stress components.  Output-side adjoints are in the
+ * step's output order (the sorted order written by mpm_g2p); input-side
+ * adjoints are in the input order, so the in_bar of one step is the out_bar of
+ * the step before it.  param_bar is a DEVICE float[2] accumulator
+ * (dL/dE in 1/Pa, dL/dphi per degree) that the caller zeroes.
+ *
+ * mpm_g2p_adj: needs mpm_sparse_build, mpm_p2g and mpm_grid_update of `in` on
+ *   this context; writes in_bar->x (partial) and in_bar->F, and records the
+ *   grid adjoint of the nodal velocities.
+ * mpm_grid_update_adj: turns it into the adjoints of nodal momentum and mass.
+ * mpm_p2g_adj: writes in_bar->v, C, tau and adds the rest of in_bar->x.
+ * mpm_step_adj: build + p2g + grid update of `in`, then the three adjoints. */
+int mpm_g2p_adj(mpm_ctx* ctx, const mpm_particles* in, const mpm_particles* out_bar, const mpm_particles* in_bar,
+                float* param_bar, void* stream);
+int mpm_grid_update_adj(mpm_ctx* ctx, void* stream);
+int mpm_p2g_adj(mpm_ctx* ctx, const mpm_particles* in, const mpm_particles* in_bar, void* stream);
+int mpm_step_adj(mpm_ctx* ctx, const mpm_particles* in, const mpm_particles* out_bar, const mpm_particles* in_bar,
+                 float* param_bar, void* stream);
 
 /* Replaces the material constants (E, nu, friction angle) and dt of a live
  * context without reallocating. */

@@ -41,6 +41,10 @@ struct mpm_ctx {
     // work
     int *w_block = nullptr, *w_start = nullptr, *w_end = nullptr;
     float4* grid = nullptr;
+    float4* grid_u = nullptr;
+    float4* grid_bar = nullptr;
+    float* adj_scratch = nullptr;
+    bool adjoint = false;
     float* heightmap = nullptr;
     DevCounters* ctr = nullptr;
     DevParams P{};
@@ -88,6 +92,8 @@ void free_capacity_buffers(mpm_ctx* c) {
     dfree(c->w_start);
     dfree(c->w_end);
     dfree(c->grid);
+    dfree(c->grid_u);
+    dfree(c->grid_bar);
     dfree(c->partials);
 }
 
@@ -99,6 +105,7 @@ void free_all(mpm_ctx* c) {
     dfree(c->v1);
     dfree(c->hist);
     dfree(c->heightmap);
+    dfree(c->adj_scratch);
     dfree(c->ctr);
 }
 
@@ -112,6 +119,9 @@ void fill_material(mpm_ctx* c) {
     c->P.alpha = (float)(sqrt(2.0 / 3.0) * 2.0 * sphi / (3.0 - sphi));
     c->P.dp_coef = (float)((c->dim * lam + 2.0 * mu) / (2.0 * mu));
     c->P.dt = c->prm.dt;
+    c->P.E = c->prm.E;
+    const double phi = c->prm.friction_deg * M_PI / 180.0;
+    c->P.dalpha_dphi = (float)(sqrt(2.0 / 3.0) * 6.0 * cos(phi) / ((3.0 - sphi) * (3.0 - sphi)) * (M_PI / 180.0));
 }
 
 void fill_params(mpm_ctx* c) {
@@ -159,6 +169,10 @@ void fill_params(mpm_ctx* c) {
     P.chunk = c->chunk;
     P.grid = c->grid;
     P.ctr = c->ctr;
+    P.grid_u = c->grid_u;
+    P.grid_bar = c->grid_bar;
+    P.adj_scratch = c->adj_scratch;
+    P.param_bar = nullptr;
     fill_material(c);
 }
 
@@ -189,6 +203,10 @@ int alloc_capacity_buffers(mpm_ctx* c) {
     e = e ? e : dalloc(&c->w_start, (size_t)c->work_cap);
     e = e ? e : dalloc(&c->w_end, (size_t)c->work_cap);
     e = e ? e : dalloc(&c->grid, cap * NPB);
+    if (c->adjoint) {
+        e = e ? e : dalloc(&c->grid_u, cap * NPB);
+        e = e ? e : dalloc(&c->grid_bar, cap * NPB);
+    }
     e = e ? e : dalloc(&c->partials, (size_t)scan_partials_size(scan_n));
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -276,6 +294,7 @@ int mpm_create(const mpm_params* q, mpm_ctx** out) {
     if (!(q->E > 0.f) || !(q->nu >= 0.f && q->nu < 0.5f) || !(q->p_mass > 0.f) || !(q->p_vol0 > 0.f)) return MPM_ERR_ARG;
     if (q->grid_mode != MPM_GRID_SPARSE && q->grid_mode != MPM_GRID_DENSE) return MPM_ERR_ARG;
     if (q->heightmap && q->dim != 3) return MPM_ERR_ARG;
+    if (q->heightmap && (q->flags & MPM_FLAG_ADJOINT)) return MPM_ERR_ARG;
     if (q->bound < 0 || q->block_capacity < 0 || q->hash_capacity_log2 < 0 || q->hash_capacity_log2 > 30)
         return MPM_ERR_ARG;
     for (int a = 0; a < q->dim; ++a) {
@@ -289,6 +308,7 @@ int mpm_create(const mpm_params* q, mpm_ctx** out) {
     c->prm.heightmap = nullptr;
     c->dim = q->dim;
     c->dense = q->grid_mode == MPM_GRID_DENSE;
+    c->adjoint = (q->flags & MPM_FLAG_ADJOINT) != 0;
     c->max_particles = q->max_particles;
     long long total = 1;
     for (int a = 0; a < 3; ++a) {
@@ -332,6 +352,7 @@ int mpm_create(const mpm_params* q, mpm_ctx** out) {
     e = e ? e : dalloc(&c->v1, np);
     e = e ? e : dalloc(&c->hist, (size_t)radix_hist_size(q->max_particles));
     e = e ? e : dalloc(&c->ctr, 1);
+    if (c->adjoint) e = e ? e : dalloc(&c->adj_scratch, np * (size_t)(c->dim + 2 * c->dim * c->dim));
     if (e == hipSuccess && q->heightmap) {
         const size_t hn = (size_t)(q->cells[0] + 1) * (size_t)(q->cells[1] + 1);
         e = dalloc(&c->heightmap, hn);
@@ -452,6 +473,56 @@ int mpm_step(mpm_ctx* c, const mpm_particles* a, const mpm_particles* b, int n_s
         std::swap(cur, nxt);
     }
     return MPM_OK;
+}
+
+int mpm_g2p_adj(mpm_ctx* c, const mpm_particles* in, const mpm_particles* ob, const mpm_particles* ib,
+                float* param_bar, void* stream) {
+    if (!c || !particles_ok(c, in, false) || !in->F || !ob || !ib || !param_bar) return MPM_ERR_ARG;
+    if (!ob->x || !ob->v || !ob->C || !ob->F || !ob->tau || !ib->x || !ib->F) return MPM_ERR_ARG;
+    if (ob->n != in->n || ib->n != in->n) return MPM_ERR_ARG;
+    if (!c->adjoint || !c->built || in->n != c->built_n) return MPM_ERR_STATE;
+    if (in->n == 0) return MPM_OK;
+    DevParams P = c->P;
+    P.param_bar = param_bar;
+    const float* obp[5] = {ob->x, ob->v, ob->C, ob->F, ob->tau};
+    const int wgs = std::min(c->persistent_wgs, c->work_cap);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_g2p_adj(P, in->x, in->F, obp, ib->x, ib->F, in->n, c->order, wgs, s);
+    if (e == hipSuccess) e = launch_scatter_adj(P, in->x, in->n, c->order, c->skeys, wgs, s);
+    return hip_status(e);
+}
+
+int mpm_grid_update_adj(mpm_ctx* c, void* stream) {
+    if (!c) return MPM_ERR_ARG;
+    if (!c->adjoint || !c->built) return MPM_ERR_STATE;
+    const long long NPB = 1ll << (2 * c->dim);
+    const long long nodes = (long long)c->block_cap * NPB;
+    long long wgs = std::min<long long>((nodes + WG - 1) / WG, c->dense ? 65536 : 8192);
+    return hip_status(launch_grid_adj(c->P, c->dense ? nodes : -1, (int)std::max(1ll, wgs), (hipStream_t)stream));
+}
+
+int mpm_p2g_adj(mpm_ctx* c, const mpm_particles* in, const mpm_particles* ib, void* stream) {
+    if (!c || !particles_ok(c, in, true) || !ib || ib->n != in->n) return MPM_ERR_ARG;
+    if (!ib->x || !ib->v || !ib->C || !ib->tau) return MPM_ERR_ARG;
+    if (!c->adjoint || !c->built || in->n != c->built_n) return MPM_ERR_STATE;
+    if (in->n == 0) return MPM_OK;
+    const float* inp[4] = {in->x, in->v, in->C, in->tau};
+    float* ibp[4] = {ib->x, ib->v, ib->C, ib->tau};
+    const int wgs = std::min(c->persistent_wgs, c->work_cap);
+    return hip_status(launch_p2g_adj(c->P, inp, ibp, in->n, c->order, wgs, (hipStream_t)stream));
+}
+
+int mpm_step_adj(mpm_ctx* c, const mpm_particles* in, const mpm_particles* ob, const mpm_particles* ib,
+                 float* param_bar, void* stream) {
+    if (!c) return MPM_ERR_ARG;
+    if (!c->adjoint) return MPM_ERR_STATE;
+    int st = mpm_sparse_build(c, in, stream);
+    if (st == MPM_OK) st = mpm_p2g(c, in, stream);
+    if (st == MPM_OK) st = mpm_grid_update(c, stream);
+    if (st == MPM_OK) st = mpm_g2p_adj(c, in, ob, ib, param_bar, stream);
+    if (st == MPM_OK) st = mpm_grid_update_adj(c, stream);
+    if (st == MPM_OK) st = mpm_p2g_adj(c, in, ib, stream);
+    return st;
 }
 
 int mpm_get_status(mpm_ctx* c, void* stream, uint32_t* flags) {

@@ -82,6 +82,13 @@ struct DevParams {
     // grid
     float4* grid;
     DevCounters* ctr;
+    // reverse mode (allocated with MPM_FLAG_ADJOINT)
+    float4* grid_u;      // pre-boundary nodal velocity u = p/m + dt g, and m
+    float4* grid_bar;    // adjoint of the nodal velocity, then (p_bar, m_bar)
+    float* adj_scratch;  // per sorted particle: v'_bar (d), B_bar (d*d), W_bar (d*d); plane stride n
+    float* param_bar;    // accumulated dL/dE, dL/dphi (per degree)
+    float E;
+    float dalpha_dphi;   // d alpha / d phi, per degree
 };
 
 // ---------------------------------------------------------------------------
@@ -219,6 +226,13 @@ hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, 
                       float* v_out, float* C_out, float* F_out, float* tau_out, uint32_t* id_out, int n,
                       const uint32_t* order, int grid_blocks, hipStream_t s);
 hipError_t launch_clear_flags(DevCounters* c, hipStream_t s);
+hipError_t launch_g2p_adj(const DevParams& P, const float* x, const float* F, const float* const* out_bar, float* x_bar,
+                          float* F_bar, int n, const uint32_t* order, int grid_blocks, hipStream_t s);
+hipError_t launch_scatter_adj(const DevParams& P, const float* x, int n, const uint32_t* order, const uint32_t* skeys,
+                              int grid_blocks, hipStream_t s);
+hipError_t launch_grid_adj(const DevParams& P, long long n_nodes_host, int grid_blocks, hipStream_t s);
+hipError_t launch_p2g_adj(const DevParams& P, const float* const* in, float* const* in_bar, int n,
+                          const uint32_t* order, int grid_blocks, hipStream_t s);
 hipError_t launch_copy_active(const DevParams& P, uint64_t* keys, uint64_t* masks, int cap, hipStream_t s);
 
 }  // namespace mpmx

@@ -1,0 +1,106 @@
+// Device helpers shared by the forward and adjoint transfer kernels: the
+// (4+2)^d node tile of an owner block, the per-particle frame (base node,
+// t = s - b, u = 1 - t), quadratic B-spline weights, and a cyclic Jacobi
+// eigen-solver for symmetric 3x3 (2x2) matrices.
+#pragma once
+
+#include "internal.h"
+
+namespace mpmx {
+
+constexpr int G2P_MAX_ITEM = 512;     // particles per G2P work item (LDS staging)
+constexpr int P2G_ORDER_STAGE = 1024; // sort permutation entries staged per P2G block
+
+template <int DIM>
+struct Tile {
+    static constexpr int E = BLK + 2;                       // 6 nodes per axis
+    static constexpr int N = DIM == 3 ? E * E * E : E * E;  // 216 / 36
+    static constexpr int NB = 1 << DIM;                     // blocks touched
+    static constexpr int NPB = 1 << (2 * DIM);              // nodes per block
+};
+
+// Per-axis base offset within the owner block, t and u, for one particle.
+template <int DIM>
+__device__ __forceinline__ void particle_frame(const DevParams& P, const float* xp, const int* org, int* lb, float* t,
+                                               float* u) {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const double s = index_arg(xp[a], P.inv_dx);
+        double f = floor(s);
+        f = fmin(fmax(f, 0.0), (double)(P.cells[a] - 2));  // keeps indices in range for flagged particles
+        const double td = s - f;
+        t[a] = fminf(fmaxf((float)td, 0.f), 1.f);
+        u[a] = fminf(fmaxf((float)(1.0 - td), 0.f), 1.f);
+        lb[a] = min(max((int)f - org[a], 0), BLK - 1);
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ void bspline(const float* t, const float* u, float inv_dx, float (*w)[3], float (*dw)[3]) {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        w[a][0] = 0.5f * u[a] * u[a];
+        w[a][1] = 0.5f + t[a] * u[a];
+        w[a][2] = 0.5f * t[a] * t[a];
+        dw[a][0] = -u[a] * inv_dx;
+        dw[a][1] = (u[a] - t[a]) * inv_dx;
+        dw[a][2] = t[a] * inv_dx;
+    }
+}
+
+
+// second derivative (in xi) of the 1D quadratic B-spline at the three stencil
+// nodes: +1, -2, +1 (times inv_dx^2)
+__device__ __forceinline__ void bspline_dd(float inv_dx2, float* ddw) {
+    ddw[0] = inv_dx2;
+    ddw[1] = -2.f * inv_dx2;
+    ddw[2] = inv_dx2;
+}
+
+// ---------------------------------------------------------------------------
+// constitutive update: Hencky strain from the eigen-decomposition of
+// F F^T - I (cyclic Jacobi), Drucker-Prager return map, Kirchhoff stress.
+template <int DIM>
+__device__ __forceinline__ void jacobi_sym(float (*A)[3], float (*U)[3]) {
+    constexpr int SWEEPS = DIM == 3 ? 4 : 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) U[a][b] = a == b ? 1.f : 0.f;
+#pragma unroll
+    for (int sw = 0; sw < SWEEPS; ++sw) {
+#pragma unroll
+        for (int pr = 0; pr < (DIM == 3 ? 3 : 1); ++pr) {
+            const int p = pr == 2 ? 1 : 0;
+            const int q = pr == 0 ? 1 : 2;
+            const float apq = A[p][q];
+            if (apq != 0.f) {
+                // rotation angle with hardware reciprocal / square root (about
+                // 1 ulp): any rotation that zeroes a_pq to that accuracy and
+                // keeps c^2 + s^2 = 1 to float precision serves the iteration
+                float th = (A[q][q] - A[p][p]) * (0.5f * __builtin_amdgcn_rcpf(apq));
+                th = fminf(fmaxf(th, -1e18f), 1e18f);
+                const float t = copysignf(__builtin_amdgcn_rcpf(fabsf(th) + __builtin_amdgcn_sqrtf(th * th + 1.f)), th);
+                const float c = __builtin_amdgcn_rsqf(t * t + 1.f);
+                const float sn = t * c;
+                A[p][p] -= t * apq;
+                A[q][q] += t * apq;
+                A[p][q] = A[q][p] = 0.f;
+                if (DIM == 3) {
+                    const int r = 3 - p - q;
+                    const float arp = A[r][p], arq = A[r][q];
+                    A[r][p] = A[p][r] = c * arp - sn * arq;
+                    A[r][q] = A[q][r] = sn * arp + c * arq;
+                }
+#pragma unroll
+                for (int r = 0; r < DIM; ++r) {
+                    const float urp = U[r][p], urq = U[r][q];
+                    U[r][p] = c * urp - sn * urq;
+                    U[r][q] = sn * urp + c * urq;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace mpmx

@@ -22,6 +22,7 @@ MPM_BC = {"none": 0, "sticky": 1, "slip": 2, "separate": 3}
 MPM_MODEL = {"elastic": 0, "dp": 1}
 MPM_GRID_SPARSE, MPM_GRID_DENSE = 0, 1
 MPM_FLAG_SYNC_REBUILD = 1
+MPM_FLAG_ADJOINT = 2
 
 
 class mpm_params(ctypes.Structure):
@@ -78,6 +79,12 @@ _SIGS = {
     "mpm_get_grid": (c_int, [_PCTX, c_void_p, c_int, c_void_p]),
     "mpm_get_order": (c_int, [_PCTX, c_void_p, c_int, c_void_p]),
     "mpm_set_material": (c_int, [_PCTX, c_float, c_float, c_float, c_float]),
+    "mpm_g2p_adj": (c_int, [_PCTX, POINTER(mpm_particles), POINTER(mpm_particles), POINTER(mpm_particles),
+                            c_void_p, c_void_p]),
+    "mpm_grid_update_adj": (c_int, [_PCTX, c_void_p]),
+    "mpm_p2g_adj": (c_int, [_PCTX, POINTER(mpm_particles), POINTER(mpm_particles), c_void_p]),
+    "mpm_step_adj": (c_int, [_PCTX, POINTER(mpm_particles), POINTER(mpm_particles), POINTER(mpm_particles),
+                             c_void_p, c_void_p]),
 }
 
 
@@ -183,6 +190,24 @@ def mpm_set_material(ctx, E: float, nu: float, friction_deg: float, dt: float):
     _check(lib.mpm_set_material(ctx, E, nu, friction_deg, dt), "mpm_set_material")
 
 
+def mpm_g2p_adj(ctx, pin: mpm_particles, out_bar: mpm_particles, in_bar: mpm_particles, param_bar, stream=None):
+    _check(lib.mpm_g2p_adj(ctx, ctypes.byref(pin), ctypes.byref(out_bar), ctypes.byref(in_bar),
+                           c_void_p(param_bar.data_ptr()), _stream(stream)), "mpm_g2p_adj")
+
+
+def mpm_grid_update_adj(ctx, stream=None):
+    _check(lib.mpm_grid_update_adj(ctx, _stream(stream)), "mpm_grid_update_adj")
+
+
+def mpm_p2g_adj(ctx, pin: mpm_particles, in_bar: mpm_particles, stream=None):
+    _check(lib.mpm_p2g_adj(ctx, ctypes.byref(pin), ctypes.byref(in_bar), _stream(stream)), "mpm_p2g_adj")
+
+
+def mpm_step_adj(ctx, pin: mpm_particles, out_bar: mpm_particles, in_bar: mpm_particles, param_bar, stream=None):
+    _check(lib.mpm_step_adj(ctx, ctypes.byref(pin), ctypes.byref(out_bar), ctypes.byref(in_bar),
+                            c_void_p(param_bar.data_ptr()), _stream(stream)), "mpm_step_adj")
+
+
 # ---------------------------------------------------------------------------
 # marshalling helpers
 def params_from_workload(w, *, max_particles=None, grid_mode=MPM_GRID_SPARSE, block_capacity=0,
@@ -239,6 +264,16 @@ class ParticleSet:
         ids = np.arange(n, dtype=np.int32) if ids is None else np.asarray(ids, dtype=np.int32)
         ps.id.copy_(torch.from_numpy(ids))
         return ps
+
+    def copy_(self, other: "ParticleSet"):
+        for k in ("x", "v", "C", "F", "tau", "id"):
+            getattr(self, k).copy_(getattr(other, k))
+        return self
+
+    def zero_(self):
+        for k in ("x", "v", "C", "F", "tau"):
+            getattr(self, k).zero_()
+        return self
 
     def to_arrays(self) -> dict:
         return {k: getattr(self, k).detach().cpu().numpy() for k in ("x", "v", "C", "F", "tau")}

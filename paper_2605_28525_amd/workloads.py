@@ -333,3 +333,36 @@ def perturbed(w: Workload, seed: int, v_scale=0.05, C_scale=1.0, F_scale=1e-3, t
     w.F = (w.F + rng.normal(0, F_scale, size=(d * d, n))).astype(np.float32)
     w.tau = rng.normal(0, tau_scale, size=w.tau.shape).astype(np.float32)
     return w
+
+
+def differentiable_3d(seed: int = 3) -> Workload:
+    """Calibration workload: the 3D column collapse at 1/8 volume (256x64x64
+    cells, 32^3-cell column, 8 ppc, 262,144 particles), 400 steps."""
+    w = collapse_3d(seed=seed, scale=2)
+    w.name = "differentiable_3d"
+    w.steps = 400
+    return w
+
+
+def differentiable_fd_copy(seed: int = 3) -> Workload:
+    """Small copy for finite-difference checks: an 8^3-cell column at 8 ppc
+    (4096 particles) in a 64x32x32-cell grid."""
+    dx = 0.01
+    rng = np.random.default_rng(seed)
+    x = stratified_cells((3, 3, 12), (11, 11, 20), dx, 2, rng)
+    vol = dx ** 3 / 8
+    w = Workload(name="differentiable_fd_copy", dim=3, dx=dx, cells=(64, 32, 32), gravity=(0.0, -9.81, 0.0),
+                 dt=1e-4, steps=400, ppc=8, p_vol0=vol, p_mass=_SAND["rho"] * vol,
+                 bc=(("separate", "separate"), ("sticky", "separate"), ("separate", "separate")), **_SAND)
+    for k, a in rest_state(x).items():
+        setattr(w, k, a)
+    return w
+
+
+def calibration_target_velocity(n: int, dim: int = 3, seed: int = 1003) -> np.ndarray:
+    """Initial velocity of the target run: (0.5, 0, 0) m/s plus N(0, 0.05^2) per
+    particle and component."""
+    rng = np.random.default_rng(seed)
+    v = rng.normal(0.0, 0.05, size=(dim, n))
+    v[0] += 0.5
+    return v.astype(np.float32)

@@ -162,3 +162,46 @@ def test_multistep_gradient_matches_fd():
     pP = [om.Params(**{**p.__dict__, "friction_deg": p.friction_deg * (1 + s * 1e-6)}) for s in (1, -1)]
     fdP = (loss(st0, pP[0]) - loss(st0, pP[1])) / (2e-6 * p.friction_deg)
     assert abs(fdP - phi_bar) <= 1e-5 * abs(fdP) + 1e-14
+
+
+def test_fd_copy_gradient_matches_central_differences():
+    """The 4096-particle calibration copy: dL/dv0 (two random directions), dL/dE
+    and dL/dphi of a 10-step rollout from the oracle's reverse mode against FP64
+    central differences (h = 1e-5 relative for E and phi, 1e-6 m/s for v0).
+    Over several steps some particles sit near a kink of the return map or of a
+    separating wall, so central differences drift with h (1e-4 .. 1e-3 relative
+    at h = 1e-4 .. 1e-5, converging as h shrinks); 1e-4 at h = 1e-6 still rejects
+    any missing or wrong term, which shows up at the 1e-2 .. 1e0 level."""
+    w = wl.differentiable_fd_copy()
+    w.E, w.dt = 2.0e5, 2.0e-4
+    p = om.Params.from_workload(w)
+    n, d = w.n, w.dim
+    rng = np.random.default_rng(1004)
+    v0 = wl.calibration_target_velocity(n, seed=1003).astype(np.float64).T
+    st0 = om.state_from_soa(w.state(), d)
+    st0["v"] = v0
+    target = st0["x"] + rng.normal(0, 0.01, size=st0["x"].shape)
+    steps = 10
+    L, v0_bar, E_bar, phi_bar = oa.run_with_gradient(st0, p, steps, target)
+
+    def loss(s0, pp):
+        s = s0
+        for _ in range(steps):
+            s = om.step(s, pp)
+        diff = s["x"] - target
+        return 0.5 * np.sum(diff * diff) / len(diff)
+
+    for _ in range(2):
+        dv = rng.normal(size=v0.shape)
+        sp = dict(st0, v=v0 + 1e-6 * dv)
+        sm = dict(st0, v=v0 - 1e-6 * dv)
+        fd = (loss(sp, p) - loss(sm, p)) / 2e-6
+        assert abs(fd - np.sum(v0_bar * dv)) <= 1e-4 * abs(fd)
+    # parameters: h = 1e-5 relative (at 1e-6 the loss difference for phi sits at
+    # the float64 round-off floor of the loss)
+    pE = [om.Params(**{**p.__dict__, "E": p.E * (1 + s * 1e-5)}) for s in (1, -1)]
+    fdE = (loss(st0, pE[0]) - loss(st0, pE[1])) / (2e-5 * p.E)
+    assert abs(fdE - E_bar) <= 1e-4 * abs(fdE)
+    pP = [om.Params(**{**p.__dict__, "friction_deg": p.friction_deg * (1 + s * 1e-5)}) for s in (1, -1)]
+    fdP = (loss(st0, pP[0]) - loss(st0, pP[1])) / (2e-5 * p.friction_deg)
+    assert abs(fdP - phi_bar) <= 1e-4 * abs(fdP)
