@@ -45,6 +45,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--block-capacity", type=int, default=0)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=400)
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--ensemble-steps", type=int, default=200)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of this many MiB (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -96,6 +100,94 @@ def time_steps(sim, steps, stream, phases=True):
     t = np.array([[ev[k][i].elapsed_time(ev[k][i + 1]) for i in range(4)] for k in range(steps)])
     total = ev[0][0].elapsed_time(ev[-1][4]) / 1e3
     return total, dict(zip(["build", "p2g", "grid_update", "g2p"], t.mean(axis=0).tolist()))
+
+
+def adjoint_ratio(steps, checkpoint=50):
+    """Calibration workload (262,144 particles): wall time of the checkpointed
+    backward pass (segment recompute + adjoint kernels) over the forward pass."""
+    import torch
+    from paper_2605_28525_amd import autograd as AG
+    from paper_2605_28525_amd import workloads as wl
+    w = wl.differentiable_3d()
+    n = w.n
+    roll = AG.Rollout(w, steps=steps, checkpoint=checkpoint)
+    try:
+        v0 = torch.from_numpy(wl.calibration_target_velocity(n, seed=1003)).cuda()
+        # warm-up (JIT of the code objects, allocator)
+        final = roll.run_forward(v0, w.E, w.friction_deg)
+        roll.backward(final, torch.zeros_like(final.x))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        final = roll.run_forward(v0, w.E, w.friction_deg)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x_bar = (final.x - final.x.mean()) / n
+        gE, gphi, gv0 = roll.backward(final, x_bar)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+    finally:
+        roll.close()
+    fwd, bwd = t1 - t0, t2 - t1
+    return {"workload": w.name, "particles": n, "steps": steps, "checkpoint_every": checkpoint,
+            "forward_ms": 1e3 * fwd, "backward_ms": 1e3 * bwd, "ratio": bwd / fwd,
+            "grad_finite": bool(np.isfinite(gE) and np.isfinite(gphi) and torch.isfinite(gv0).all().item())}
+
+
+def ensemble_leg(steps, stream):
+    """64 uneven column collapses (about 19.5 M particles): autotuned, one
+    graph-captured step pair replayed, against the same instances run one after
+    another as 64 stand-alone simulations (eager steps)."""
+    import torch
+    from paper_2605_28525_amd import mpm as M
+    from paper_2605_28525_amd import workloads as wl
+    steps += steps & 1
+    ens = wl.ensemble()
+    n = ens.n
+    log(f"bench: ensemble of {ens.n_instances} instances, {n} particles")
+    sim = M.Simulation(ens)
+    chosen = M.mpm_autotune(sim.ctx, sim.a.view(), sim.b.view(), stream)
+    log(f"bench: ensemble autotune -> chunk {chosen[0]}, p2g wgs {chosen[1]}, g2p wgs {chosen[2]}")
+    M.mpm_graph_capture(sim.ctx, sim.a.view(), sim.b.view(), 2, stream)
+    M.mpm_graph_launch(sim.ctx, 1, stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    M.mpm_graph_launch(sim.ctx, steps // 2, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_batch = e0.elapsed_time(e1) / 1e3
+    rc, flags = sim.status()
+    if rc != 0:
+        raise SystemExit(f"ensemble status: {rc} flags={flags}")
+    nb, _ = M.mpm_active_count(sim.ctx)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    log("bench: ensemble, 64 stand-alone runs")
+    sims = [M.Simulation(m) for m in ens.members]
+    for s_ in sims:
+        s_.step(2, stream=stream)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for s_ in sims:
+        s_.step(steps, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_seq = e0.elapsed_time(e1) / 1e3
+    for s_ in sims:
+        rc, flags = s_.status()
+        if rc != 0:
+            raise SystemExit(f"ensemble member status: {rc} flags={flags}")
+        s_.close()
+    del sims
+    torch.cuda.empty_cache()
+    return {"workload": ens.name, "instances": ens.n_instances, "particles": n,
+            "particles_min": min(m.n for m in ens.members), "particles_max": max(m.n for m in ens.members),
+            "steps": steps, "active_blocks": nb, "tuning": {"chunk": chosen[0], "p2g_workgroups": chosen[1],
+                                                             "g2p_workgroups": chosen[2]},
+            "batched": {"value": n * steps / t_batch, "ms_per_step": 1e3 * t_batch / steps, "graph": True},
+            "sequential": {"value": n * steps / t_seq, "ms_per_step": 1e3 * t_seq / steps, "graph": False},
+            "speedup": t_seq / t_batch, "unit": "particle-steps/s"}
 
 
 def src_digest(*names):
@@ -244,6 +336,13 @@ def main():
         simd.close()
         del simd
         torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        log("bench: adjoint/forward ratio")
+        out["adjoint"] = adjoint_ratio(args.adjoint_steps)
+        out["adjoint_forward_ratio"] = out["adjoint"]["ratio"]
+    if not args.no_ensemble:
+        log("bench: ensemble")
+        out["ensemble"] = ensemble_leg(args.ensemble_steps, stream)
     if not args.no_cpu:
         log("bench: cpu baseline")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)

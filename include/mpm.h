@@ -95,6 +95,14 @@ typedef struct mpm_ctx mpm_ctx;
                                     scratch); the grid update then also records u.
                                     Walls only: not allowed with a heightmap. */
 
+/* Material and time step of one instance of an ensemble (see n_instances). */
+typedef struct mpm_instance {
+    float E, nu;             /* Young's modulus (Pa) and Poisson ratio */
+    float friction_deg;      /* Drucker-Prager friction angle (degrees) */
+    float dt;                /* time step of this instance */
+    float p_mass, p_vol0;    /* particle mass and initial volume */
+} mpm_instance;
+
 typedef struct mpm_params {
     int dim;                 /* 2 or 3 */
     double dx;               /* grid spacing h (Eq. 3), metres */
@@ -117,6 +125,15 @@ typedef struct mpm_params {
     int hash_capacity_log2;  /* log2 H of the block hash table (0 = default) */
     int grid_mode;           /* MPM_GRID_* */
     int flags;               /* MPM_FLAG_SYNC_REBUILD ... */
+    int n_instances;         /* 0 or 1: one simulation.  2..64: an ensemble of independent
+                                simulations on identical potential grids, sharing every
+                                buffer; each particle names its instance in inst[] and each
+                                instance has its own material and dt (instances[]).  The
+                                instance id is folded into the sort key and into the block
+                                key (then m = 19 bits per coordinate, bias 2^18, instance in
+                                bits 57-62); the instance, block and cell bits together must
+                                fit 32 bits.  Sparse grid only, no adjoint. */
+    const mpm_instance* instances;  /* HOST pointer, n_instances entries, copied at create */
 } mpm_params;
 
 typedef struct mpm_particles {
@@ -127,6 +144,8 @@ typedef struct mpm_particles {
     float* F;
     float* tau;
     uint32_t* id;            /* optional */
+    uint32_t* inst;          /* instance of each particle (ensembles; NULL = instance 0),
+                                permuted with the particle like id */
 } mpm_particles;
 
 /* Create a context: validates *params, copies the heightmap, allocates every
@@ -190,7 +209,8 @@ int mpm_active_count(mpm_ctx* ctx, void* stream, int* n_blocks, int* n_touched);
  * packed block key of Eq. 22 (m = 21, bias 2^20; 2D packs (i, j) in the low
  * 42 bits) into keys[] and the node-level active mask (bit l(n) =
  * i_l + 4 (j_l + 4 k_l) set iff node n is in A) into masks[].  Device pointers
- * owned by the caller.  Sparse mode only. */
+ * owned by the caller.  Sparse mode only.  In an ensemble the keys use the
+ * ensemble packing (instance in bits 57-62, m = 19, bias 2^18). */
 int mpm_get_active(mpm_ctx* ctx, uint64_t* keys, uint64_t* masks, int capacity, void* stream);
 
 /* Copies the compact grid, 4 floats per node, blocks 0..min(n_blocks,
@@ -226,6 +246,36 @@ int mpm_grid_update_adj(mpm_ctx* ctx, void* stream);
 int mpm_p2g_adj(mpm_ctx* ctx, const mpm_particles* in, const mpm_particles* in_bar, void* stream);
 int mpm_step_adj(mpm_ctx* ctx, const mpm_particles* in, const mpm_particles* out_bar, const mpm_particles* in_bar,
                  float* param_bar, void* stream);
+
+/* ---- graphs and tuning -------------------------------------------------------
+ * mpm_graph_capture records n_steps (even, >= 2) of mpm_step(a, b) into a HIP
+ * graph held by the context (replacing any previous one).  It first waits for
+ * the work queued on `stream`, records on a private stream and executes
+ * nothing.  mpm_graph_launch replays the graph `times` times on `stream`; each
+ * replay advances a by n_steps (the state ends in a).  The step needs no host
+ * synchronisation, so one graph holds whole steps.  The graph keeps the
+ * particle pointers, material and launch shape it was recorded with: a, b must
+ * stay allocated, and mpm_set_material / mpm_set_tuning do not change it.
+ * Returns MPM_ERR_STATE with MPM_FLAG_SYNC_REBUILD (that rebuild needs the
+ * host).  mpm_graph_release frees the graph (mpm_destroy does too). */
+int mpm_graph_capture(mpm_ctx* ctx, const mpm_particles* a, const mpm_particles* b, int n_steps, void* stream);
+int mpm_graph_launch(mpm_ctx* ctx, int times, void* stream);
+int mpm_graph_release(mpm_ctx* ctx);
+
+/* Launch shape of the transfer kernels: particles per G2P / P2G-adjoint work
+ * item (64..512) and persistent workgroup counts of the P2G and G2P launches
+ * (0 = keep).  Takes effect on the next step; a captured graph keeps the shape
+ * it was recorded with. */
+int mpm_set_tuning(mpm_ctx* ctx, int chunk, int p2g_workgroups, int g2p_workgroups);
+
+/* Autotuner: for every candidate launch shape (work-item size in {128, 256,
+ * 512} x persistent workgroups in {1024, 2048, 4096, 8192}) runs one warm-up
+ * and 3 timed steps that read a and write b (a is left unchanged; b ends one
+ * step ahead of a), keeps the fastest P2G workgroup count and the fastest
+ * G2P (work-item size, workgroup count) pair, and reports them in chosen[3]
+ * = {chunk, p2g_workgroups, g2p_workgroups} (host ints, may be NULL).
+ * Synchronises the stream. */
+int mpm_autotune(mpm_ctx* ctx, const mpm_particles* a, const mpm_particles* b, int* chosen, void* stream);
 
 /* Replaces the material constants (E, nu, friction angle) and dt of a live
  * context without reallocating. */

@@ -26,7 +26,14 @@ struct mpm_ctx {
     int chunk = 512;
     int max_particles = 0;
     bool dense = false;
-    int persistent_wgs = 2048;
+    int p2g_wgs = 2048;     // persistent workgroups of the P2G launch
+    int g2p_wgs = 2048;     // persistent workgroups of the G2P launch
+    int n_inst = 1;
+    int blk_bits = 0;
+    InstMat* inst = nullptr;  // device table of per-instance constants (ensembles)
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
     // sort
     uint32_t *k0 = nullptr, *k1 = nullptr, *v0 = nullptr, *v1 = nullptr;
     unsigned* hist = nullptr;
@@ -106,22 +113,48 @@ void free_all(mpm_ctx* c) {
     dfree(c->hist);
     dfree(c->heightmap);
     dfree(c->adj_scratch);
+    dfree(c->inst);
     dfree(c->ctr);
 }
 
-void fill_material(mpm_ctx* c) {
-    const double E = c->prm.E, nu = c->prm.nu;
+void release_graph(mpm_ctx* c) {
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+}
+
+// Material constants of one simulation: Lame parameters, the Drucker-Prager
+// cone coefficient alpha = sqrt(2/3) 2 sin(phi) / (3 - sin(phi)) and its
+// derivative in degrees, and (d lambda + 2 mu) / (2 mu).
+InstMat make_instmat(int dim, double E, double nu, double friction_deg, float dt, float p_mass, float p_vol0) {
+    InstMat m{};
     const double mu = E / (2.0 * (1.0 + nu));
     const double lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
-    const double sphi = sin(c->prm.friction_deg * M_PI / 180.0);
-    c->P.mu = (float)mu;
-    c->P.lam = (float)lam;
-    c->P.alpha = (float)(sqrt(2.0 / 3.0) * 2.0 * sphi / (3.0 - sphi));
-    c->P.dp_coef = (float)((c->dim * lam + 2.0 * mu) / (2.0 * mu));
-    c->P.dt = c->prm.dt;
-    c->P.E = c->prm.E;
-    const double phi = c->prm.friction_deg * M_PI / 180.0;
-    c->P.dalpha_dphi = (float)(sqrt(2.0 / 3.0) * 6.0 * cos(phi) / ((3.0 - sphi) * (3.0 - sphi)) * (M_PI / 180.0));
+    const double phi = friction_deg * M_PI / 180.0;
+    const double sphi = sin(phi);
+    m.mu = (float)mu;
+    m.lam = (float)lam;
+    m.alpha = (float)(sqrt(2.0 / 3.0) * 2.0 * sphi / (3.0 - sphi));
+    m.dp_coef = (float)((dim * lam + 2.0 * mu) / (2.0 * mu));
+    m.dt = dt;
+    m.p_mass = p_mass;
+    m.p_vol0 = p_vol0;
+    m.E = (float)E;
+    m.dalpha_dphi = (float)(sqrt(2.0 / 3.0) * 6.0 * cos(phi) / ((3.0 - sphi) * (3.0 - sphi)) * (M_PI / 180.0));
+    return m;
+}
+
+void fill_material(mpm_ctx* c) {
+    const InstMat m = make_instmat(c->dim, c->prm.E, c->prm.nu, c->prm.friction_deg, c->prm.dt, c->prm.p_mass,
+                                   c->prm.p_vol0);
+    c->P.mu = m.mu;
+    c->P.lam = m.lam;
+    c->P.alpha = m.alpha;
+    c->P.dp_coef = m.dp_coef;
+    c->P.dt = m.dt;
+    c->P.E = m.E;
+    c->P.dalpha_dphi = m.dalpha_dphi;
 }
 
 void fill_params(mpm_ctx* c) {
@@ -173,6 +206,9 @@ void fill_params(mpm_ctx* c) {
     P.grid_bar = c->grid_bar;
     P.adj_scratch = c->adj_scratch;
     P.param_bar = nullptr;
+    P.n_inst = c->n_inst;
+    P.blk_bits = c->blk_bits;
+    P.inst = c->inst;
     fill_material(c);
 }
 
@@ -182,7 +218,8 @@ int alloc_capacity_buffers(mpm_ctx* c) {
     const int NB = 1 << c->dim, NPB = 1 << (2 * c->dim);
     const size_t H = (size_t)1 << c->H_log2;
     const size_t cap = (size_t)c->block_cap;
-    c->work_cap = c->block_cap + c->max_particles / c->chunk + 1;
+    // room for the smallest work-item size mpm_set_tuning accepts
+    c->work_cap = c->block_cap + c->max_particles / MIN_CHUNK + 1;
     int scan_n = std::max({radix_hist_size(c->max_particles), (int)H, c->block_cap, 1});
     hipError_t e = hipSuccess;
     if (!c->dense) {
@@ -219,6 +256,7 @@ int alloc_capacity_buffers(mpm_ctx* c) {
 
 bool particles_ok(const mpm_ctx* c, const mpm_particles* p, bool need_state) {
     if (!p || p->n < 0 || p->n > c->max_particles || !p->x) return false;
+    if (c->n_inst > 1 && !p->inst) return false;
     if (need_state && (!p->v || !p->C || !p->F || !p->tau)) return false;
     return true;
 }
@@ -227,7 +265,7 @@ int hip_status(hipError_t e) { return e == hipSuccess ? MPM_OK : MPM_ERR_HIP; }
 
 int build_once(mpm_ctx* c, const mpm_particles* p, hipStream_t s) {
     const int n = p->n;
-    hipError_t e = launch_bin(c->P, p->x, n, c->k1, s);
+    hipError_t e = launch_bin(c->P, p->x, p->inst, n, c->k1, s);
     if (e != hipSuccess) return MPM_ERR_HIP;
     uint32_t *ko = c->k1, *vo = c->v0;
     if (n > 0) {
@@ -297,6 +335,17 @@ int mpm_create(const mpm_params* q, mpm_ctx** out) {
     if (q->heightmap && (q->flags & MPM_FLAG_ADJOINT)) return MPM_ERR_ARG;
     if (q->bound < 0 || q->block_capacity < 0 || q->hash_capacity_log2 < 0 || q->hash_capacity_log2 > 30)
         return MPM_ERR_ARG;
+    if (q->n_instances < 0 || q->n_instances > MAX_INSTANCES) return MPM_ERR_ARG;
+    const int n_inst = std::max(1, q->n_instances);
+    if (n_inst > 1) {
+        if (!q->instances || q->grid_mode != MPM_GRID_SPARSE || (q->flags & MPM_FLAG_ADJOINT)) return MPM_ERR_ARG;
+        for (int i = 0; i < n_inst; ++i) {
+            const mpm_instance& m = q->instances[i];
+            if (!(m.E > 0.f) || !(m.nu >= 0.f && m.nu < 0.5f) || !(m.dt > 0.f) || !(m.p_mass > 0.f) ||
+                !(m.p_vol0 > 0.f))
+                return MPM_ERR_ARG;
+        }
+    }
     for (int a = 0; a < q->dim; ++a) {
         if (q->cells[a] < 4 || q->cells[a] > (1 << 20)) return MPM_ERR_ARG;
         for (int sd = 0; sd < 2; ++sd)
@@ -316,8 +365,14 @@ int mpm_create(const mpm_params* q, mpm_ctx** out) {
         total *= c->nblk[a];
     }
     c->n_blocks_total = total;
-    c->key_bits = bits_for(total - 1) + 2 * c->dim;
-    if (c->key_bits > 32 || total > (1ll << 30)) {
+    c->n_inst = n_inst;
+    c->blk_bits = bits_for(total - 1);
+    // sort key: instance | linear block | local cell, all in 32 bits
+    c->key_bits = (n_inst > 1 ? bits_for(n_inst - 1) : 0) + c->blk_bits + 2 * c->dim;
+    bool fits = c->key_bits <= 32 && total <= (1ll << 30);
+    if (n_inst > 1)  // ensemble block keys hold 19-bit biased coordinates (block -1 .. nblk)
+        for (int a = 0; a < c->dim; ++a) fits = fits && c->nblk[a] < (int)ENS_KEY_BIAS - 1;
+    if (!fits) {
         delete c;
         return MPM_ERR_ARG;
     }
@@ -338,11 +393,11 @@ int mpm_create(const mpm_params* q, mpm_ctx** out) {
     }
     if (const char* ch = getenv("MPMX_CHUNK")) {
         int v = atoi(ch);
-        if (v >= 32 && v <= 512) c->chunk = v;
+        if (v >= MIN_CHUNK && v <= 512) c->chunk = v;
     }
     if (const char* pw = getenv("MPMX_WGS")) {
         int v = atoi(pw);
-        if (v >= 1 && v <= 1 << 20) c->persistent_wgs = v;
+        if (v >= 1 && v <= 1 << 20) c->p2g_wgs = c->g2p_wgs = v;
     }
     hipError_t e = hipSuccess;
     const size_t np = (size_t)q->max_particles;
@@ -359,6 +414,16 @@ int mpm_create(const mpm_params* q, mpm_ctx** out) {
         if (e == hipSuccess) e = hipMemcpy(c->heightmap, q->heightmap, hn * sizeof(float), hipMemcpyHostToDevice);
     }
     if (e == hipSuccess) e = hipMemset(c->ctr, 0, sizeof(DevCounters));
+    if (e == hipSuccess && n_inst > 1) {
+        InstMat host[MAX_INSTANCES];
+        for (int i = 0; i < n_inst; ++i) {
+            const mpm_instance& m = q->instances[i];
+            host[i] = make_instmat(c->dim, m.E, m.nu, m.friction_deg, m.dt, m.p_mass, m.p_vol0);
+        }
+        e = dalloc(&c->inst, (size_t)n_inst);
+        if (e == hipSuccess) e = hipMemcpy(c->inst, host, n_inst * sizeof(InstMat), hipMemcpyHostToDevice);
+    }
+    c->prm.instances = nullptr;
     if (e != hipSuccess) {
         (void)hipGetLastError();
         free_all(c);
@@ -383,6 +448,8 @@ int mpm_create(const mpm_params* q, mpm_ctx** out) {
 int mpm_destroy(mpm_ctx* c) {
     if (!c) return MPM_ERR_ARG;
     (void)hipDeviceSynchronize();
+    release_graph(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     free_all(c);
     delete c;
     return MPM_OK;
@@ -390,6 +457,7 @@ int mpm_destroy(mpm_ctx* c) {
 
 int mpm_set_material(mpm_ctx* c, float E, float nu, float friction_deg, float dt) {
     if (!c || !(E > 0.f) || !(nu >= 0.f && nu < 0.5f) || !(dt > 0.f)) return MPM_ERR_ARG;
+    if (c->n_inst > 1) return MPM_ERR_STATE;
     c->prm.E = E;
     c->prm.nu = nu;
     c->prm.friction_deg = friction_deg;
@@ -434,7 +502,7 @@ int mpm_p2g(mpm_ctx* c, const mpm_particles* p, void* stream) {
     if (!c || !particles_ok(c, p, true)) return MPM_ERR_ARG;
     if (!c->built || p->n != c->built_n) return MPM_ERR_STATE;
     if (p->n == 0) return MPM_OK;
-    const int wgs = std::min(c->persistent_wgs, c->work_cap);
+    const int wgs = std::min(c->p2g_wgs, c->work_cap);
     return hip_status(launch_p2g(c->P, p->x, p->v, p->C, p->tau, p->n, c->order, c->skeys, wgs, (hipStream_t)stream));
 }
 
@@ -453,11 +521,12 @@ int mpm_g2p(mpm_ctx* c, const mpm_particles* in, const mpm_particles* out, void*
         !in->F || out->n != in->n)
         return MPM_ERR_ARG;
     if (in->x == out->x || in->F == out->F) return MPM_ERR_ARG;
+    if (c->n_inst > 1 && (!out->inst || out->inst == in->inst)) return MPM_ERR_ARG;
     if (!c->built || in->n != c->built_n) return MPM_ERR_STATE;
     if (in->n == 0) return MPM_OK;
-    const int wgs = std::min(c->persistent_wgs, c->work_cap);
-    return hip_status(launch_g2p(c->P, in->x, in->F, in->id, out->x, out->v, out->C, out->F, out->tau, out->id, in->n,
-                                 c->order, wgs, (hipStream_t)stream));
+    const int wgs = std::min(c->g2p_wgs, c->work_cap);
+    return hip_status(launch_g2p(c->P, in->x, in->F, in->id, in->inst, out->x, out->v, out->C, out->F, out->tau,
+                                 out->id, out->inst, in->n, c->order, wgs, (hipStream_t)stream));
 }
 
 int mpm_step(mpm_ctx* c, const mpm_particles* a, const mpm_particles* b, int n_steps, void* stream) {
@@ -485,7 +554,7 @@ int mpm_g2p_adj(mpm_ctx* c, const mpm_particles* in, const mpm_particles* ob, co
     DevParams P = c->P;
     P.param_bar = param_bar;
     const float* obp[5] = {ob->x, ob->v, ob->C, ob->F, ob->tau};
-    const int wgs = std::min(c->persistent_wgs, c->work_cap);
+    const int wgs = std::min(c->g2p_wgs, c->work_cap);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_g2p_adj(P, in->x, in->F, obp, ib->x, ib->F, in->n, c->order, wgs, s);
     if (e == hipSuccess) e = launch_scatter_adj(P, in->x, in->n, c->order, c->skeys, wgs, s);
@@ -508,7 +577,7 @@ int mpm_p2g_adj(mpm_ctx* c, const mpm_particles* in, const mpm_particles* ib, vo
     if (in->n == 0) return MPM_OK;
     const float* inp[4] = {in->x, in->v, in->C, in->tau};
     float* ibp[4] = {ib->x, ib->v, ib->C, ib->tau};
-    const int wgs = std::min(c->persistent_wgs, c->work_cap);
+    const int wgs = std::min(c->g2p_wgs, c->work_cap);
     return hip_status(launch_p2g_adj(c->P, inp, ibp, in->n, c->order, wgs, (hipStream_t)stream));
 }
 
@@ -572,6 +641,122 @@ int mpm_get_order(mpm_ctx* c, uint32_t* order, int n, void* stream) {
     if (n == 0) return MPM_OK;
     return hip_status(
         hipMemcpyAsync(order, c->order, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, (hipStream_t)stream));
+}
+
+int mpm_graph_release(mpm_ctx* c) {
+    if (!c) return MPM_ERR_ARG;
+    release_graph(c);
+    return MPM_OK;
+}
+
+int mpm_graph_capture(mpm_ctx* c, const mpm_particles* a, const mpm_particles* b, int n_steps, void* stream) {
+    if (!c || !a || !b || n_steps < 2 || (n_steps & 1)) return MPM_ERR_ARG;
+    if (c->prm.flags & MPM_FLAG_SYNC_REBUILD) return MPM_ERR_STATE;
+    release_graph(c);
+    // Record on a private stream (the caller's may be the legacy default
+    // stream, which cannot be captured); the graph is replayed on the
+    // caller's stream.  Work already queued on `stream` is waited for first.
+    if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return MPM_ERR_HIP;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return MPM_ERR_HIP;
+    if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return MPM_ERR_HIP;
+    const int st = mpm_step(c, a, b, n_steps, c->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (st != MPM_OK || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return st != MPM_OK ? st : MPM_ERR_HIP;
+    }
+    c->graph = g;
+    if (hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        c->graph_exec = nullptr;
+        release_graph(c);
+        return MPM_ERR_HIP;
+    }
+    return MPM_OK;
+}
+
+int mpm_graph_launch(mpm_ctx* c, int times, void* stream) {
+    if (!c || times < 0) return MPM_ERR_ARG;
+    if (!c->graph_exec) return MPM_ERR_STATE;
+    for (int i = 0; i < times; ++i)
+        if (hipGraphLaunch(c->graph_exec, (hipStream_t)stream) != hipSuccess) return MPM_ERR_HIP;
+    return MPM_OK;
+}
+
+int mpm_set_tuning(mpm_ctx* c, int chunk, int p2g_workgroups, int g2p_workgroups) {
+    if (!c) return MPM_ERR_ARG;
+    if (chunk != 0 && (chunk < MIN_CHUNK || chunk > 512)) return MPM_ERR_ARG;
+    if (p2g_workgroups < 0 || p2g_workgroups > (1 << 20) || g2p_workgroups < 0 || g2p_workgroups > (1 << 20))
+        return MPM_ERR_ARG;
+    if (chunk) {
+        c->chunk = chunk;
+        c->P.chunk = chunk;
+        c->built = false;  // work items of the last build used the old size
+    }
+    if (p2g_workgroups) c->p2g_wgs = p2g_workgroups;
+    if (g2p_workgroups) c->g2p_wgs = g2p_workgroups;
+    return MPM_OK;
+}
+
+int mpm_autotune(mpm_ctx* c, const mpm_particles* a, const mpm_particles* b, int* chosen, void* stream) {
+    if (!c || !particles_ok(c, a, true) || !b || b->n != a->n) return MPM_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    static const int chunks[] = {128, 256, 512};
+    static const int wgs[] = {1024, 2048, 4096, 8192};
+    constexpr int NC = 3, NW = 4, REPS = 3;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    int st = MPM_OK;
+    for (int i = 0; i < 4 && st == MPM_OK; ++i)
+        if (hipEventCreate(&ev[i]) != hipSuccess) st = MPM_ERR_HIP;
+    double p2g_ms[NW] = {0}, g2p_ms[NC][NW] = {{0}};
+    // Every trial reads a and writes b, so a is left as it was.  P2G does not
+    // depend on the work-item size: its time per workgroup count is summed
+    // over the work-item sizes.
+    for (int ci = 0; ci < NC && st == MPM_OK; ++ci) {
+        for (int wi = 0; wi < NW && st == MPM_OK; ++wi) {
+            c->chunk = c->P.chunk = chunks[ci];
+            c->p2g_wgs = c->g2p_wgs = wgs[wi];
+            for (int r = 0; r <= REPS && st == MPM_OK; ++r) {
+                st = mpm_sparse_build(c, a, s);
+                if (st == MPM_OK && hipEventRecord(ev[0], s) != hipSuccess) st = MPM_ERR_HIP;
+                if (st == MPM_OK) st = mpm_p2g(c, a, s);
+                if (st == MPM_OK && hipEventRecord(ev[1], s) != hipSuccess) st = MPM_ERR_HIP;
+                if (st == MPM_OK) st = mpm_grid_update(c, s);
+                if (st == MPM_OK && hipEventRecord(ev[2], s) != hipSuccess) st = MPM_ERR_HIP;
+                if (st == MPM_OK) st = mpm_g2p(c, a, b, s);
+                if (st == MPM_OK && hipEventRecord(ev[3], s) != hipSuccess) st = MPM_ERR_HIP;
+                if (st == MPM_OK && hipEventSynchronize(ev[3]) != hipSuccess) st = MPM_ERR_HIP;
+                if (st != MPM_OK || r == 0) continue;  // the first repetition warms up
+                float t_p2g = 0.f, t_g2p = 0.f;
+                if (hipEventElapsedTime(&t_p2g, ev[0], ev[1]) != hipSuccess ||
+                    hipEventElapsedTime(&t_g2p, ev[2], ev[3]) != hipSuccess)
+                    st = MPM_ERR_HIP;
+                p2g_ms[wi] += t_p2g;
+                g2p_ms[ci][wi] += t_g2p;
+            }
+        }
+    }
+    for (int i = 0; i < 4; ++i)
+        if (ev[i]) (void)hipEventDestroy(ev[i]);
+    if (st != MPM_OK) return st;
+    int best_p2g = 0, best_c = 0, best_w = 0;
+    for (int wi = 1; wi < NW; ++wi)
+        if (p2g_ms[wi] < p2g_ms[best_p2g]) best_p2g = wi;
+    for (int ci = 0; ci < NC; ++ci)
+        for (int wi = 0; wi < NW; ++wi)
+            if (g2p_ms[ci][wi] < g2p_ms[best_c][best_w]) best_c = ci, best_w = wi;
+    c->chunk = c->P.chunk = chunks[best_c];
+    c->p2g_wgs = wgs[best_p2g];
+    c->g2p_wgs = wgs[best_w];
+    c->built = false;
+    if (chosen) {
+        chosen[0] = c->chunk;
+        chosen[1] = c->p2g_wgs;
+        chosen[2] = c->g2p_wgs;
+    }
+    return MPM_OK;
 }
 
 }  // extern "C"

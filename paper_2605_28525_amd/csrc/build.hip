@@ -27,12 +27,20 @@
 namespace mpmx {
 
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_bin(DevParams P, const float* __restrict__ x, int n,
-                                            uint32_t* __restrict__ keys) {
+__global__ __launch_bounds__(WG) void k_bin(DevParams P, const float* __restrict__ x,
+                                            const uint32_t* __restrict__ inst, int n, uint32_t* __restrict__ keys) {
     const int i = blockIdx.x * WG + threadIdx.x;
     if (i >= n) return;
     int b[3] = {0, 0, 0};
     unsigned bad = 0;
+    uint32_t in = 0;
+    if (P.n_inst > 1 && inst) {
+        in = inst[i];
+        if (in >= (uint32_t)P.n_inst) {
+            bad |= MPM_FLAG_DOMAIN;
+            in = (uint32_t)P.n_inst - 1;
+        }
+    }
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         double f = floor(index_arg(x[(size_t)a * n + i], P.inv_dx));
@@ -55,7 +63,7 @@ __global__ __launch_bounds__(WG) void k_bin(DevParams P, const float* __restrict
         bl = (uint32_t)(b[1] >> 2) * (uint32_t)P.nblk[0] + (uint32_t)(b[0] >> 2);
         cell = (b[0] & 3) | ((b[1] & 3) << 2);
     }
-    keys[i] = (bl << (2 * DIM)) | cell;
+    keys[i] = (in << (P.blk_bits + 2 * DIM)) | (bl << (2 * DIM)) | cell;
 }
 
 __device__ int hash_insert(const DevParams& P, uint64_t K) {
@@ -115,7 +123,9 @@ __global__ __launch_bounds__(WG) void k_hash_insert(DevParams P, const uint32_t*
     const int lane = __lane_id();
     const bool valid = i < n;
     const uint32_t key = valid ? skeys[i] : 0u;
-    const uint32_t bl = key >> CB;
+    const uint32_t seg = key >> CB;                                   // instance and block
+    const uint32_t bl = seg & ((1u << P.blk_bits) - 1u);              // block within the instance
+    const int inst = (int)(seg >> P.blk_bits);
     int l[3] = {(int)(key & 3u), (int)((key >> 2) & 3u), DIM == 3 ? (int)((key >> 4) & 3u) : 0};
     int bc[3];
     linear_to_block<DIM>(P, bl, bc);
@@ -140,9 +150,9 @@ __global__ __launch_bounds__(WG) void k_hash_insert(DevParams P, const uint32_t*
         }
         if (!valid) m[d] = 0ull;
     }
-    const uint64_t ko = pack_key<DIM>(bc[0], bc[1], bc[2]);
-    const bool is_start = valid && (i == 0 || (skeys[i - 1] >> CB) != bl);
-    const bool is_end = valid && (i == n - 1 || (skeys[i + 1] >> CB) != bl);
+    const uint64_t ko = block_key<DIM>(P, bc[0], bc[1], bc[2], inst);
+    const bool is_start = valid && (i == 0 || (skeys[i - 1] >> CB) != seg);
+    const bool is_end = valid && (i == n - 1 || (skeys[i + 1] >> CB) != seg);
 
     unsigned long long todo = __ballot(valid);
     while (todo) {
@@ -151,6 +161,7 @@ __global__ __launch_bounds__(WG) void k_hash_insert(DevParams P, const uint32_t*
         const bool mine = valid && ko == K;
         const unsigned long long grp = __ballot(mine);
         const int lbx = readlane32(bc[0], leader), lby = readlane32(bc[1], leader), lbz = readlane32(bc[2], leader);
+        const int lin = readlane32(inst, leader);
         uint64_t mymask = 0ull;
 #pragma unroll
         for (int d = 0; d < NB; ++d) {
@@ -162,7 +173,7 @@ __global__ __launch_bounds__(WG) void k_hash_insert(DevParams P, const uint32_t*
         }
         int slot = -1;
         if (lane < NB && mymask != 0ull) {
-            const uint64_t Kd = pack_key<DIM>(lbx + (lane & 1), lby + ((lane >> 1) & 1), lbz + ((lane >> 2) & 1));
+            const uint64_t Kd = block_key<DIM>(P, lbx + (lane & 1), lby + ((lane >> 1) & 1), lbz + ((lane >> 2) & 1), lin);
             slot = hash_insert(P, Kd);
             if (slot >= 0) atomicOr((unsigned long long*)&P.h_mask[slot], (unsigned long long)mymask);
         }
@@ -229,13 +240,13 @@ __global__ __launch_bounds__(WG) void k_block_setup(DevParams P) {
     constexpr int NB = 1 << DIM;
     const int nb = P.ctr->nb;
     for (int b = blockIdx.x * WG + threadIdx.x; b < nb; b += gridDim.x * WG) {
-        int bc[3];
-        unpack_key<DIM>(P.b_keys[b], bc);
+        int bc[3], inst;
+        unblock_key<DIM>(P, P.b_keys[b], bc, &inst);
         P.b_nbr[b * NB] = b;
 #pragma unroll
         for (int d = 1; d < NB; ++d)
-            P.b_nbr[b * NB + d] = hash_lookup(P, pack_key<DIM>(bc[0] + (d & 1), bc[1] + ((d >> 1) & 1),
-                                                                bc[2] + ((d >> 2) & 1)));
+            P.b_nbr[b * NB + d] = hash_lookup(P, block_key<DIM>(P, bc[0] + (d & 1), bc[1] + ((d >> 1) & 1),
+                                                                 bc[2] + ((d >> 2) & 1), inst));
         P.b_chunks[b] = (unsigned)((P.b_count[b] + P.chunk - 1) / P.chunk);
     }
 }
@@ -327,12 +338,12 @@ static int grid_for(long long items, int cap_wgs = 8192) {
     return (int)g;
 }
 
-hipError_t launch_bin(const DevParams& P, const float* x, int n, uint32_t* keys, hipStream_t s) {
+hipError_t launch_bin(const DevParams& P, const float* x, const uint32_t* inst, int n, uint32_t* keys, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (P.dim == 3)
-        k_bin<3><<<(n + WG - 1) / WG, WG, 0, s>>>(P, x, n, keys);
+        k_bin<3><<<(n + WG - 1) / WG, WG, 0, s>>>(P, x, inst, n, keys);
     else
-        k_bin<2><<<(n + WG - 1) / WG, WG, 0, s>>>(P, x, n, keys);
+        k_bin<2><<<(n + WG - 1) / WG, WG, 0, s>>>(P, x, inst, n, keys);
     return hipGetLastError();
 }
 

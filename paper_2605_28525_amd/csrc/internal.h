@@ -31,6 +31,7 @@ constexpr int SORT_ITEMS = 16;                 // keys per thread per radix tile
 constexpr int SORT_TILE = WG * SORT_ITEMS;     // 4096 keys per tile
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = WG * SCAN_ITEMS;     // 2048 values per scan tile
+constexpr int MIN_CHUNK = 64;                  // smallest particles-per-work-item setting
 
 struct DevCounters {
     int nb;          // active blocks (compact count, <= capacity)
@@ -39,6 +40,18 @@ struct DevCounters {
     unsigned flags;  // sticky MPM_FLAG_* bits
     int pad[4];
 };
+
+// Per-instance material and step constants (one entry for a single simulation).
+struct InstMat {
+    float mu, lam, alpha, dp_coef;
+    float dt, p_mass, p_vol0, E;
+    float dalpha_dphi, pad[3];
+};
+
+constexpr int MAX_INSTANCES = 64;
+constexpr int ENS_KEY_M = 19;                 // ensemble block keys: bits per coordinate
+constexpr int64_t ENS_KEY_BIAS = 1 << 18;
+constexpr int ENS_INST_SHIFT = 57;            // instance id in bits 57..62
 
 struct DevParams {
     int dim;
@@ -89,6 +102,10 @@ struct DevParams {
     float* param_bar;    // accumulated dL/dE, dL/dphi (per degree)
     float E;
     float dalpha_dphi;   // d alpha / d phi, per degree
+    // ensembles
+    int n_inst;          // 1 = single simulation
+    int blk_bits;        // bits of the linear block id inside the sort key
+    const InstMat* inst; // device table, n_inst entries
 };
 
 // ---------------------------------------------------------------------------
@@ -124,6 +141,39 @@ __device__ __forceinline__ void unpack_key(uint64_t k, int* b) {
     }
 }
 
+// Block key with the instance folded in.  A single simulation uses Eq. 22
+// as printed (m = 21, bias 2^20); an ensemble uses m = 19 (bias 2^18) and puts
+// the instance id in bits 57-62, which keeps 3m + 6 <= 63.
+template <int DIM>
+__device__ __forceinline__ uint64_t block_key(const DevParams& P, int bx, int by, int bz, int inst) {
+    if (P.n_inst <= 1) return pack_key<DIM>(bx, by, bz);
+    const uint64_t ib = (uint64_t)inst << ENS_INST_SHIFT;
+    if (DIM == 3)
+        return ib | ((uint64_t)(bx + ENS_KEY_BIAS) << (2 * ENS_KEY_M)) | ((uint64_t)(by + ENS_KEY_BIAS) << ENS_KEY_M) |
+               (uint64_t)(bz + ENS_KEY_BIAS);
+    return ib | ((uint64_t)(bx + ENS_KEY_BIAS) << ENS_KEY_M) | (uint64_t)(by + ENS_KEY_BIAS);
+}
+
+template <int DIM>
+__device__ __forceinline__ void unblock_key(const DevParams& P, uint64_t k, int* b, int* inst) {
+    if (P.n_inst <= 1) {
+        unpack_key<DIM>(k, b);
+        *inst = 0;
+        return;
+    }
+    const uint64_t m = (1ull << ENS_KEY_M) - 1;
+    *inst = (int)((k >> ENS_INST_SHIFT) & 63u);
+    if (DIM == 3) {
+        b[0] = (int)((k >> (2 * ENS_KEY_M)) & m) - (int)ENS_KEY_BIAS;
+        b[1] = (int)((k >> ENS_KEY_M) & m) - (int)ENS_KEY_BIAS;
+        b[2] = (int)(k & m) - (int)ENS_KEY_BIAS;
+    } else {
+        b[0] = (int)((k >> ENS_KEY_M) & m) - (int)ENS_KEY_BIAS;
+        b[1] = (int)(k & m) - (int)ENS_KEY_BIAS;
+        b[2] = 0;
+    }
+}
+
 // Base node floor(x * (1/dx) - 1/2) in float64, multiply and subtract rounded
 // separately (no contraction), and the fractional offset s - floor(s).
 __device__ __forceinline__ double index_arg(float x, double inv_dx) {
@@ -145,14 +195,32 @@ __device__ __forceinline__ void linear_to_block(const DevParams& P, uint32_t bl,
     }
 }
 
-// Block coordinates of compact block b (sparse: from its packed key; dense: b is
-// the linear block index).
+// Block coordinates (and instance) of compact block b (sparse: from its packed
+// key; dense: b is the linear block index).
 template <int DIM>
-__device__ __forceinline__ void block_coords(const DevParams& P, int b, int* bc) {
+__device__ __forceinline__ void block_coords(const DevParams& P, int b, int* bc, int* inst = nullptr) {
+    int i = 0;
     if (P.dense)
         linear_to_block<DIM>(P, (uint32_t)b, bc);
     else
-        unpack_key<DIM>(P.b_keys[b], bc);
+        unblock_key<DIM>(P, P.b_keys[b], bc, &i);
+    if (inst) *inst = i;
+}
+
+// Material of an instance (a single simulation reads the scalar fields).
+__device__ __forceinline__ InstMat material(const DevParams& P, int inst) {
+    if (P.n_inst > 1) return P.inst[inst];
+    InstMat m;
+    m.mu = P.mu;
+    m.lam = P.lam;
+    m.alpha = P.alpha;
+    m.dp_coef = P.dp_coef;
+    m.dt = P.dt;
+    m.p_mass = P.p_mass;
+    m.p_vol0 = P.p_vol0;
+    m.E = P.E;
+    m.dalpha_dphi = P.dalpha_dphi;
+    return m;
 }
 
 __device__ __forceinline__ unsigned long long wave_ballot(bool p) { return __ballot(p); }
@@ -214,7 +282,7 @@ hipError_t radix_sort(const uint32_t* keys_in, uint32_t* k0, uint32_t* k1, uint3
                       hipStream_t s);
 int radix_hist_size(int n);
 
-hipError_t launch_bin(const DevParams& P, const float* x, int n, uint32_t* keys, hipStream_t s);
+hipError_t launch_bin(const DevParams& P, const float* x, const uint32_t* inst, int n, uint32_t* keys, hipStream_t s);
 hipError_t launch_build_sparse(const DevParams& P, const uint32_t* skeys, int n, unsigned H, unsigned* partials,
                                hipStream_t s);
 hipError_t launch_build_dense(const DevParams& P, const uint32_t* skeys, int n, int n_blocks, unsigned* partials,
@@ -222,9 +290,10 @@ hipError_t launch_build_dense(const DevParams& P, const uint32_t* skeys, int n, 
 hipError_t launch_p2g(const DevParams& P, const float* x, const float* v, const float* C, const float* tau, int n,
                       const uint32_t* order, const uint32_t* skeys, int grid_blocks, hipStream_t s);
 hipError_t launch_grid_update(const DevParams& P, long long n_nodes_host, int grid_blocks, hipStream_t s);
-hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, const uint32_t* id_in, float* x_out,
-                      float* v_out, float* C_out, float* F_out, float* tau_out, uint32_t* id_out, int n,
-                      const uint32_t* order, int grid_blocks, hipStream_t s);
+hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, const uint32_t* id_in,
+                      const uint32_t* inst_in, float* x_out, float* v_out, float* C_out, float* F_out, float* tau_out,
+                      uint32_t* id_out, uint32_t* inst_out, int n, const uint32_t* order, int grid_blocks,
+                      hipStream_t s);
 hipError_t launch_clear_flags(DevCounters* c, hipStream_t s);
 hipError_t launch_g2p_adj(const DevParams& P, const float* x, const float* F, const float* const* out_bar, float* x_bar,
                           float* F_bar, int n, const uint32_t* order, int grid_blocks, hipStream_t s);

@@ -47,8 +47,6 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
     __shared__ uint32_t ord[P2G_ORDER_STAGE];
     const int lane = threadIdx.x;
     const int nb = min(P.ctr->nb, P.block_cap);
-    const float mp = P.p_mass;
-    const float dtv = P.dt * P.p_vol0;
     const float dx = P.dxf, inv_dx = P.inv_dxf;
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
         const int cnt = P.b_count[b];
@@ -56,8 +54,11 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
         const int st = P.b_start[b], en = st + cnt;
         for (int t = lane; t < 4 * T::N; t += 64) (&tile[0][0])[t] = 0.f;
         for (int c = lane; c < NC; c += 64) cs[c] = ce[c] = 0;
-        int bc[3];
-        block_coords<DIM>(P, b, bc);
+        int bc[3], inst;
+        block_coords<DIM>(P, b, bc, &inst);
+        const InstMat mat = material(P, inst);
+        const float mp = mat.p_mass;
+        const float dtv = mat.dt * mat.p_vol0;
         const int org[3] = {bc[0] * BLK, bc[1] * BLK, bc[2] * BLK};
         __syncthreads();
         for (int i = st + lane; i < en; i += 64) {
@@ -257,13 +258,14 @@ __global__ __launch_bounds__(WG) void k_grid_update(DevParams P, long long n_nod
         const float m = gv.w;
         float vel[3] = {0.f, 0.f, 0.f};
         if (m > 0.f) {
-            vel[0] = gv.x / m + P.dt * P.g[0];
-            vel[1] = gv.y / m + P.dt * P.g[1];
-            if (DIM == 3) vel[2] = gv.z / m + P.dt * P.g[2];
-            if (P.grid_u) P.grid_u[s] = make_float4(vel[0], vel[1], vel[2], m);
             const int b = (int)(s / NPB), l = (int)(s % NPB);
-            int bc[3];
-            block_coords<DIM>(P, b, bc);
+            int bc[3], inst;
+            block_coords<DIM>(P, b, bc, &inst);
+            const float dtn = P.n_inst > 1 ? P.inst[inst].dt : P.dt;
+            vel[0] = gv.x / m + dtn * P.g[0];
+            vel[1] = gv.y / m + dtn * P.g[1];
+            if (DIM == 3) vel[2] = gv.z / m + dtn * P.g[2];
+            if (P.grid_u) P.grid_u[s] = make_float4(vel[0], vel[1], vel[2], m);
             int node[3] = {bc[0] * BLK + (l & 3), bc[1] * BLK + ((l >> 2) & 3), DIM == 3 ? bc[2] * BLK + (l >> 4) : 0};
             if (DIM == 3 && P.has_terrain && node[0] <= P.cells[0] && node[1] <= P.cells[1])
                 terrain_bc<DIM>(P, node[0], node[1], node[2], vel);
@@ -291,7 +293,7 @@ __global__ __launch_bounds__(WG) void k_grid_update(DevParams P, long long n_nod
 }
 
 template <int DIM>
-__device__ __forceinline__ unsigned constitutive(const DevParams& P, const float (*Ft)[3], float (*Fn)[3],
+__device__ __forceinline__ unsigned constitutive(int model, const InstMat& P, const float (*Ft)[3], float (*Fn)[3],
                                                  float* tau6) {
     unsigned flags = 0;
     float det;
@@ -330,7 +332,7 @@ __device__ __forceinline__ unsigned constitutive(const DevParams& P, const float
     bool plastic = false;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) e2[a] = eps[a];
-    if (P.model == MPM_MODEL_DP) {
+    if (model == MPM_MODEL_DP) {
         if (tr > 0.f) {
 #pragma unroll
             for (int a = 0; a < DIM; ++a) e2[a] = 0.f;
@@ -405,6 +407,7 @@ struct G2PIn {
     const float* x;
     const float* F;
     const uint32_t* id;
+    const uint32_t* inst;
 };
 struct G2POut {
     float* x;
@@ -413,6 +416,7 @@ struct G2POut {
     float* F;
     float* tau;
     uint32_t* id;
+    uint32_t* inst;
 };
 
 template <int DIM>
@@ -425,20 +429,21 @@ __global__ __launch_bounds__(WG) void k_g2p(DevParams P, G2PIn in, G2POut out, i
     __shared__ float xs[DIM][G2P_MAX_ITEM];
     __shared__ float fs[DD][G2P_MAX_ITEM];
     __shared__ int nbr[T::NB];
-    __shared__ int org[3];
+    __shared__ int org[4];
     const int n_work = min(P.ctr->n_work, P.work_cap);
-    const float dt = P.dt, dx = P.dxf, inv_dx = P.inv_dxf;
+    const float dx = P.dxf, inv_dx = P.inv_dxf;
     const float cscale = 4.f * inv_dx * inv_dx;  // D_p^{-1} = (4/dx^2) I for quadratic B-splines
     for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
         const int blk = P.w_block[w], s = P.w_start[w];
         const int L = min(P.w_end[w] - s, G2P_MAX_ITEM);
         if (threadIdx.x < T::NB) nbr[threadIdx.x] = P.b_nbr[blk * T::NB + threadIdx.x];
         if (threadIdx.x == 0) {
-            int bc[3];
-            block_coords<DIM>(P, blk, bc);
+            int bc[3], inst;
+            block_coords<DIM>(P, blk, bc, &inst);
             org[0] = bc[0] * BLK;
             org[1] = bc[1] * BLK;
             org[2] = bc[2] * BLK;
+            org[3] = inst;
         }
         // phase 0: issue every global gather of the work item up front
         // (positions, deformation gradients, ids) and stage them in LDS
@@ -450,8 +455,11 @@ __global__ __launch_bounds__(WG) void k_g2p(DevParams P, G2PIn in, G2POut out, i
 #pragma unroll
             for (int k = 0; k < DD; ++k) fs[k][r] = in.F[(size_t)k * n + q];
             if (out.id) out.id[s + r] = in.id ? in.id[q] : (uint32_t)q;
+            if (out.inst) out.inst[s + r] = in.inst ? in.inst[q] : 0u;
         }
         __syncthreads();
+        const InstMat mat = material(P, org[3]);
+        const float dt = mat.dt;
         for (int t = threadIdx.x; t < T::N; t += WG) {
             const int I = t % T::E, J = (t / T::E) % T::E, K = DIM == 3 ? t / (T::E * T::E) : 0;
             const int d = (I >> 2) | ((J >> 2) << 1) | ((K >> 2) << 2);
@@ -564,7 +572,7 @@ __global__ __launch_bounds__(WG) void k_g2p(DevParams P, G2PIn in, G2POut out, i
             for (int a = 0; a < DIM; ++a)
 #pragma unroll
                 for (int b = 0; b < DIM; ++b) Ft[a][b] = fs[a * DIM + b][r];
-            unsigned flags = constitutive<DIM>(P, Ft, Fn, tau6);
+            unsigned flags = constitutive<DIM>(P.model, mat, Ft, Fn, tau6);
             bool finite = true;
 #pragma unroll
             for (int a = 0; a < DIM; ++a)
@@ -600,11 +608,12 @@ hipError_t launch_grid_update(const DevParams& P, long long n_nodes_host, int gr
     return hipGetLastError();
 }
 
-hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, const uint32_t* id_in, float* x_out,
-                      float* v_out, float* C_out, float* F_out, float* tau_out, uint32_t* id_out, int n,
-                      const uint32_t* order, int grid_blocks, hipStream_t s) {
-    G2PIn in{x_in, F_in, id_in};
-    G2POut out{x_out, v_out, C_out, F_out, tau_out, id_out};
+hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, const uint32_t* id_in,
+                      const uint32_t* inst_in, float* x_out, float* v_out, float* C_out, float* F_out, float* tau_out,
+                      uint32_t* id_out, uint32_t* inst_out, int n, const uint32_t* order, int grid_blocks,
+                      hipStream_t s) {
+    G2PIn in{x_in, F_in, id_in, inst_in};
+    G2POut out{x_out, v_out, C_out, F_out, tau_out, id_out, inst_out};
     if (P.dim == 3)
         k_g2p<3><<<grid_blocks, WG, 0, s>>>(P, in, out, n, order);
     else

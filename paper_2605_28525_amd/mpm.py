@@ -25,6 +25,17 @@ MPM_FLAG_SYNC_REBUILD = 1
 MPM_FLAG_ADJOINT = 2
 
 
+class mpm_instance(ctypes.Structure):
+    _fields_ = [
+        ("E", c_float),
+        ("nu", c_float),
+        ("friction_deg", c_float),
+        ("dt", c_float),
+        ("p_mass", c_float),
+        ("p_vol0", c_float),
+    ]
+
+
 class mpm_params(ctypes.Structure):
     _fields_ = [
         ("dim", c_int),
@@ -47,6 +58,8 @@ class mpm_params(ctypes.Structure):
         ("hash_capacity_log2", c_int),
         ("grid_mode", c_int),
         ("flags", c_int),
+        ("n_instances", c_int),
+        ("instances", POINTER(mpm_instance)),
     ]
 
 
@@ -59,6 +72,7 @@ class mpm_particles(ctypes.Structure):
         ("F", c_void_p),
         ("tau", c_void_p),
         ("id", c_void_p),
+        ("inst", c_void_p),
     ]
 
 
@@ -85,6 +99,11 @@ _SIGS = {
     "mpm_p2g_adj": (c_int, [_PCTX, POINTER(mpm_particles), POINTER(mpm_particles), c_void_p]),
     "mpm_step_adj": (c_int, [_PCTX, POINTER(mpm_particles), POINTER(mpm_particles), POINTER(mpm_particles),
                              c_void_p, c_void_p]),
+    "mpm_graph_capture": (c_int, [_PCTX, POINTER(mpm_particles), POINTER(mpm_particles), c_int, c_void_p]),
+    "mpm_graph_launch": (c_int, [_PCTX, c_int, c_void_p]),
+    "mpm_graph_release": (c_int, [_PCTX]),
+    "mpm_set_tuning": (c_int, [_PCTX, c_int, c_int, c_int]),
+    "mpm_autotune": (c_int, [_PCTX, POINTER(mpm_particles), POINTER(mpm_particles), POINTER(c_int), c_void_p]),
 }
 
 
@@ -208,6 +227,30 @@ def mpm_step_adj(ctx, pin: mpm_particles, out_bar: mpm_particles, in_bar: mpm_pa
                             c_void_p(param_bar.data_ptr()), _stream(stream)), "mpm_step_adj")
 
 
+def mpm_graph_capture(ctx, a: mpm_particles, b: mpm_particles, n_steps: int, stream=None):
+    _check(lib.mpm_graph_capture(ctx, ctypes.byref(a), ctypes.byref(b), int(n_steps), _stream(stream)),
+           "mpm_graph_capture")
+
+
+def mpm_graph_launch(ctx, times: int = 1, stream=None):
+    _check(lib.mpm_graph_launch(ctx, int(times), _stream(stream)), "mpm_graph_launch")
+
+
+def mpm_graph_release(ctx):
+    _check(lib.mpm_graph_release(ctx), "mpm_graph_release")
+
+
+def mpm_set_tuning(ctx, chunk: int = 0, p2g_workgroups: int = 0, g2p_workgroups: int = 0):
+    _check(lib.mpm_set_tuning(ctx, int(chunk), int(p2g_workgroups), int(g2p_workgroups)), "mpm_set_tuning")
+
+
+def mpm_autotune(ctx, a: mpm_particles, b: mpm_particles, stream=None):
+    """Returns the chosen (chunk, p2g_workgroups, g2p_workgroups)."""
+    out = (c_int * 3)()
+    _check(lib.mpm_autotune(ctx, ctypes.byref(a), ctypes.byref(b), out, _stream(stream)), "mpm_autotune")
+    return tuple(int(v) for v in out)
+
+
 # ---------------------------------------------------------------------------
 # marshalling helpers
 def params_from_workload(w, *, max_particles=None, grid_mode=MPM_GRID_SPARSE, block_capacity=0,
@@ -237,16 +280,35 @@ def params_from_workload(w, *, max_particles=None, grid_mode=MPM_GRID_SPARSE, bl
     p.hash_capacity_log2 = int(hash_capacity_log2)
     p.grid_mode = int(grid_mode)
     p.flags = int(flags)
+    p.n_instances = 0
+    return p
+
+
+def params_from_ensemble(ens, *, max_particles=None, block_capacity=0, hash_capacity_log2=0, flags=0):
+    """``mpm_params`` of an ensemble: the shared grid, walls and model from its
+    first member, one ``mpm_instance`` per member.  The returned object keeps
+    the instance table alive until mpm_create has copied it."""
+    m0 = ens.members[0]
+    p = params_from_workload(m0, max_particles=max_particles or ens.n, block_capacity=block_capacity,
+                             hash_capacity_log2=hash_capacity_log2, flags=flags)
+    table = (mpm_instance * len(ens.members))()
+    for i, m in enumerate(ens.members):
+        table[i] = mpm_instance(float(m.E), float(m.nu), float(m.friction_deg), float(m.dt), float(m.p_mass),
+                                float(m.p_vol0))
+    p._inst_keepalive = table
+    p.n_instances = len(ens.members)
+    p.instances = ctypes.cast(table, POINTER(mpm_instance))
     return p
 
 
 class ParticleSet:
     """Device SoA particle state as torch tensors plus its ``mpm_particles`` view."""
 
-    def __init__(self, dim: int, n: int, device="cuda"):
+    def __init__(self, dim: int, n: int, device="cuda", with_inst: bool = False):
         import torch
         d = dim
         self.dim, self.n = dim, n
+        self.inst = torch.zeros((n,), dtype=torch.int32, device=device) if with_inst else None
         self.x = torch.zeros((d, n), dtype=torch.float32, device=device)
         self.v = torch.zeros((d, n), dtype=torch.float32, device=device)
         self.C = torch.zeros((d * d, n), dtype=torch.float32, device=device)
@@ -255,20 +317,26 @@ class ParticleSet:
         self.id = torch.zeros((n,), dtype=torch.int32, device=device)
 
     @classmethod
-    def from_arrays(cls, st: dict, ids=None, device="cuda"):
+    def from_arrays(cls, st: dict, ids=None, device="cuda", inst=None):
         import torch
         d, n = st["x"].shape
-        ps = cls(d, n, device)
+        ps = cls(d, n, device, with_inst=inst is not None)
         for k in ("x", "v", "C", "F", "tau"):
             getattr(ps, k).copy_(torch.from_numpy(np.ascontiguousarray(st[k], dtype=np.float32)))
         ids = np.arange(n, dtype=np.int32) if ids is None else np.asarray(ids, dtype=np.int32)
         ps.id.copy_(torch.from_numpy(ids))
+        if inst is not None:
+            ps.inst.copy_(torch.from_numpy(np.asarray(inst).astype(np.int32)))
         return ps
 
     def copy_(self, other: "ParticleSet"):
-        for k in ("x", "v", "C", "F", "tau", "id"):
-            getattr(self, k).copy_(getattr(other, k))
+        for k in ("x", "v", "C", "F", "tau", "id", "inst"):
+            if getattr(self, k) is not None:
+                getattr(self, k).copy_(getattr(other, k))
         return self
+
+    def insts(self) -> np.ndarray:
+        return self.inst.detach().cpu().numpy().view(np.uint32)
 
     def zero_(self):
         for k in ("x", "v", "C", "F", "tau"):
@@ -286,6 +354,7 @@ class ParticleSet:
         p.n = self.n
         p.x, p.v, p.C = self.x.data_ptr(), self.v.data_ptr(), self.C.data_ptr()
         p.F, p.tau, p.id = self.F.data_ptr(), self.tau.data_ptr(), self.id.data_ptr()
+        p.inst = self.inst.data_ptr() if self.inst is not None else None
         return p
 
 
@@ -295,11 +364,18 @@ class Simulation:
     def __init__(self, w, *, grid_mode=MPM_GRID_SPARSE, block_capacity=0, hash_capacity_log2=0, flags=0,
                  device="cuda"):
         self.w = w
-        self.params = params_from_workload(w, grid_mode=grid_mode, block_capacity=block_capacity,
-                                           hash_capacity_log2=hash_capacity_log2, flags=flags)
+        inst = getattr(w, "inst", None)
+        if inst is not None:   # an ensemble
+            self.params = params_from_ensemble(w, block_capacity=block_capacity,
+                                               hash_capacity_log2=hash_capacity_log2, flags=flags)
+            dim = w.members[0].dim
+        else:
+            self.params = params_from_workload(w, grid_mode=grid_mode, block_capacity=block_capacity,
+                                               hash_capacity_log2=hash_capacity_log2, flags=flags)
+            dim = w.dim
         self.ctx = mpm_create(self.params)
-        self.a = ParticleSet.from_arrays(w.state(), device=device)
-        self.b = ParticleSet(w.dim, w.n, device)
+        self.a = ParticleSet.from_arrays(w.state(), device=device, inst=inst)
+        self.b = ParticleSet(dim, w.n, device, with_inst=inst is not None)
 
     def set_state(self, st: dict, ids=None):
         import torch

@@ -366,3 +366,105 @@ def calibration_target_velocity(n: int, dim: int = 3, seed: int = 1003) -> np.nd
     v = rng.normal(0.0, 0.05, size=(dim, n))
     v[0] += 0.5
     return v.astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# ensembles of independent simulations
+@dataclass
+class Ensemble:
+    """Independent 3D column collapses on identical potential grids.
+
+    ``members[i]`` is instance i as a stand-alone workload (its own particles,
+    material and dt); ``x .. tau`` hold every member's particles together and
+    ``inst[p]`` names the instance of particle p.  The members' particles keep
+    their relative order inside the combined arrays.
+    """
+    name: str
+    members: list
+    steps: int
+    x: np.ndarray = field(default=None, repr=False)
+    v: np.ndarray = field(default=None, repr=False)
+    C: np.ndarray = field(default=None, repr=False)
+    F: np.ndarray = field(default=None, repr=False)
+    tau: np.ndarray = field(default=None, repr=False)
+    inst: np.ndarray = field(default=None, repr=False)
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[1])
+
+    @property
+    def n_instances(self) -> int:
+        return len(self.members)
+
+    def state(self) -> dict:
+        return {k: getattr(self, k).copy() for k in ("x", "v", "C", "F", "tau")}
+
+    def member_positions(self, i: int) -> np.ndarray:
+        """Positions in the combined arrays of instance i's particles, in member order."""
+        return np.nonzero(self.inst == i)[0]
+
+
+def ensemble(seed: int = 4, n_instances: int = 64, n_range=(5.0e4, 1.0e6), cells=(1020, 252, 252),
+             steps: int = 1000, interleave: bool = False) -> Ensemble:
+    """Batched column collapses: per instance N_i = round(exp U[ln a, ln b]) target
+    particles, aspect a_i ~ U[0.5, 4], footprint L_i = round((N_i / (8 a_i))^(1/3))
+    cells, height round(a_i L_i) cells (8 ppc, so the realised count is 8 L_i^2 H_i),
+    friction angle U[20, 40] degrees, E_i = exp U[ln 1e6, ln 1e8] Pa, nu = 0.3,
+    rho = 2000 kg/m^3, dt_i = 0.3 dx / c_P,i with c_P = sqrt((lambda + 2 mu) / rho),
+    dx = 0.01 m.  Every instance has the same potential grid (``cells``) and
+    walls; its column stands on the sticky floor y = 3 dx against the x = 3 dx
+    wall, centred in z.  ``interleave`` mixes the instances' particles in the
+    combined arrays (random merge that keeps each member's order)."""
+    dx = 0.01
+    rho, nu = 2000.0, 0.3
+    rng = np.random.default_rng(seed)
+    vol = dx ** 3 / 8
+    members = []
+    for i in range(n_instances):
+        n_t = float(np.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1]))))
+        a = float(rng.uniform(0.5, 4.0))
+        L = max(1, int(round((n_t / (8 * a)) ** (1 / 3))))
+        H = max(1, int(round(a * L)))
+        phi = float(rng.uniform(20.0, 40.0))
+        E = float(np.exp(rng.uniform(math.log(1e6), math.log(1e8))))
+        mu = E / (2 * (1 + nu))
+        lam = E * nu / ((1 + nu) * (1 - 2 * nu))
+        dt = 0.3 * dx / math.sqrt((lam + 2 * mu) / rho)
+        z0 = cells[2] // 2 - L // 2
+        if 3 + L > cells[0] - 3 or 3 + H > cells[1] - 3 or z0 < 3 or z0 + L > cells[2] - 3:
+            raise ValueError(f"instance {i}: a {L}x{H}x{L}-cell column does not fit {cells}")
+        x = stratified_cells((3, 3, z0), (3 + L, 3 + H, z0 + L), dx, 2, rng)
+        w = Workload(name=f"ensemble_member_{i}", dim=3, dx=dx, cells=tuple(cells), gravity=(0.0, -9.81, 0.0),
+                     dt=dt, steps=steps, ppc=8, p_vol0=vol, p_mass=rho * vol,
+                     bc=(("separate", "separate"), ("sticky", "separate"), ("separate", "separate")),
+                     model="dp", E=E, nu=nu, rho=rho, friction_deg=phi,
+                     meta={"aspect": a, "footprint_cells": L, "height_cells": H})
+        for k, arr in rest_state(x).items():
+            setattr(w, k, arr)
+        members.append(w)
+    counts = [m.n for m in members]
+    inst = np.repeat(np.arange(n_instances, dtype=np.uint32), counts)
+    ens = Ensemble(name=f"ensemble_{n_instances}", members=members, steps=steps)
+    if interleave:
+        inst = inst[rng.permutation(inst.size)]
+    ens.inst = np.ascontiguousarray(inst)
+    if interleave:
+        pos = [np.nonzero(ens.inst == i)[0] for i in range(n_instances)]
+    for k in ("x", "v", "C", "F", "tau"):
+        if not interleave:
+            setattr(ens, k, np.ascontiguousarray(np.concatenate([getattr(m, k) for m in members], axis=1)))
+            continue
+        rows = getattr(members[0], k).shape[0]
+        out = np.empty((rows, inst.size), np.float32)
+        for i, m in enumerate(members):
+            out[:, pos[i]] = getattr(m, k)
+        setattr(ens, k, out)
+    return ens
+
+
+def ensemble_small(seed: int = 5, n_instances: int = 6, interleave: bool = True) -> Ensemble:
+    """A few small members (200 .. 3000 target particles) on a 64x32x32-cell
+    grid, for reference checks."""
+    return ensemble(seed=seed, n_instances=n_instances, n_range=(200.0, 3000.0), cells=(64, 32, 32), steps=20,
+                    interleave=interleave)

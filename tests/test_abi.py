@@ -37,23 +37,13 @@ def test_library_exports_every_declared_symbol():
 @pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
 def test_struct_layout_matches_c():
     from paper_2605_28525_amd import mpm as M
-    src = r"""
-#include <stdio.h>
-#include <stddef.h>
-#include "mpm.h"
-#define O(s, f) printf("%s.%s %zu\n", #s, #f, offsetof(s, f))
-int main(void) {
-  printf("sizeof.mpm_params %zu\nsizeof.mpm_particles %zu\n", sizeof(mpm_params), sizeof(mpm_particles));
-  O(mpm_params, dim); O(mpm_params, dx); O(mpm_params, cells); O(mpm_params, gravity); O(mpm_params, dt);
-  O(mpm_params, bound); O(mpm_params, bc); O(mpm_params, heightmap); O(mpm_params, mu_terrain);
-  O(mpm_params, model); O(mpm_params, E); O(mpm_params, nu); O(mpm_params, friction_deg);
-  O(mpm_params, p_mass); O(mpm_params, p_vol0); O(mpm_params, max_particles); O(mpm_params, block_capacity);
-  O(mpm_params, hash_capacity_log2); O(mpm_params, grid_mode); O(mpm_params, flags);
-  O(mpm_particles, n); O(mpm_particles, x); O(mpm_particles, v); O(mpm_particles, C); O(mpm_particles, F);
-  O(mpm_particles, tau); O(mpm_particles, id);
-  return 0;
-}
-"""
+    structs = (M.mpm_params, M.mpm_particles, M.mpm_instance)
+    body = []
+    for st in structs:
+        body.append(f'printf("sizeof.{st.__name__} %zu\\n", sizeof({st.__name__}));')
+        body += [f'printf("{st.__name__}.{f} %zu\\n", offsetof({st.__name__}, {f}));' for f, _ in st._fields_]
+    src = "#include <stdio.h>\n#include <stddef.h>\n#include \"mpm.h\"\nint main(void) {\n" + \
+        "\n".join(body) + "\nreturn 0;\n}\n"
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "layout.c")
         exe = os.path.join(d, "layout")
@@ -64,9 +54,8 @@ int main(void) {
     for line in out.strip().splitlines():
         k, v = line.split()
         got[k] = int(v)
-    assert got["sizeof.mpm_params"] == ctypes.sizeof(M.mpm_params)
-    assert got["sizeof.mpm_particles"] == ctypes.sizeof(M.mpm_particles)
-    for struct in (M.mpm_params, M.mpm_particles):
+    for struct in structs:
+        assert got[f"sizeof.{struct.__name__}"] == ctypes.sizeof(struct), struct.__name__
         for name, _ in struct._fields_:
             assert got[f"{struct.__name__}.{name}"] == getattr(struct, name).offset, name
 
@@ -93,3 +82,29 @@ def test_create_rejects_bad_arguments_without_touching_the_device():
     assert M.lib.mpm_create(ctypes.byref(p), ctypes.byref(ctx)) == M.MPM_ERR_ARG
     assert not ctx.value
     assert M.lib.mpm_create(None, ctypes.byref(ctx)) == M.MPM_ERR_ARG
+
+
+def test_create_rejects_bad_ensembles_without_touching_the_device():
+    from paper_2605_28525_amd import mpm as M
+    from paper_2605_28525_amd import workloads as wl
+    ens = wl.ensemble_small(n_instances=3)
+    ctx = ctypes.c_void_p()
+    p = M.params_from_ensemble(ens)
+    p.n_instances = 65                      # more than 64 instances
+    assert M.lib.mpm_create(ctypes.byref(p), ctypes.byref(ctx)) == M.MPM_ERR_ARG
+    p = M.params_from_ensemble(ens)
+    p.instances = None                      # table missing
+    assert M.lib.mpm_create(ctypes.byref(p), ctypes.byref(ctx)) == M.MPM_ERR_ARG
+    p = M.params_from_ensemble(ens)
+    p.grid_mode = M.MPM_GRID_DENSE          # dense grids have no instance bits
+    assert M.lib.mpm_create(ctypes.byref(p), ctypes.byref(ctx)) == M.MPM_ERR_ARG
+    p = M.params_from_ensemble(ens)
+    p.flags = M.MPM_FLAG_ADJOINT
+    assert M.lib.mpm_create(ctypes.byref(p), ctypes.byref(ctx)) == M.MPM_ERR_ARG
+    p = M.params_from_ensemble(ens)
+    p._inst_keepalive[1].dt = 0.0           # invalid instance material
+    assert M.lib.mpm_create(ctypes.byref(p), ctypes.byref(ctx)) == M.MPM_ERR_ARG
+    p = M.params_from_ensemble(ens)
+    p.cells[0] = 1 << 20                    # instance + block + cell bits exceed 32
+    assert M.lib.mpm_create(ctypes.byref(p), ctypes.byref(ctx)) == M.MPM_ERR_ARG
+    assert not ctx.value
