@@ -183,8 +183,13 @@ int mpm_p2g(mpm_ctx* ctx, const mpm_particles* p, void* stream);
 int mpm_grid_update(mpm_ctx* ctx, void* stream);
 
 /* G2P (Eqs. 13-17) and the constitutive update.  Reads `in` through the sort
- * permutation of the last build and writes the advanced state to `out` in
- * sorted order; `in` and `out` must not overlap and must have the same n. */
+ * permutation of the last build and writes the advanced state to `out`
+ * grouped by owner block in Phi's sort order; inside a block's range the
+ * particles are stored rank-major over the block's cells (first particle of
+ * each occupied cell, then the second, ... up to rank 31, then the rest cell
+ * by cell), which makes the next step's P2G loads contiguous.
+ * mpm_get_order gives the resulting permutation.  `in` and `out` must not
+ * overlap and must have the same n. */
 int mpm_g2p(mpm_ctx* ctx, const mpm_particles* in, const mpm_particles* out, void* stream);
 
 /* n_steps explicit steps ping-ponging between a and b: step 0 reads a and
@@ -219,8 +224,9 @@ int mpm_get_active(mpm_ctx* ctx, uint64_t* keys, uint64_t* masks, int capacity, 
  * Device pointer owned by the caller, capacity * 4^d * 4 floats. */
 int mpm_get_grid(mpm_ctx* ctx, float* out, int capacity_blocks, void* stream);
 
-/* Copies the sort permutation of the last build: order[i] = index in the input
- * set of the particle written to position i by mpm_g2p.  Device pointer. */
+/* Writes the particle permutation of mpm_g2p for the last build: order[i] =
+ * index in the input set of the particle that mpm_g2p writes to position i.
+ * Device pointer owned by the caller, n entries. */
 int mpm_get_order(mpm_ctx* ctx, uint32_t* order, int n, void* stream);
 
 /* ---- reverse mode (contexts created with MPM_FLAG_ADJOINT) -------------

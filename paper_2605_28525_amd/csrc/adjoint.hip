@@ -319,7 +319,8 @@ __device__ __forceinline__ void shape_k(const float (*wt)[3], const float (*dw)[
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_g2p_adj(DevParams P, const float* __restrict__ x, const float* __restrict__ F,
                                                 OutBar ob, float* __restrict__ x_bar, float* __restrict__ F_bar, int n,
-                                                const uint32_t* __restrict__ order) {
+                                                const uint32_t* __restrict__ order,
+                                                const uint32_t* __restrict__ skeys) {
     using T = Tile<DIM>;
     constexpr int NS = DIM == 3 ? 6 : 3;
     constexpr int DD = DIM * DIM;
@@ -327,6 +328,7 @@ __global__ __launch_bounds__(WG) void k_g2p_adj(DevParams P, const float* __rest
     __shared__ int nbr[T::NB];
     __shared__ int org[3];
     __shared__ float red[2][WG / 64];
+    __shared__ Interleave<DIM> il;
     const int n_work = min(P.ctr->n_work, P.work_cap);
     const float dt = P.dt, dx = P.dxf, inv_dx = P.inv_dxf;
     const float bscale = 4.f * inv_dx * inv_dx;
@@ -341,7 +343,7 @@ __global__ __launch_bounds__(WG) void k_g2p_adj(DevParams P, const float* __rest
             org[1] = bc[1] * BLK;
             org[2] = bc[2] * BLK;
         }
-        __syncthreads();
+        interleave_setup<DIM>(il, skeys, P.b_start[blk], P.b_start[blk] + P.b_count[blk]);
         for (int t = threadIdx.x; t < T::N; t += WG) {
             const int I = t % T::E, J = (t / T::E) % T::E, K = DIM == 3 ? t / (T::E * T::E) : 0;
             const int d = (I >> 2) | ((J >> 2) << 1) | ((K >> 2) << 2);
@@ -353,6 +355,7 @@ __global__ __launch_bounds__(WG) void k_g2p_adj(DevParams P, const float* __rest
 #pragma unroll 1
         for (int i = s + (int)threadIdx.x; i < e; i += WG) {
             const size_t q = order[i];
+            const size_t o = (size_t)interleave_pos<DIM>(il, i, skeys[i]);  // where G2P stored it
             float xp[3] = {0, 0, 0}, Fp[3][3];
 #pragma unroll
             for (int a = 0; a < DIM; ++a) xp[a] = x[(size_t)a * n + q];
@@ -398,22 +401,22 @@ __global__ __launch_bounds__(WG) void k_g2p_adj(DevParams P, const float* __rest
                     for (int c = 0; c < DIM; ++c) s2 += W[a][c] * Fp[c][b];
                     Ft[a][b] = Fp[a][b] + dt * s2;
                 }
-            // output adjoints at the sorted position i
+            // output adjoints at the particle's G2P output position o
             float xbo[3] = {0, 0, 0}, vbo[3] = {0, 0, 0}, Cbo[3][3] = {{0}}, Fbo[3][3] = {{0}}, tbo[6] = {0};
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
-                xbo[a] = ob.x[(size_t)a * n + i];
-                vbo[a] = ob.v[(size_t)a * n + i];
+                xbo[a] = ob.x[(size_t)a * n + o];
+                vbo[a] = ob.v[(size_t)a * n + o];
             }
 #pragma unroll
             for (int a = 0; a < DIM; ++a)
 #pragma unroll
                 for (int b = 0; b < DIM; ++b) {
-                    Cbo[a][b] = ob.C[(size_t)(a * DIM + b) * n + i];
-                    Fbo[a][b] = ob.F[(size_t)(a * DIM + b) * n + i];
+                    Cbo[a][b] = ob.C[(size_t)(a * DIM + b) * n + o];
+                    Fbo[a][b] = ob.F[(size_t)(a * DIM + b) * n + o];
                 }
 #pragma unroll
-            for (int k = 0; k < NS; ++k) tbo[k] = ob.tau[(size_t)k * n + i];
+            for (int k = 0; k < NS; ++k) tbo[k] = ob.tau[(size_t)k * n + o];
             float Ftb[3][3], eb, ab;
             constitutive_adj<DIM>(P, Ft, Fbo, tbo, Ftb, &eb, &ab);
             accE += eb;
@@ -832,12 +835,13 @@ __global__ __launch_bounds__(WG) void k_grid_bar_clear(DevParams P, long long n_
 }
 
 hipError_t launch_g2p_adj(const DevParams& P, const float* x, const float* F, const float* const* out_bar, float* x_bar,
-                          float* F_bar, int n, const uint32_t* order, int grid_blocks, hipStream_t s) {
+                          float* F_bar, int n, const uint32_t* order, const uint32_t* skeys, int grid_blocks,
+                          hipStream_t s) {
     OutBar ob{out_bar[0], out_bar[1], out_bar[2], out_bar[3], out_bar[4]};
     if (P.dim == 3)
-        k_g2p_adj<3><<<grid_blocks, WG, 0, s>>>(P, x, F, ob, x_bar, F_bar, n, order);
+        k_g2p_adj<3><<<grid_blocks, WG, 0, s>>>(P, x, F, ob, x_bar, F_bar, n, order, skeys);
     else
-        k_g2p_adj<2><<<grid_blocks, WG, 0, s>>>(P, x, F, ob, x_bar, F_bar, n, order);
+        k_g2p_adj<2><<<grid_blocks, WG, 0, s>>>(P, x, F, ob, x_bar, F_bar, n, order, skeys);
     return hipGetLastError();
 }
 

@@ -526,7 +526,7 @@ int mpm_g2p(mpm_ctx* c, const mpm_particles* in, const mpm_particles* out, void*
     if (in->n == 0) return MPM_OK;
     const int wgs = std::min(c->g2p_wgs, c->work_cap);
     return hip_status(launch_g2p(c->P, in->x, in->F, in->id, in->inst, out->x, out->v, out->C, out->F, out->tau,
-                                 out->id, out->inst, in->n, c->order, wgs, (hipStream_t)stream));
+                                 out->id, out->inst, in->n, c->order, c->skeys, wgs, (hipStream_t)stream));
 }
 
 int mpm_step(mpm_ctx* c, const mpm_particles* a, const mpm_particles* b, int n_steps, void* stream) {
@@ -556,7 +556,7 @@ int mpm_g2p_adj(mpm_ctx* c, const mpm_particles* in, const mpm_particles* ob, co
     const float* obp[5] = {ob->x, ob->v, ob->C, ob->F, ob->tau};
     const int wgs = std::min(c->g2p_wgs, c->work_cap);
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = launch_g2p_adj(P, in->x, in->F, obp, ib->x, ib->F, in->n, c->order, wgs, s);
+    hipError_t e = launch_g2p_adj(P, in->x, in->F, obp, ib->x, ib->F, in->n, c->order, c->skeys, wgs, s);
     if (e == hipSuccess) e = launch_scatter_adj(P, in->x, in->n, c->order, c->skeys, wgs, s);
     return hip_status(e);
 }
@@ -639,8 +639,8 @@ int mpm_get_order(mpm_ctx* c, uint32_t* order, int n, void* stream) {
     if (!c || !order || n < 0) return MPM_ERR_ARG;
     if (!c->built || n != c->built_n) return MPM_ERR_STATE;
     if (n == 0) return MPM_OK;
-    return hip_status(
-        hipMemcpyAsync(order, c->order, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    const int wgs = std::min(c->g2p_wgs, c->work_cap);
+    return hip_status(launch_out_order(c->P, c->order, c->skeys, order, wgs, (hipStream_t)stream));
 }
 
 int mpm_graph_release(mpm_ctx* c) {

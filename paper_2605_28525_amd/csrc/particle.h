@@ -103,4 +103,71 @@ __device__ __forceinline__ void jacobi_sym(float (*A)[3], float (*U)[3]) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Placement of a block's particles in the G2P output.
+//
+// The sort lists a block's particles cell by cell.  The next step's P2G gives
+// each base cell of a block to one lane and walks that cell's particles, so
+// cell-major storage would make its loads stride by the particles per cell
+// (a few cache lines per wave instruction, each used in part).  G2P therefore
+// stores a block's particles rank-major: the first particle of every non-empty
+// cell (cells in order), then every second particle, and so on for ranks below
+// IL_ROUNDS; particles of higher rank follow cell by cell.  The next sort is
+// stable, so a cell that keeps its particles hands them back to its P2G lane
+// in the same rank order, and consecutive lanes load consecutive addresses.
+constexpr int IL_ROUNDS = 32;
+
+template <int DIM>
+struct Interleave {
+    static constexpr int NC = 1 << (2 * DIM);
+    unsigned long long mask[IL_ROUNDS];  // cells holding more than j particles
+    int R[IL_ROUNDS + 1];                // particles of rank < j
+    int cs[NC], ce[NC];                  // cell ranges in sorted order
+    int op[NC];                          // rank >= IL_ROUNDS particles of the cells before
+    int st;                              // first sorted position of the block
+};
+
+// Workgroup-cooperative set-up for the owner segment [st, en) (every thread
+// calls it; blockDim.x >= 64; ends with a barrier).
+template <int DIM>
+__device__ void interleave_setup(Interleave<DIM>& L, const uint32_t* __restrict__ skeys, int st, int en) {
+    constexpr int NC = Interleave<DIM>::NC;
+    for (int c = threadIdx.x; c < NC; c += blockDim.x) L.cs[c] = L.ce[c] = 0;
+    if (threadIdx.x == 0) L.st = st;
+    __syncthreads();
+    for (int i = st + (int)threadIdx.x; i < en; i += blockDim.x) {
+        const uint32_t c = skeys[i] & (NC - 1);
+        if (i == st || (skeys[i - 1] & (NC - 1)) != c) L.cs[c] = i;
+        if (i == en - 1 || (skeys[i + 1] & (NC - 1)) != c) L.ce[c] = i + 1;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const int cnt = lane < NC ? L.ce[lane] - L.cs[lane] : 0;
+        const int ovf = max(cnt - IL_ROUNDS, 0);
+        const int inc = (int)wave_incl_scan((unsigned)ovf);
+        if (lane < NC) L.op[lane] = inc - ovf;
+        int acc = 0;
+        for (int j = 0; j < IL_ROUNDS; ++j) {
+            const unsigned long long m = __ballot(cnt > j);
+            if (lane == 0) {
+                L.mask[j] = m;
+                L.R[j] = acc;
+            }
+            acc += __popcll(m);
+        }
+        if (lane == 0) L.R[IL_ROUNDS] = acc;
+    }
+    __syncthreads();
+}
+
+// Output position of the particle at sorted position i (sort key `key`).
+template <int DIM>
+__device__ __forceinline__ int interleave_pos(const Interleave<DIM>& L, int i, uint32_t key) {
+    const int c = (int)(key & (Interleave<DIM>::NC - 1));
+    const int j = i - L.cs[c];
+    if (j < IL_ROUNDS) return L.st + L.R[j] + __popcll(L.mask[j] & ((1ull << c) - 1ull));
+    return L.st + L.R[IL_ROUNDS] + L.op[c] + (j - IL_ROUNDS);
+}
+
 }  // namespace mpmx

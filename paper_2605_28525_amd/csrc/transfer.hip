@@ -421,13 +421,15 @@ struct G2POut {
 
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_g2p(DevParams P, G2PIn in, G2POut out, int n,
-                                            const uint32_t* __restrict__ order) {
+                                            const uint32_t* __restrict__ order, const uint32_t* __restrict__ skeys) {
     using T = Tile<DIM>;
     constexpr int NS = DIM == 3 ? 6 : 3;
     constexpr int DD = DIM * DIM;
     __shared__ float4 vt[T::N];
     __shared__ float xs[DIM][G2P_MAX_ITEM];
     __shared__ float fs[DD][G2P_MAX_ITEM];
+    __shared__ int os[G2P_MAX_ITEM];
+    __shared__ Interleave<DIM> il;
     __shared__ int nbr[T::NB];
     __shared__ int org[4];
     const int n_work = min(P.ctr->n_work, P.work_cap);
@@ -445,17 +447,20 @@ __global__ __launch_bounds__(WG) void k_g2p(DevParams P, G2PIn in, G2POut out, i
             org[2] = bc[2] * BLK;
             org[3] = inst;
         }
+        interleave_setup<DIM>(il, skeys, P.b_start[blk], P.b_start[blk] + P.b_count[blk]);
         // phase 0: issue every global gather of the work item up front
         // (positions, deformation gradients, ids) and stage them in LDS
 #pragma unroll 2
         for (int r = threadIdx.x; r < L; r += WG) {
             const size_t q = order[s + r];
+            const int o = interleave_pos<DIM>(il, s + r, skeys[s + r]);
+            os[r] = o;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) xs[a][r] = in.x[(size_t)a * n + q];
 #pragma unroll
             for (int k = 0; k < DD; ++k) fs[k][r] = in.F[(size_t)k * n + q];
-            if (out.id) out.id[s + r] = in.id ? in.id[q] : (uint32_t)q;
-            if (out.inst) out.inst[s + r] = in.inst ? in.inst[q] : 0u;
+            if (out.id) out.id[o] = in.id ? in.id[q] : (uint32_t)q;
+            if (out.inst) out.inst[o] = in.inst ? in.inst[q] : 0u;
         }
         __syncthreads();
         const InstMat mat = material(P, org[3]);
@@ -533,7 +538,7 @@ __global__ __launch_bounds__(WG) void k_g2p(DevParams P, G2PIn in, G2POut out, i
                     // (bounds register pressure, hence raises occupancy)
                     __builtin_amdgcn_sched_barrier(0);
                 }
-            const size_t o = (size_t)(s + r);
+            const size_t o = (size_t)os[r];
             bool finite = true;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
@@ -566,7 +571,7 @@ __global__ __launch_bounds__(WG) void k_g2p(DevParams P, G2PIn in, G2POut out, i
         // phase 2: constitutive update (its register live range is separate)
 #pragma unroll 1
         for (int r = threadIdx.x; r < L; r += WG) {
-            const size_t o = (size_t)(s + r);
+            const size_t o = (size_t)os[r];
             float Ft[3][3], Fn[3][3], tau6[6];
 #pragma unroll
             for (int a = 0; a < DIM; ++a)
@@ -610,14 +615,37 @@ hipError_t launch_grid_update(const DevParams& P, long long n_nodes_host, int gr
 
 hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, const uint32_t* id_in,
                       const uint32_t* inst_in, float* x_out, float* v_out, float* C_out, float* F_out, float* tau_out,
-                      uint32_t* id_out, uint32_t* inst_out, int n, const uint32_t* order, int grid_blocks,
-                      hipStream_t s) {
+                      uint32_t* id_out, uint32_t* inst_out, int n, const uint32_t* order, const uint32_t* skeys,
+                      int grid_blocks, hipStream_t s) {
     G2PIn in{x_in, F_in, id_in, inst_in};
     G2POut out{x_out, v_out, C_out, F_out, tau_out, id_out, inst_out};
     if (P.dim == 3)
-        k_g2p<3><<<grid_blocks, WG, 0, s>>>(P, in, out, n, order);
+        k_g2p<3><<<grid_blocks, WG, 0, s>>>(P, in, out, n, order, skeys);
     else
-        k_g2p<2><<<grid_blocks, WG, 0, s>>>(P, in, out, n, order);
+        k_g2p<2><<<grid_blocks, WG, 0, s>>>(P, in, out, n, order, skeys);
+    return hipGetLastError();
+}
+
+// Output position -> input index map of the G2P of the last build.
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_out_order(DevParams P, const uint32_t* __restrict__ order,
+                                                  const uint32_t* __restrict__ skeys, uint32_t* __restrict__ out) {
+    __shared__ Interleave<DIM> il;
+    const int n_work = min(P.ctr->n_work, P.work_cap);
+    for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
+        const int blk = P.w_block[w], s = P.w_start[w], e = P.w_end[w];
+        interleave_setup<DIM>(il, skeys, P.b_start[blk], P.b_start[blk] + P.b_count[blk]);
+        for (int i = s + (int)threadIdx.x; i < e; i += WG) out[interleave_pos<DIM>(il, i, skeys[i])] = order[i];
+        __syncthreads();
+    }
+}
+
+hipError_t launch_out_order(const DevParams& P, const uint32_t* order, const uint32_t* skeys, uint32_t* out,
+                            int grid_blocks, hipStream_t s) {
+    if (P.dim == 3)
+        k_out_order<3><<<grid_blocks, WG, 0, s>>>(P, order, skeys, out);
+    else
+        k_out_order<2><<<grid_blocks, WG, 0, s>>>(P, order, skeys, out);
     return hipGetLastError();
 }
 

@@ -111,7 +111,9 @@ def _check_step_adjoint(w, st, seed):
 
 
 def test_step_adjoint_tiny_3d():
-    w = wl.tiny_3d(n=48)
+    # no particles on half-cell ties: the B-spline's second derivative jumps at
+    # its knots, so the position adjoint (which uses it) is undefined there
+    w = wl.tiny_3d(n=48, ties=False)
     w.E = 5e4
     st = _consistent_state(w, 1)
     _announce("step adjoint tiny_3d", w.n)
