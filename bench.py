@@ -103,17 +103,21 @@ def time_steps(sim, steps, stream, phases=True):
 
 
 def adjoint_ratio(steps, checkpoint=50):
-    """Calibration workload (262,144 particles): wall time of the checkpointed
-    backward pass (segment recompute + adjoint kernels) over the forward pass."""
+    """Calibration workload (262,144 particles).  step_ratio: one adjoint step
+    (mpm_step_adj: rebuild, P2G and grid update of the input state, then the
+    reverse kernels) over one forward step (mpm_step) on the same input state.
+    rollout_ratio: wall time of the checkpointed backward pass (segment
+    recompute + adjoint steps) over the forward rollout."""
     import torch
     from paper_2605_28525_amd import autograd as AG
+    from paper_2605_28525_amd import mpm as M
     from paper_2605_28525_amd import workloads as wl
     w = wl.differentiable_3d()
     n = w.n
     roll = AG.Rollout(w, steps=steps, checkpoint=checkpoint)
     try:
         v0 = torch.from_numpy(wl.calibration_target_velocity(n, seed=1003)).cuda()
-        # warm-up (JIT of the code objects, allocator)
+        # warm-up (code objects, allocator)
         final = roll.run_forward(v0, w.E, w.friction_deg)
         roll.backward(final, torch.zeros_like(final.x))
         torch.cuda.synchronize()
@@ -125,11 +129,35 @@ def adjoint_ratio(steps, checkpoint=50):
         gE, gphi, gv0 = roll.backward(final, x_bar)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+        # mpm_step reads a and writes b; mpm_step_adj reads a and the output
+        # adjoint and writes the input adjoint: both leave a unchanged
+        reps = 20
+        a = final
+        b = M.ParticleSet(w.dim, n, zero=False)
+        ob = M.ParticleSet(w.dim, n)
+        ob.x.copy_(x_bar)
+        ib = M.ParticleSet(w.dim, n, zero=False)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        for _ in range(2):
+            M.mpm_step(roll.ctx, a.view(), b.view(), 1)
+            M.mpm_step_adj(roll.ctx, a.view(), ob.view(), ib.view(), roll.param_bar)
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(reps):
+            M.mpm_step(roll.ctx, a.view(), b.view(), 1)
+        ev[1].record()
+        for _ in range(reps):
+            M.mpm_step_adj(roll.ctx, a.view(), ob.view(), ib.view(), roll.param_bar)
+        ev[2].record()
+        torch.cuda.synchronize()
+        t_step = ev[0].elapsed_time(ev[1]) / reps
+        t_adj = ev[1].elapsed_time(ev[2]) / reps
     finally:
         roll.close()
     fwd, bwd = t1 - t0, t2 - t1
     return {"workload": w.name, "particles": n, "steps": steps, "checkpoint_every": checkpoint,
-            "forward_ms": 1e3 * fwd, "backward_ms": 1e3 * bwd, "ratio": bwd / fwd,
+            "step_ms": t_step, "adjoint_step_ms": t_adj, "step_ratio": t_adj / t_step,
+            "rollout_forward_ms": 1e3 * fwd, "rollout_backward_ms": 1e3 * bwd, "rollout_ratio": bwd / fwd,
             "grad_finite": bool(np.isfinite(gE) and np.isfinite(gphi) and torch.isfinite(gv0).all().item())}
 
 
@@ -339,7 +367,7 @@ def main():
     if not args.no_adjoint:
         log("bench: adjoint/forward ratio")
         out["adjoint"] = adjoint_ratio(args.adjoint_steps)
-        out["adjoint_forward_ratio"] = out["adjoint"]["ratio"]
+        out["adjoint_forward_ratio"] = out["adjoint"]["step_ratio"]
     if not args.no_ensemble:
         log("bench: ensemble")
         out["ensemble"] = ensemble_leg(args.ensemble_steps, stream)

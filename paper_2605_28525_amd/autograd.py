@@ -34,7 +34,8 @@ class Rollout:
         self.nu = float(w.nu)
         self.dt = float(w.dt)
         self._bufs = [M.ParticleSet(w.dim, w.n, device) for _ in range(2)]
-        self._bars = [M.ParticleSet(w.dim, w.n, device) for _ in range(2)]
+        self._bars = [M.ParticleSet(w.dim, w.n, device, zero=False) for _ in range(2)]
+        self._pool = []   # states of one recomputed segment, allocated on first use
         self.param_bar = torch.zeros(2, dtype=torch.float32, device=device)
         self.checkpoints = []
 
@@ -68,18 +69,20 @@ class Rollout:
         """x_bar: dL/dx of `final` (same order).  Returns (dL/dE, dL/dphi, dL/dv0)."""
         self.param_bar.zero_()
         bar_ids = final.id.clone()
-        bar = M.ParticleSet(self.dim, self.n, self.device)
+        bar, spare = self._bars
+        for key in ("v", "C", "F", "tau"):
+            getattr(bar, key).zero_()
         bar.x.copy_(x_bar)
-        spare = M.ParticleSet(self.dim, self.n, self.device)
+        while len(self._pool) < self.K + 1:
+            self._pool.append(M.ParticleSet(self.dim, self.n, self.device, zero=False))
         nseg = len(self.checkpoints)
         for si in range(nseg - 1, -1, -1):
             s0 = si * self.K
             k = min(self.K, self.steps - s0)
-            states = [M.ParticleSet(self.dim, self.n, self.device).copy_(self.checkpoints[si])]
+            states = self._pool[:k + 1]
+            states[0].copy_(self.checkpoints[si])
             for j in range(k):
-                nxt = M.ParticleSet(self.dim, self.n, self.device)
-                M.mpm_step(self.ctx, states[-1].view(), nxt.view(), 1)
-                states.append(nxt)
+                M.mpm_step(self.ctx, states[j].view(), states[j + 1].view(), 1)
             # align the incoming adjoint with the recomputed end state by id
             end_ids = states[-1].id
             if not torch.equal(end_ids, bar_ids):
@@ -88,8 +91,8 @@ class Rollout:
                 perm = inv[end_ids.long()]
                 for key in ("x", "v", "C", "F", "tau"):
                     getattr(bar, key).copy_(getattr(bar, key)[:, perm])
+            # every field of the input adjoint is overwritten by mpm_step_adj
             for j in range(k - 1, -1, -1):
-                spare.zero_()
                 M.mpm_step_adj(self.ctx, states[j].view(), bar.view(), spare.view(), self.param_bar)
                 bar, spare = spare, bar
             bar_ids = states[0].id.clone()
@@ -97,6 +100,7 @@ class Rollout:
         inv = torch.empty_like(bar_ids, dtype=torch.long)
         inv[bar_ids.long()] = torch.arange(self.n, device=self.device)
         v0_bar = bar.v[:, inv].clone()
+        self._bars = [bar, spare]
         pb = self.param_bar.detach().cpu()
         return float(pb[0]), float(pb[1]), v0_bar
 

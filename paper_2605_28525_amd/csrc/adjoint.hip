@@ -527,7 +527,7 @@ __global__ __launch_bounds__(64) void k_scatter_adj(DevParams P, const float* __
     constexpr int NC = T::NPB;
     constexpr int NK = DIM == 3 ? 27 : 9;
     constexpr int DD = DIM * DIM;
-    __shared__ float tile[3][T::N];
+    __shared__ float tile[3][T::NP];
     __shared__ int cs[NC], ce[NC];
     const int lane = threadIdx.x;
     const int nb = min(P.ctr->nb, P.block_cap);
@@ -537,7 +537,7 @@ __global__ __launch_bounds__(64) void k_scatter_adj(DevParams P, const float* __
         const int cnt = P.b_count[b];
         if (cnt <= 0) continue;
         const int st = P.b_start[b], en = st + cnt;
-        for (int t = lane; t < 3 * T::N; t += 64) (&tile[0][0])[t] = 0.f;
+        for (int t = lane; t < 3 * T::NP; t += 64) (&tile[0][0])[t] = 0.f;
         for (int c = lane; c < NC; c += 64) cs[c] = ce[c] = 0;
         int bc[3];
         block_coords<DIM>(P, b, bc);
@@ -606,7 +606,7 @@ __global__ __launch_bounds__(64) void k_scatter_adj(DevParams P, const float* __
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
             const int kx = k % 3, ky = (k / 3) % 3, kz = DIM == 3 ? k / 9 : 0;
-            const int idx = (lb[0] + kx) + T::E * ((lb[1] + ky) + (DIM == 3 ? T::E * (lb[2] + kz) : 0));
+            const int idx = T::pad(lb[0] + kx, lb[1] + ky, DIM == 3 ? lb[2] + kz : 0);
             if (has) {
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) tile[a][idx] += acc[k][a];
@@ -614,11 +614,12 @@ __global__ __launch_bounds__(64) void k_scatter_adj(DevParams P, const float* __
             __syncthreads();
         }
         for (int t = lane; t < T::N; t += 64) {
-            const float p0 = tile[0][t], p1 = tile[1][t], p2 = DIM == 3 ? tile[2][t] : 0.f;
+            const int I = t % T::E;
+            const int J = (t / T::E) % T::E;
+            const int K = DIM == 3 ? t / (T::E * T::E) : 0;
+            const int tp = T::pad(I, J, K);
+            const float p0 = tile[0][tp], p1 = tile[1][tp], p2 = DIM == 3 ? tile[2][tp] : 0.f;
             if (p0 != 0.f || p1 != 0.f || p2 != 0.f) {
-                const int I = t % T::E;
-                const int J = (t / T::E) % T::E;
-                const int K = DIM == 3 ? t / (T::E * T::E) : 0;
                 const int d = (I >> 2) | ((J >> 2) << 1) | ((K >> 2) << 2);
                 const int phi = P.b_nbr[(size_t)b * T::NB + d];
                 if (phi >= 0) {

@@ -17,6 +17,14 @@ struct Tile {
     static constexpr int N = DIM == 3 ? E * E * E : E * E;  // 216 / 36
     static constexpr int NB = 1 << DIM;                     // blocks touched
     static constexpr int NPB = 1 << (2 * DIM);              // nodes per block
+    // Padded LDS layout of a scatter tile written by one lane per base cell:
+    // node (I, J, K) at I + SY J + SZ K.  For a fixed stencil offset the 64
+    // lanes of a wave (cells i, j, k in 0..3) then hit 64 distinct banks
+    // modulo 64, and 32 distinct banks within each half-wave modulo 32.
+    static constexpr int SY = DIM == 3 ? 12 : E;
+    static constexpr int SZ = DIM == 3 ? 80 : 0;
+    static constexpr int NP = DIM == 3 ? E * SZ : E * E;   // padded size
+    static __device__ __forceinline__ int pad(int I, int J, int K) { return I + SY * J + SZ * K; }
 };
 
 // Per-axis base offset within the owner block, t and u, for one particle.

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
     constexpr int NS = DIM == 3 ? 6 : 3;
     constexpr int NC = T::NPB;  // base cells per block
     constexpr int NK = DIM == 3 ? 27 : 9;
-    __shared__ float tile[4][T::N];
+    __shared__ float tile[4][T::NP];
     __shared__ int cs[NC], ce[NC];
     __shared__ uint32_t ord[P2G_ORDER_STAGE];
     const int lane = threadIdx.x;
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
         const int cnt = P.b_count[b];
         if (cnt <= 0) continue;
         const int st = P.b_start[b], en = st + cnt;
-        for (int t = lane; t < 4 * T::N; t += 64) (&tile[0][0])[t] = 0.f;
+        for (int t = lane; t < 4 * T::NP; t += 64) (&tile[0][0])[t] = 0.f;
         for (int c = lane; c < NC; c += 64) cs[c] = ce[c] = 0;
         int bc[3], inst;
         block_coords<DIM>(P, b, bc, &inst);
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
             const int kx = k % 3, ky = (k / 3) % 3, kz = DIM == 3 ? k / 9 : 0;
-            const int idx = (lb[0] + kx) + T::E * ((lb[1] + ky) + (DIM == 3 ? T::E * (lb[2] + kz) : 0));
+            const int idx = T::pad(lb[0] + kx, lb[1] + ky, DIM == 3 ? lb[2] + kz : 0);
             if (has) {
                 tile[0][idx] += acc[k][0];
                 tile[1][idx] += acc[k][1];
@@ -201,11 +201,12 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
         }
         __syncthreads();
         for (int t = lane; t < T::N; t += 64) {
-            const float m = tile[3][t], p0 = tile[0][t], p1 = tile[1][t], p2 = DIM == 3 ? tile[2][t] : 0.f;
+            const int I = t % T::E;
+            const int J = (t / T::E) % T::E;
+            const int K = DIM == 3 ? t / (T::E * T::E) : 0;
+            const int tp = T::pad(I, J, K);
+            const float m = tile[3][tp], p0 = tile[0][tp], p1 = tile[1][tp], p2 = DIM == 3 ? tile[2][tp] : 0.f;
             if (m != 0.f || p0 != 0.f || p1 != 0.f || p2 != 0.f) {
-                const int I = t % T::E;
-                const int J = (t / T::E) % T::E;
-                const int K = DIM == 3 ? t / (T::E * T::E) : 0;
                 const int d = (I >> 2) | ((J >> 2) << 1) | ((K >> 2) << 2);
                 const int phi = P.b_nbr[(size_t)b * T::NB + d];
                 if (phi >= 0) {
@@ -428,7 +429,7 @@ __global__ __launch_bounds__(WG) void k_g2p(DevParams P, G2PIn in, G2POut out, i
     __shared__ float4 vt[T::N];
     __shared__ float xs[DIM][G2P_MAX_ITEM];
     __shared__ float fs[DD][G2P_MAX_ITEM];
-    __shared__ int os[G2P_MAX_ITEM];
+    __shared__ int src[G2P_MAX_ITEM];
     __shared__ Interleave<DIM> il;
     __shared__ int nbr[T::NB];
     __shared__ int org[4];
@@ -447,20 +448,28 @@ __global__ __launch_bounds__(WG) void k_g2p(DevParams P, G2PIn in, G2POut out, i
             org[2] = bc[2] * BLK;
             org[3] = inst;
         }
-        interleave_setup<DIM>(il, skeys, P.b_start[blk], P.b_start[blk] + P.b_count[blk]);
+        // The work item writes output positions s .. s+L-1 (contiguous, so the
+        // stores below coalesce); find the sorted position stored at each.
+        {
+            const int st = P.b_start[blk], en = st + P.b_count[blk];
+            interleave_setup<DIM>(il, skeys, st, en);
+            for (int i = st + (int)threadIdx.x; i < en; i += WG) {
+                const int o = interleave_pos<DIM>(il, i, skeys[i]) - s;
+                if (o >= 0 && o < L) src[o] = i;
+            }
+            __syncthreads();
+        }
         // phase 0: issue every global gather of the work item up front
         // (positions, deformation gradients, ids) and stage them in LDS
 #pragma unroll 2
         for (int r = threadIdx.x; r < L; r += WG) {
-            const size_t q = order[s + r];
-            const int o = interleave_pos<DIM>(il, s + r, skeys[s + r]);
-            os[r] = o;
+            const size_t q = order[src[r]];
 #pragma unroll
             for (int a = 0; a < DIM; ++a) xs[a][r] = in.x[(size_t)a * n + q];
 #pragma unroll
             for (int k = 0; k < DD; ++k) fs[k][r] = in.F[(size_t)k * n + q];
-            if (out.id) out.id[o] = in.id ? in.id[q] : (uint32_t)q;
-            if (out.inst) out.inst[o] = in.inst ? in.inst[q] : 0u;
+            if (out.id) out.id[s + r] = in.id ? in.id[q] : (uint32_t)q;
+            if (out.inst) out.inst[s + r] = in.inst ? in.inst[q] : 0u;
         }
         __syncthreads();
         const InstMat mat = material(P, org[3]);
@@ -538,7 +547,7 @@ __global__ __launch_bounds__(WG) void k_g2p(DevParams P, G2PIn in, G2POut out, i
                     // (bounds register pressure, hence raises occupancy)
                     __builtin_amdgcn_sched_barrier(0);
                 }
-            const size_t o = (size_t)os[r];
+            const size_t o = (size_t)(s + r);
             bool finite = true;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
@@ -571,7 +580,7 @@ __global__ __launch_bounds__(WG) void k_g2p(DevParams P, G2PIn in, G2POut out, i
         // phase 2: constitutive update (its register live range is separate)
 #pragma unroll 1
         for (int r = threadIdx.x; r < L; r += WG) {
-            const size_t o = (size_t)os[r];
+            const size_t o = (size_t)(s + r);
             float Ft[3][3], Fn[3][3], tau6[6];
 #pragma unroll
             for (int a = 0; a < DIM; ++a)

@@ -304,17 +304,18 @@ def params_from_ensemble(ens, *, max_particles=None, block_capacity=0, hash_capa
 class ParticleSet:
     """Device SoA particle state as torch tensors plus its ``mpm_particles`` view."""
 
-    def __init__(self, dim: int, n: int, device="cuda", with_inst: bool = False):
+    def __init__(self, dim: int, n: int, device="cuda", with_inst: bool = False, zero: bool = True):
         import torch
         d = dim
+        make = torch.zeros if zero else torch.empty
         self.dim, self.n = dim, n
-        self.inst = torch.zeros((n,), dtype=torch.int32, device=device) if with_inst else None
-        self.x = torch.zeros((d, n), dtype=torch.float32, device=device)
-        self.v = torch.zeros((d, n), dtype=torch.float32, device=device)
-        self.C = torch.zeros((d * d, n), dtype=torch.float32, device=device)
-        self.F = torch.zeros((d * d, n), dtype=torch.float32, device=device)
-        self.tau = torch.zeros((3 if d == 2 else 6, n), dtype=torch.float32, device=device)
-        self.id = torch.zeros((n,), dtype=torch.int32, device=device)
+        self.inst = make((n,), dtype=torch.int32, device=device) if with_inst else None
+        self.x = make((d, n), dtype=torch.float32, device=device)
+        self.v = make((d, n), dtype=torch.float32, device=device)
+        self.C = make((d * d, n), dtype=torch.float32, device=device)
+        self.F = make((d * d, n), dtype=torch.float32, device=device)
+        self.tau = make((3 if d == 2 else 6, n), dtype=torch.float32, device=device)
+        self.id = make((n,), dtype=torch.int32, device=device)
 
     @classmethod
     def from_arrays(cls, st: dict, ids=None, device="cuda", inst=None):
