@@ -59,6 +59,7 @@ struct mpm_ctx {
     int built_n = -1;
     uint32_t* order = nullptr;
     uint32_t* skeys = nullptr;
+    uint32_t* osrc = nullptr;  // G2P output position -> input index (the spare sort value buffer)
 };
 
 namespace {
@@ -274,10 +275,12 @@ int build_once(mpm_ctx* c, const mpm_particles* p, hipStream_t s) {
     }
     c->skeys = ko;
     c->order = vo;
+    c->osrc = vo == c->v0 ? c->v1 : c->v0;
     if (c->dense)
         e = launch_build_dense(c->P, ko, n, (int)c->n_blocks_total, c->partials, s);
     else
         e = launch_build_sparse(c->P, ko, n, 1u << c->H_log2, c->partials, s);
+    if (e == hipSuccess && n > 0) e = launch_out_layout(c->P, vo, ko, c->osrc, s);
     return hip_status(e);
 }
 
@@ -526,7 +529,7 @@ int mpm_g2p(mpm_ctx* c, const mpm_particles* in, const mpm_particles* out, void*
     if (in->n == 0) return MPM_OK;
     const int wgs = std::min(c->g2p_wgs, c->work_cap);
     return hip_status(launch_g2p(c->P, in->x, in->F, in->id, in->inst, out->x, out->v, out->C, out->F, out->tau,
-                                 out->id, out->inst, in->n, c->order, c->skeys, wgs, (hipStream_t)stream));
+                                 out->id, out->inst, in->n, c->osrc, wgs, (hipStream_t)stream));
 }
 
 int mpm_step(mpm_ctx* c, const mpm_particles* a, const mpm_particles* b, int n_steps, void* stream) {
@@ -639,8 +642,8 @@ int mpm_get_order(mpm_ctx* c, uint32_t* order, int n, void* stream) {
     if (!c || !order || n < 0) return MPM_ERR_ARG;
     if (!c->built || n != c->built_n) return MPM_ERR_STATE;
     if (n == 0) return MPM_OK;
-    const int wgs = std::min(c->g2p_wgs, c->work_cap);
-    return hip_status(launch_out_order(c->P, c->order, c->skeys, order, wgs, (hipStream_t)stream));
+    return hip_status(
+        hipMemcpyAsync(order, c->osrc, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, (hipStream_t)stream));
 }
 
 int mpm_graph_release(mpm_ctx* c) {

@@ -107,12 +107,42 @@ __global__ __launch_bounds__(WG) void k_hash_clear(DevParams P, unsigned H) {
     }
 }
 
-// spread a 4-bit row mask to the j-rows (stride 4) / k-planes (stride 16) of a 4^d block
-__device__ __forceinline__ uint64_t spread_j(unsigned r) {
-    return (uint64_t)((r & 1u) | ((r & 2u) << 3) | ((r & 4u) << 6) | ((r & 8u) << 9));
+// Node masks from the occupied base cells of a block.  With bit i + 4 j + 16 k
+// for cell / node (i, j, k), the stencil of a base cell covers nodes +0..+2 on
+// each axis; along one axis that is a dilation inside the block ("own") and a
+// spill of cells 2 and 3 into nodes 0 and 1 of the upper neighbour ("spill").
+// The node mask of neighbour d = (dx, dy, dz) is the composition of the per-axis
+// own/spill maps selected by the bits of d.
+__device__ __forceinline__ uint64_t own_x(uint64_t o) {
+    return o | ((o << 1) & 0xEEEEEEEEEEEEEEEEull) | ((o << 2) & 0xCCCCCCCCCCCCCCCCull);
 }
-__device__ __forceinline__ uint64_t spread_k(unsigned r) {
-    return (uint64_t)(r & 1u) | ((uint64_t)(r & 2u) << 15) | ((uint64_t)(r & 4u) << 30) | ((uint64_t)(r & 8u) << 45);
+__device__ __forceinline__ uint64_t spill_x(uint64_t o) {
+    return ((o >> 2) & 0x1111111111111111ull) | ((o >> 3) & 0x1111111111111111ull) |
+           ((o >> 2) & 0x2222222222222222ull);
+}
+template <int DIM>
+__device__ __forceinline__ uint64_t own_y(uint64_t o) {
+    if (DIM == 2) return (o | (o << 4) | (o << 8)) & 0xFFFFull;
+    return o | ((o << 4) & ~0x000F000F000F000Full) | ((o << 8) & ~0x00FF00FF00FF00FFull);
+}
+template <int DIM>
+__device__ __forceinline__ uint64_t spill_y(uint64_t o) {
+    if (DIM == 2) return ((o >> 8) & 0xFull) | ((o >> 12) & 0xFull) | ((o >> 8) & 0xF0ull);
+    return ((o >> 8) & 0x000F000F000F000Full) | ((o >> 12) & 0x000F000F000F000Full) |
+           ((o >> 8) & 0x00F000F000F000F0ull);
+}
+__device__ __forceinline__ uint64_t own_z(uint64_t o) { return o | (o << 16) | (o << 32); }
+__device__ __forceinline__ uint64_t spill_z(uint64_t o) {
+    return ((o >> 32) & 0xFFFFull) | ((o >> 48) & 0xFFFFull) | ((o >> 32) & 0xFFFF0000ull);
+}
+
+template <int DIM>
+__device__ __forceinline__ uint64_t neighbour_mask(uint64_t occ, int d) {
+    uint64_t o = (d & 1) ? spill_x(occ) : own_x(occ);
+    if (DIM == 2) o &= 0xFFFFull;
+    o = (d & 2) ? spill_y<DIM>(o) : own_y<DIM>(o);
+    if (DIM == 3) o = (d & 4) ? spill_z(o) : own_z(o);
+    return o;
 }
 
 template <int DIM>
@@ -126,56 +156,35 @@ __global__ __launch_bounds__(WG) void k_hash_insert(DevParams P, const uint32_t*
     const uint32_t seg = key >> CB;                                   // instance and block
     const uint32_t bl = seg & ((1u << P.blk_bits) - 1u);              // block within the instance
     const int inst = (int)(seg >> P.blk_bits);
-    int l[3] = {(int)(key & 3u), (int)((key >> 2) & 3u), DIM == 3 ? (int)((key >> 4) & 3u) : 0};
+    const uint32_t cell = key & ((1u << CB) - 1u);
     int bc[3];
     linear_to_block<DIM>(P, bl, bc);
-    // rows of the stencil [l, l+2] inside the owner block (lo) and spilled into the upper block (hi)
-    unsigned lo[3], hi[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int top = min(l[a] + 2, 3);
-        lo[a] = ((1u << (top + 1)) - 1u) & ~((1u << l[a]) - 1u);
-        hi[a] = l[a] >= 2 ? ((1u << (l[a] - 1)) - 1u) : 0u;
-    }
-    uint64_t m[NB];
-#pragma unroll
-    for (int d = 0; d < NB; ++d) {
-        const unsigned rx = (d & 1) ? hi[0] : lo[0];
-        const unsigned ry = (d & 2) ? hi[1] : lo[1];
-        if (DIM == 3) {
-            const unsigned rz = (d & 4) ? hi[2] : lo[2];
-            m[d] = (uint64_t)rx * spread_j(ry) * spread_k(rz);
-        } else {
-            m[d] = (uint64_t)rx * spread_j(ry);
-        }
-        if (!valid) m[d] = 0ull;
-    }
     const uint64_t ko = block_key<DIM>(P, bc[0], bc[1], bc[2], inst);
     const bool is_start = valid && (i == 0 || (skeys[i - 1] >> CB) != seg);
     const bool is_end = valid && (i == n - 1 || (skeys[i + 1] >> CB) != seg);
 
+    // one pass per distinct owner block in the wave (the keys are sorted, so
+    // usually one or two): OR the base-cell bits of its lanes, derive the node
+    // masks of the block and its upper neighbours, and let lane d insert
+    // neighbour d
     unsigned long long todo = __ballot(valid);
     while (todo) {
         const int leader = __ffsll((long long)todo) - 1;
         const uint64_t K = readlane64(ko, leader);
         const bool mine = valid && ko == K;
         const unsigned long long grp = __ballot(mine);
+        const uint64_t occ = readlane64(wave_or64(mine ? (1ull << cell) : 0ull), leader);
         const int lbx = readlane32(bc[0], leader), lby = readlane32(bc[1], leader), lbz = readlane32(bc[2], leader);
         const int lin = readlane32(inst, leader);
-        uint64_t mymask = 0ull;
-#pragma unroll
-        for (int d = 0; d < NB; ++d) {
-            const unsigned long long any = __ballot(mine && m[d] != 0ull);
-            if (any) {
-                const uint64_t r = wave_or64(mine ? m[d] : 0ull);
-                if (lane == d) mymask = r;
-            }
-        }
         int slot = -1;
-        if (lane < NB && mymask != 0ull) {
-            const uint64_t Kd = block_key<DIM>(P, lbx + (lane & 1), lby + ((lane >> 1) & 1), lbz + ((lane >> 2) & 1), lin);
-            slot = hash_insert(P, Kd);
-            if (slot >= 0) atomicOr((unsigned long long*)&P.h_mask[slot], (unsigned long long)mymask);
+        if (lane < NB) {
+            const uint64_t mymask = neighbour_mask<DIM>(occ, lane);
+            if (mymask != 0ull) {
+                const uint64_t Kd =
+                    block_key<DIM>(P, lbx + (lane & 1), lby + ((lane >> 1) & 1), lbz + ((lane >> 2) & 1), lin);
+                slot = hash_insert(P, Kd);
+                if (slot >= 0) atomicOr((unsigned long long*)&P.h_mask[slot], (unsigned long long)mymask);
+            }
         }
         const int so = readlane32(slot, 0);
         if (mine && so >= 0) {

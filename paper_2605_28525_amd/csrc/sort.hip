@@ -28,12 +28,17 @@ __global__ __launch_bounds__(WG) void k_radix_hist(const uint32_t* __restrict__ 
     __syncthreads();
     const int w = threadIdx.x >> 6, lane = __lane_id();
     const int base = blockIdx.x * SORT_TILE + w * (SORT_TILE / (WG / 64));
-#pragma unroll 4
+    // all loads of the wave's keys first (one round trip), then the ranking
+    uint32_t k[SORT_ITEMS];
+#pragma unroll
     for (int r = 0; r < SORT_ITEMS; ++r) {
         const int pos = base + r * 64 + lane;
-        const bool valid = pos < n;
-        const uint32_t k = valid ? keys[pos] : 0u;
-        const unsigned dg = (k >> shift) & 255u;
+        k[r] = pos < n ? keys[pos] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < SORT_ITEMS; ++r) {
+        const bool valid = base + r * 64 + lane < n;
+        const unsigned dg = (k[r] >> shift) & 255u;
         const unsigned long long m = digit_match(dg, valid);
         if (valid && (__ffsll((long long)m) - 1) == lane) cnt[w][dg] += (unsigned)__popcll(m);
     }
@@ -61,6 +66,11 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t* __restrict
         const bool valid = pos < n;
         k[r] = valid ? kin[pos] : 0u;
         v[r] = valid ? (vin ? vin[pos] : (uint32_t)pos) : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < SORT_ITEMS; ++r) {
+        const int pos = base + r * 64 + lane;
+        const bool valid = pos < n;
         const unsigned dg = (k[r] >> shift) & 255u;
         const unsigned long long m = digit_match(dg, valid);
         const unsigned cur = run[w][dg];

@@ -422,15 +422,13 @@ struct G2POut {
 
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_g2p(DevParams P, G2PIn in, G2POut out, int n,
-                                            const uint32_t* __restrict__ order, const uint32_t* __restrict__ skeys) {
+                                            const uint32_t* __restrict__ osrc) {
     using T = Tile<DIM>;
     constexpr int NS = DIM == 3 ? 6 : 3;
     constexpr int DD = DIM * DIM;
     __shared__ float4 vt[T::N];
     __shared__ float xs[DIM][G2P_MAX_ITEM];
     __shared__ float fs[DD][G2P_MAX_ITEM];
-    __shared__ int src[G2P_MAX_ITEM];
-    __shared__ Interleave<DIM> il;
     __shared__ int nbr[T::NB];
     __shared__ int org[4];
     const int n_work = min(P.ctr->n_work, P.work_cap);
@@ -448,22 +446,13 @@ __global__ __launch_bounds__(WG) void k_g2p(DevParams P, G2PIn in, G2POut out, i
             org[2] = bc[2] * BLK;
             org[3] = inst;
         }
-        // The work item writes output positions s .. s+L-1 (contiguous, so the
-        // stores below coalesce); find the sorted position stored at each.
-        {
-            const int st = P.b_start[blk], en = st + P.b_count[blk];
-            interleave_setup<DIM>(il, skeys, st, en);
-            for (int i = st + (int)threadIdx.x; i < en; i += WG) {
-                const int o = interleave_pos<DIM>(il, i, skeys[i]) - s;
-                if (o >= 0 && o < L) src[o] = i;
-            }
-            __syncthreads();
-        }
         // phase 0: issue every global gather of the work item up front
-        // (positions, deformation gradients, ids) and stage them in LDS
+        // (positions, deformation gradients, ids) and stage them in LDS.  The
+        // work item writes output positions s .. s+L-1 (contiguous, so every
+        // store below coalesces); osrc names the input particle of each.
 #pragma unroll 2
         for (int r = threadIdx.x; r < L; r += WG) {
-            const size_t q = order[src[r]];
+            const size_t q = osrc[s + r];
 #pragma unroll
             for (int a = 0; a < DIM; ++a) xs[a][r] = in.x[(size_t)a * n + q];
 #pragma unroll
@@ -624,37 +613,42 @@ hipError_t launch_grid_update(const DevParams& P, long long n_nodes_host, int gr
 
 hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, const uint32_t* id_in,
                       const uint32_t* inst_in, float* x_out, float* v_out, float* C_out, float* F_out, float* tau_out,
-                      uint32_t* id_out, uint32_t* inst_out, int n, const uint32_t* order, const uint32_t* skeys,
-                      int grid_blocks, hipStream_t s) {
+                      uint32_t* id_out, uint32_t* inst_out, int n, const uint32_t* osrc, int grid_blocks,
+                      hipStream_t s) {
     G2PIn in{x_in, F_in, id_in, inst_in};
     G2POut out{x_out, v_out, C_out, F_out, tau_out, id_out, inst_out};
     if (P.dim == 3)
-        k_g2p<3><<<grid_blocks, WG, 0, s>>>(P, in, out, n, order, skeys);
+        k_g2p<3><<<grid_blocks, WG, 0, s>>>(P, in, out, n, osrc);
     else
-        k_g2p<2><<<grid_blocks, WG, 0, s>>>(P, in, out, n, order, skeys);
+        k_g2p<2><<<grid_blocks, WG, 0, s>>>(P, in, out, n, osrc);
     return hipGetLastError();
 }
 
-// Output position -> input index map of the G2P of the last build.
+// Output layout of the G2P of this build: osrc[o] = input index of the
+// particle that G2P stores at position o (blocks in sort order, rank-major
+// inside a block).  One workgroup per owner block.
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_out_order(DevParams P, const uint32_t* __restrict__ order,
-                                                  const uint32_t* __restrict__ skeys, uint32_t* __restrict__ out) {
+__global__ __launch_bounds__(WG) void k_out_layout(DevParams P, const uint32_t* __restrict__ order,
+                                                   const uint32_t* __restrict__ skeys, uint32_t* __restrict__ osrc) {
     __shared__ Interleave<DIM> il;
-    const int n_work = min(P.ctr->n_work, P.work_cap);
-    for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
-        const int blk = P.w_block[w], s = P.w_start[w], e = P.w_end[w];
-        interleave_setup<DIM>(il, skeys, P.b_start[blk], P.b_start[blk] + P.b_count[blk]);
-        for (int i = s + (int)threadIdx.x; i < e; i += WG) out[interleave_pos<DIM>(il, i, skeys[i])] = order[i];
+    const int nb = min(P.ctr->nb, P.block_cap);
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        const int cnt = P.b_count[b];
+        if (cnt <= 0) continue;
+        const int st = P.b_start[b], en = st + cnt;
+        interleave_setup<DIM>(il, skeys, st, en);
+        for (int i = st + (int)threadIdx.x; i < en; i += WG) osrc[interleave_pos<DIM>(il, i, skeys[i])] = order[i];
         __syncthreads();
     }
 }
 
-hipError_t launch_out_order(const DevParams& P, const uint32_t* order, const uint32_t* skeys, uint32_t* out,
-                            int grid_blocks, hipStream_t s) {
+hipError_t launch_out_layout(const DevParams& P, const uint32_t* order, const uint32_t* skeys, uint32_t* osrc,
+                             hipStream_t s) {
+    const int g = P.dense ? 65536 : 8192;
     if (P.dim == 3)
-        k_out_order<3><<<grid_blocks, WG, 0, s>>>(P, order, skeys, out);
+        k_out_layout<3><<<g, WG, 0, s>>>(P, order, skeys, osrc);
     else
-        k_out_order<2><<<grid_blocks, WG, 0, s>>>(P, order, skeys, out);
+        k_out_layout<2><<<g, WG, 0, s>>>(P, order, skeys, osrc);
     return hipGetLastError();
 }
 
