@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=400)
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=200)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of this many MiB (a kernel of known traffic "
@@ -174,7 +175,8 @@ def ensemble_leg(steps, stream):
     log(f"bench: ensemble of {ens.n_instances} instances, {n} particles")
     sim = M.Simulation(ens)
     chosen = M.mpm_autotune(sim.ctx, sim.a.view(), sim.b.view(), stream)
-    log(f"bench: ensemble autotune -> chunk {chosen[0]}, p2g wgs {chosen[1]}, g2p wgs {chosen[2]}")
+    log(f"bench: ensemble autotune -> chunk {chosen[0]}, g2p block {chosen[1]}, p2g wgs {chosen[2]}, "
+        f"g2p wgs {chosen[3]}")
     M.mpm_graph_capture(sim.ctx, sim.a.view(), sim.b.view(), 2, stream)
     M.mpm_graph_launch(sim.ctx, 1, stream)
     torch.cuda.synchronize()
@@ -211,8 +213,8 @@ def ensemble_leg(steps, stream):
     torch.cuda.empty_cache()
     return {"workload": ens.name, "instances": ens.n_instances, "particles": n,
             "particles_min": min(m.n for m in ens.members), "particles_max": max(m.n for m in ens.members),
-            "steps": steps, "active_blocks": nb, "tuning": {"chunk": chosen[0], "p2g_workgroups": chosen[1],
-                                                             "g2p_workgroups": chosen[2]},
+            "steps": steps, "active_blocks": nb, "tuning": {"chunk": chosen[0], "g2p_block": chosen[1],
+                                                             "p2g_workgroups": chosen[2], "g2p_workgroups": chosen[3]},
             "batched": {"value": n * steps / t_batch, "ms_per_step": 1e3 * t_batch / steps, "graph": True},
             "sequential": {"value": n * steps / t_seq, "ms_per_step": 1e3 * t_seq / steps, "graph": False},
             "speedup": t_seq / t_batch, "unit": "particle-steps/s"}
@@ -299,6 +301,11 @@ def main():
     rc, flags = sim.status()
     if rc != 0:
         raise SystemExit(f"device status after warmup: {rc} flags={flags}")
+    tuning = None
+    if not args.no_autotune:
+        chosen = M.mpm_autotune(sim.ctx, sim.a.view(), sim.b.view(), stream)
+        tuning = dict(zip(("chunk", "g2p_block", "p2g_workgroups", "g2p_workgroups"), chosen))
+        log(f"bench: autotune -> {tuning}")
     nb, nt = M.mpm_active_count(sim.ctx)
     log(f"bench: timed {args.steps} steps (active blocks {nb})")
     t, ph = time_steps(sim, args.steps, stream)
@@ -340,6 +347,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "phases_ms": ph,
+        "tuning": tuning,
         "build_ms_per_step": ph["build"],
         "build_roofline_frac": build_bytes / (ph["build"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "step_roofline_frac": step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,

@@ -268,19 +268,21 @@ int mpm_graph_capture(mpm_ctx* ctx, const mpm_particles* a, const mpm_particles*
 int mpm_graph_launch(mpm_ctx* ctx, int times, void* stream);
 int mpm_graph_release(mpm_ctx* ctx);
 
-/* Launch shape of the transfer kernels: particles per G2P / P2G-adjoint work
- * item (64..512) and persistent workgroup counts of the P2G and G2P launches
- * (0 = keep).  Takes effect on the next step; a captured graph keeps the shape
- * it was recorded with. */
-int mpm_set_tuning(mpm_ctx* ctx, int chunk, int p2g_workgroups, int g2p_workgroups);
+/* Launch shape of the transfer kernels: particles per work item `chunk`
+ * (64..512, used by G2P and the reverse kernels), G2P workgroup size
+ * `g2p_block` (64, 128 or 256; chunk <= 2 g2p_block) and the persistent
+ * workgroup counts of the P2G and G2P launches.  0 keeps a value.  Takes
+ * effect on the next build; a captured graph keeps the shape it was recorded
+ * with.  MPM_ERR_ARG for values out of range. */
+int mpm_set_tuning(mpm_ctx* ctx, int chunk, int g2p_block, int p2g_workgroups, int g2p_workgroups);
 
-/* Autotuner: for every candidate launch shape (work-item size in {128, 256,
- * 512} x persistent workgroups in {1024, 2048, 4096, 8192}) runs one warm-up
- * and 3 timed steps that read a and write b (a is left unchanged; b ends one
- * step ahead of a), keeps the fastest P2G workgroup count and the fastest
- * G2P (work-item size, workgroup count) pair, and reports them in chosen[3]
- * = {chunk, p2g_workgroups, g2p_workgroups} (host ints, may be NULL).
- * Synchronises the stream. */
+/* Autotuner: for every candidate launch shape ((g2p_block, chunk) in {(64,
+ * 64), (64, 128), (128, 128), (128, 256), (256, 256), (256, 512)} x persistent
+ * workgroups in {1024, 2048, 4096, 8192}) runs one warm-up and 3 timed steps
+ * that read a and write b (a is left unchanged; b ends one step ahead of a),
+ * keeps the fastest P2G workgroup count and the fastest G2P shape, and
+ * reports them in chosen[4] = {chunk, g2p_block, p2g_workgroups,
+ * g2p_workgroups} (host ints, may be NULL).  Synchronises the stream. */
 int mpm_autotune(mpm_ctx* ctx, const mpm_particles* a, const mpm_particles* b, int* chosen, void* stream);
 
 /* Replaces the material constants (E, nu, friction angle) and dt of a live

@@ -28,6 +28,7 @@ struct mpm_ctx {
     bool dense = false;
     int p2g_wgs = 2048;     // persistent workgroups of the P2G launch
     int g2p_wgs = 2048;     // persistent workgroups of the G2P launch
+    int g2p_block = 256;    // threads per G2P workgroup (work items of at most twice as many particles)
     int n_inst = 1;
     int blk_bits = 0;
     InstMat* inst = nullptr;  // device table of per-instance constants (ensembles)
@@ -396,7 +397,7 @@ int mpm_create(const mpm_params* q, mpm_ctx** out) {
     }
     if (const char* ch = getenv("MPMX_CHUNK")) {
         int v = atoi(ch);
-        if (v >= MIN_CHUNK && v <= 512) c->chunk = v;
+        if (v >= MIN_CHUNK && v <= MAX_CHUNK) c->chunk = v;
     }
     if (const char* pw = getenv("MPMX_WGS")) {
         int v = atoi(pw);
@@ -529,7 +530,7 @@ int mpm_g2p(mpm_ctx* c, const mpm_particles* in, const mpm_particles* out, void*
     if (in->n == 0) return MPM_OK;
     const int wgs = std::min(c->g2p_wgs, c->work_cap);
     return hip_status(launch_g2p(c->P, in->x, in->F, in->id, in->inst, out->x, out->v, out->C, out->F, out->tau,
-                                 out->id, out->inst, in->n, c->osrc, wgs, (hipStream_t)stream));
+                                 out->id, out->inst, in->n, c->osrc, c->g2p_block, wgs, (hipStream_t)stream));
 }
 
 int mpm_step(mpm_ctx* c, const mpm_particles* a, const mpm_particles* b, int n_steps, void* stream) {
@@ -688,16 +689,20 @@ int mpm_graph_launch(mpm_ctx* c, int times, void* stream) {
     return MPM_OK;
 }
 
-int mpm_set_tuning(mpm_ctx* c, int chunk, int p2g_workgroups, int g2p_workgroups) {
+int mpm_set_tuning(mpm_ctx* c, int chunk, int g2p_block, int p2g_workgroups, int g2p_workgroups) {
     if (!c) return MPM_ERR_ARG;
-    if (chunk != 0 && (chunk < MIN_CHUNK || chunk > 512)) return MPM_ERR_ARG;
+    if (chunk != 0 && (chunk < MIN_CHUNK || chunk > MAX_CHUNK)) return MPM_ERR_ARG;
+    if (g2p_block != 0 && g2p_block != 64 && g2p_block != 128 && g2p_block != 256) return MPM_ERR_ARG;
     if (p2g_workgroups < 0 || p2g_workgroups > (1 << 20) || g2p_workgroups < 0 || g2p_workgroups > (1 << 20))
         return MPM_ERR_ARG;
-    if (chunk) {
-        c->chunk = chunk;
-        c->P.chunk = chunk;
+    const int new_chunk = chunk ? chunk : c->chunk;
+    const int new_block = g2p_block ? g2p_block : c->g2p_block;
+    if (new_chunk > 2 * new_block) return MPM_ERR_ARG;
+    if (new_chunk != c->chunk) {
+        c->chunk = c->P.chunk = new_chunk;
         c->built = false;  // work items of the last build used the old size
     }
+    c->g2p_block = new_block;
     if (p2g_workgroups) c->p2g_wgs = p2g_workgroups;
     if (g2p_workgroups) c->g2p_wgs = g2p_workgroups;
     return MPM_OK;
@@ -706,20 +711,22 @@ int mpm_set_tuning(mpm_ctx* c, int chunk, int p2g_workgroups, int g2p_workgroups
 int mpm_autotune(mpm_ctx* c, const mpm_particles* a, const mpm_particles* b, int* chosen, void* stream) {
     if (!c || !particles_ok(c, a, true) || !b || b->n != a->n) return MPM_ERR_ARG;
     hipStream_t s = (hipStream_t)stream;
-    static const int chunks[] = {128, 256, 512};
+    // (G2P workgroup size, particles per work item) pairs, persistent workgroup counts
+    static const int shapes[][2] = {{64, 64}, {64, 128}, {128, 128}, {128, 256}, {256, 256}, {256, 512}};
     static const int wgs[] = {1024, 2048, 4096, 8192};
-    constexpr int NC = 3, NW = 4, REPS = 3;
+    constexpr int NS = 6, NW = 4, REPS = 3;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     int st = MPM_OK;
     for (int i = 0; i < 4 && st == MPM_OK; ++i)
         if (hipEventCreate(&ev[i]) != hipSuccess) st = MPM_ERR_HIP;
-    double p2g_ms[NW] = {0}, g2p_ms[NC][NW] = {{0}};
+    double p2g_ms[NW] = {0}, g2p_ms[NS][NW] = {{0}};
     // Every trial reads a and writes b, so a is left as it was.  P2G does not
-    // depend on the work-item size: its time per workgroup count is summed
-    // over the work-item sizes.
-    for (int ci = 0; ci < NC && st == MPM_OK; ++ci) {
+    // depend on the G2P shape: its time per workgroup count is summed over
+    // the shapes.
+    for (int si = 0; si < NS && st == MPM_OK; ++si) {
         for (int wi = 0; wi < NW && st == MPM_OK; ++wi) {
-            c->chunk = c->P.chunk = chunks[ci];
+            c->g2p_block = shapes[si][0];
+            c->chunk = c->P.chunk = shapes[si][1];
             c->p2g_wgs = c->g2p_wgs = wgs[wi];
             for (int r = 0; r <= REPS && st == MPM_OK; ++r) {
                 st = mpm_sparse_build(c, a, s);
@@ -737,27 +744,29 @@ int mpm_autotune(mpm_ctx* c, const mpm_particles* a, const mpm_particles* b, int
                     hipEventElapsedTime(&t_g2p, ev[2], ev[3]) != hipSuccess)
                     st = MPM_ERR_HIP;
                 p2g_ms[wi] += t_p2g;
-                g2p_ms[ci][wi] += t_g2p;
+                g2p_ms[si][wi] += t_g2p;
             }
         }
     }
     for (int i = 0; i < 4; ++i)
         if (ev[i]) (void)hipEventDestroy(ev[i]);
     if (st != MPM_OK) return st;
-    int best_p2g = 0, best_c = 0, best_w = 0;
+    int best_p2g = 0, best_s = 0, best_w = 0;
     for (int wi = 1; wi < NW; ++wi)
         if (p2g_ms[wi] < p2g_ms[best_p2g]) best_p2g = wi;
-    for (int ci = 0; ci < NC; ++ci)
+    for (int si = 0; si < NS; ++si)
         for (int wi = 0; wi < NW; ++wi)
-            if (g2p_ms[ci][wi] < g2p_ms[best_c][best_w]) best_c = ci, best_w = wi;
-    c->chunk = c->P.chunk = chunks[best_c];
+            if (g2p_ms[si][wi] < g2p_ms[best_s][best_w]) best_s = si, best_w = wi;
+    c->g2p_block = shapes[best_s][0];
+    c->chunk = c->P.chunk = shapes[best_s][1];
     c->p2g_wgs = wgs[best_p2g];
     c->g2p_wgs = wgs[best_w];
     c->built = false;
     if (chosen) {
         chosen[0] = c->chunk;
-        chosen[1] = c->p2g_wgs;
-        chosen[2] = c->g2p_wgs;
+        chosen[1] = c->g2p_block;
+        chosen[2] = c->p2g_wgs;
+        chosen[3] = c->g2p_wgs;
     }
     return MPM_OK;
 }

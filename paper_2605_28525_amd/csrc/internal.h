@@ -32,6 +32,7 @@ constexpr int SORT_TILE = WG * SORT_ITEMS;     // 4096 keys per tile
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = WG * SCAN_ITEMS;     // 2048 values per scan tile
 constexpr int MIN_CHUNK = 64;                  // smallest particles-per-work-item setting
+constexpr int MAX_CHUNK = 512;                 // largest (G2P stages a work item in LDS)
 
 struct DevCounters {
     int nb;          // active blocks (compact count, <= capacity)
@@ -292,8 +293,8 @@ hipError_t launch_p2g(const DevParams& P, const float* x, const float* v, const 
 hipError_t launch_grid_update(const DevParams& P, long long n_nodes_host, int grid_blocks, hipStream_t s);
 hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, const uint32_t* id_in,
                       const uint32_t* inst_in, float* x_out, float* v_out, float* C_out, float* F_out, float* tau_out,
-                      uint32_t* id_out, uint32_t* inst_out, int n, const uint32_t* osrc, int grid_blocks,
-                      hipStream_t s);
+                      uint32_t* id_out, uint32_t* inst_out, int n, const uint32_t* osrc, int block_size,
+                      int grid_blocks, hipStream_t s);
 hipError_t launch_out_layout(const DevParams& P, const uint32_t* order, const uint32_t* skeys, uint32_t* osrc,
                              hipStream_t s);
 hipError_t launch_clear_flags(DevCounters* c, hipStream_t s);

@@ -8,7 +8,6 @@
 
 namespace mpmx {
 
-constexpr int G2P_MAX_ITEM = 512;     // particles per G2P work item (LDS staging)
 constexpr int P2G_ORDER_STAGE = 1024; // sort permutation entries staged per P2G block
 
 template <int DIM>

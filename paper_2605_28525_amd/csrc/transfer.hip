@@ -420,15 +420,17 @@ struct G2POut {
     uint32_t* inst;
 };
 
-template <int DIM>
-__global__ __launch_bounds__(WG) void k_g2p(DevParams P, G2PIn in, G2POut out, int n,
+// GS threads per workgroup, work items of at most 2 GS particles.
+template <int DIM, int GS>
+__global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, int n,
                                             const uint32_t* __restrict__ osrc) {
     using T = Tile<DIM>;
     constexpr int NS = DIM == 3 ? 6 : 3;
     constexpr int DD = DIM * DIM;
     __shared__ float4 vt[T::N];
-    __shared__ float xs[DIM][G2P_MAX_ITEM];
-    __shared__ float fs[DD][G2P_MAX_ITEM];
+    constexpr int MAXI = 2 * GS;
+    __shared__ float xs[DIM][MAXI];
+    __shared__ float fs[DD][MAXI];
     __shared__ int nbr[T::NB];
     __shared__ int org[4];
     const int n_work = min(P.ctr->n_work, P.work_cap);
@@ -436,7 +438,7 @@ __global__ __launch_bounds__(WG) void k_g2p(DevParams P, G2PIn in, G2POut out, i
     const float cscale = 4.f * inv_dx * inv_dx;  // D_p^{-1} = (4/dx^2) I for quadratic B-splines
     for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
         const int blk = P.w_block[w], s = P.w_start[w];
-        const int L = min(P.w_end[w] - s, G2P_MAX_ITEM);
+        const int L = min(P.w_end[w] - s, MAXI);
         if (threadIdx.x < T::NB) nbr[threadIdx.x] = P.b_nbr[blk * T::NB + threadIdx.x];
         if (threadIdx.x == 0) {
             int bc[3], inst;
@@ -451,7 +453,7 @@ __global__ __launch_bounds__(WG) void k_g2p(DevParams P, G2PIn in, G2POut out, i
         // work item writes output positions s .. s+L-1 (contiguous, so every
         // store below coalesces); osrc names the input particle of each.
 #pragma unroll 2
-        for (int r = threadIdx.x; r < L; r += WG) {
+        for (int r = threadIdx.x; r < L; r += GS) {
             const size_t q = osrc[s + r];
 #pragma unroll
             for (int a = 0; a < DIM; ++a) xs[a][r] = in.x[(size_t)a * n + q];
@@ -463,7 +465,7 @@ __global__ __launch_bounds__(WG) void k_g2p(DevParams P, G2PIn in, G2POut out, i
         __syncthreads();
         const InstMat mat = material(P, org[3]);
         const float dt = mat.dt;
-        for (int t = threadIdx.x; t < T::N; t += WG) {
+        for (int t = threadIdx.x; t < T::N; t += GS) {
             const int I = t % T::E, J = (t / T::E) % T::E, K = DIM == 3 ? t / (T::E * T::E) : 0;
             const int d = (I >> 2) | ((J >> 2) << 1) | ((K >> 2) << 2);
             const int phi = nbr[d];
@@ -474,7 +476,7 @@ __global__ __launch_bounds__(WG) void k_g2p(DevParams P, G2PIn in, G2POut out, i
         // phase 1: grid gather, new position, velocity and affine matrix,
         // F_trial = (I + dt grad v) F (Eq. 17) kept in LDS
 #pragma unroll 1
-        for (int r = threadIdx.x; r < L; r += WG) {
+        for (int r = threadIdx.x; r < L; r += GS) {
             float xp[3] = {0, 0, 0};
 #pragma unroll
             for (int a = 0; a < DIM; ++a) xp[a] = xs[a][r];
@@ -568,7 +570,7 @@ __global__ __launch_bounds__(WG) void k_g2p(DevParams P, G2PIn in, G2POut out, i
         __syncthreads();
         // phase 2: constitutive update (its register live range is separate)
 #pragma unroll 1
-        for (int r = threadIdx.x; r < L; r += WG) {
+        for (int r = threadIdx.x; r < L; r += GS) {
             const size_t o = (size_t)(s + r);
             float Ft[3][3], Fn[3][3], tau6[6];
 #pragma unroll
@@ -613,14 +615,20 @@ hipError_t launch_grid_update(const DevParams& P, long long n_nodes_host, int gr
 
 hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, const uint32_t* id_in,
                       const uint32_t* inst_in, float* x_out, float* v_out, float* C_out, float* F_out, float* tau_out,
-                      uint32_t* id_out, uint32_t* inst_out, int n, const uint32_t* osrc, int grid_blocks,
-                      hipStream_t s) {
+                      uint32_t* id_out, uint32_t* inst_out, int n, const uint32_t* osrc, int block_size,
+                      int grid_blocks, hipStream_t s) {
     G2PIn in{x_in, F_in, id_in, inst_in};
     G2POut out{x_out, v_out, C_out, F_out, tau_out, id_out, inst_out};
-    if (P.dim == 3)
-        k_g2p<3><<<grid_blocks, WG, 0, s>>>(P, in, out, n, osrc);
-    else
-        k_g2p<2><<<grid_blocks, WG, 0, s>>>(P, in, out, n, osrc);
+    if (2 * block_size < P.chunk) return hipErrorInvalidValue;  // work items must fit the LDS staging
+    switch (block_size * 4 + P.dim) {
+        case 64 * 4 + 3: k_g2p<3, 64><<<grid_blocks, 64, 0, s>>>(P, in, out, n, osrc); break;
+        case 128 * 4 + 3: k_g2p<3, 128><<<grid_blocks, 128, 0, s>>>(P, in, out, n, osrc); break;
+        case 256 * 4 + 3: k_g2p<3, 256><<<grid_blocks, 256, 0, s>>>(P, in, out, n, osrc); break;
+        case 64 * 4 + 2: k_g2p<2, 64><<<grid_blocks, 64, 0, s>>>(P, in, out, n, osrc); break;
+        case 128 * 4 + 2: k_g2p<2, 128><<<grid_blocks, 128, 0, s>>>(P, in, out, n, osrc); break;
+        case 256 * 4 + 2: k_g2p<2, 256><<<grid_blocks, 256, 0, s>>>(P, in, out, n, osrc); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -102,7 +102,7 @@ _SIGS = {
     "mpm_graph_capture": (c_int, [_PCTX, POINTER(mpm_particles), POINTER(mpm_particles), c_int, c_void_p]),
     "mpm_graph_launch": (c_int, [_PCTX, c_int, c_void_p]),
     "mpm_graph_release": (c_int, [_PCTX]),
-    "mpm_set_tuning": (c_int, [_PCTX, c_int, c_int, c_int]),
+    "mpm_set_tuning": (c_int, [_PCTX, c_int, c_int, c_int, c_int]),
     "mpm_autotune": (c_int, [_PCTX, POINTER(mpm_particles), POINTER(mpm_particles), POINTER(c_int), c_void_p]),
 }
 
@@ -240,13 +240,14 @@ def mpm_graph_release(ctx):
     _check(lib.mpm_graph_release(ctx), "mpm_graph_release")
 
 
-def mpm_set_tuning(ctx, chunk: int = 0, p2g_workgroups: int = 0, g2p_workgroups: int = 0):
-    _check(lib.mpm_set_tuning(ctx, int(chunk), int(p2g_workgroups), int(g2p_workgroups)), "mpm_set_tuning")
+def mpm_set_tuning(ctx, chunk: int = 0, g2p_block: int = 0, p2g_workgroups: int = 0, g2p_workgroups: int = 0):
+    _check(lib.mpm_set_tuning(ctx, int(chunk), int(g2p_block), int(p2g_workgroups), int(g2p_workgroups)),
+           "mpm_set_tuning")
 
 
 def mpm_autotune(ctx, a: mpm_particles, b: mpm_particles, stream=None):
-    """Returns the chosen (chunk, p2g_workgroups, g2p_workgroups)."""
-    out = (c_int * 3)()
+    """Returns the chosen (chunk, g2p_block, p2g_workgroups, g2p_workgroups)."""
+    out = (c_int * 4)()
     _check(lib.mpm_autotune(ctx, ctypes.byref(a), ctypes.byref(b), out, _stream(stream)), "mpm_autotune")
     return tuple(int(v) for v in out)
 

@@ -197,8 +197,9 @@ def test_autotune_leaves_input_and_steps_correctly():
     e = M.Simulation(ens)
     try:
         before = t.a.to_arrays()
-        chunk, p2g_wg, g2p_wg = M.mpm_autotune(t.ctx, t.a.view(), t.b.view())
-        assert chunk in (128, 256, 512) and p2g_wg in (1024, 2048, 4096, 8192) and g2p_wg in (1024, 2048, 4096, 8192)
+        chunk, g2p_block, p2g_wg, g2p_wg = M.mpm_autotune(t.ctx, t.a.view(), t.b.view())
+        assert (g2p_block, chunk) in ((64, 64), (64, 128), (128, 128), (128, 256), (256, 256), (256, 512))
+        assert p2g_wg in (1024, 2048, 4096, 8192) and g2p_wg in (1024, 2048, 4096, 8192)
         after = t.a.to_arrays()
         for k in FIELDS:
             assert np.array_equal(before[k], after[k]), f"autotune changed input {k}"
@@ -231,3 +232,45 @@ def test_bad_instance_id_is_reported():
         assert rc == M.MPM_ERR_DOMAIN and flags & M.MPM_FLAG_DOMAIN
     finally:
         s.close()
+
+
+def test_g2p_launch_shapes_agree():
+    """Every G2P launch shape the tuner may pick computes the same step: with
+    one build and one grid, the three workgroup sizes give bit-identical
+    particles; across work-item sizes (a new build and P2G each) the step
+    agrees at the parity bar."""
+    import torch
+    from paper_2605_28525_amd import mpm as M
+    w = wl.perturbed(wl.collapse_3d(seed=2, scale=2), seed=5)
+    _announce("g2p launch shapes", w.n)
+    sim = M.Simulation(w)
+    try:
+        a, b = sim.a.view(), sim.b.view()
+        M.mpm_set_tuning(sim.ctx, 128, 128, 0, 0)
+        M.mpm_sparse_build(sim.ctx, a)
+        M.mpm_p2g(sim.ctx, a)
+        M.mpm_grid_update(sim.ctx)
+        outs = []
+        for blk in (64, 128, 256):
+            M.mpm_set_tuning(sim.ctx, 0, blk, 0, 0)
+            sim.b.zero_()
+            M.mpm_g2p(sim.ctx, a, b)
+            assert M.mpm_get_status(sim.ctx)[0] == 0
+            outs.append(sim.b.to_arrays())
+        for o in outs[1:]:
+            for k in FIELDS:
+                assert np.array_equal(o[k], outs[0][k]), k
+        ids = np.arange(w.n)
+        ref = None
+        for blk, chunk in ((256, 512), (64, 64), (64, 128), (128, 256), (256, 256)):
+            M.mpm_set_tuning(sim.ctx, chunk, blk, 0, 0)
+            M.mpm_step(sim.ctx, a, b, 1)
+            assert M.mpm_get_status(sim.ctx)[0] == 0
+            got = _by_id(sim.b, ids)
+            if ref is None:
+                ref = got
+                continue
+            for k in FIELDS:
+                assert_field(f"shape {blk}/{chunk} {k}", got[k], ref[k], RTOL, atol=tau_floor(w) if k == "tau" else 0.0)
+    finally:
+        sim.close()
