@@ -325,7 +325,7 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k][1])
     dom_bytes, dom_ms = kernels[dom]
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    digest = src_digest("transfer.hip", "internal.h")
+    digest = src_digest("transfer.hip", "particle.h", "internal.h")
     traffic = measured_traffic(dom, args.workload, digest)
     build_bytes = n * 16 + 24 * (1 << max(10, int(np.ceil(np.log2(2 * cap))))) + 16 * nb
     step_bytes = (276 if d == 3 else 148) * n + (72 if d == 3 else 52) * n_slot
