@@ -154,9 +154,12 @@ __device__ void interleave_setup(Interleave<DIM>& L, const uint32_t* __restrict_
         const int ovf = max(cnt - IL_ROUNDS, 0);
         const int inc = (int)wave_incl_scan((unsigned)ovf);
         if (lane < NC) L.op[lane] = inc - ovf;
+        // ranks at or beyond the largest count are never looked up, and
+        // R[IL_ROUNDS] only when some cell overflows (then no early exit)
         int acc = 0;
         for (int j = 0; j < IL_ROUNDS; ++j) {
             const unsigned long long m = __ballot(cnt > j);
+            if (m == 0ull) break;
             if (lane == 0) {
                 L.mask[j] = m;
                 L.R[j] = acc;

@@ -293,33 +293,30 @@ __global__ __launch_bounds__(WG) void k_grid_update(DevParams P, long long n_nod
     }
 }
 
+// C = A B for symmetric A, B that commute (polynomials in one matrix), so C
+// is symmetric: upper triangle computed, mirrored.
 template <int DIM>
-__device__ __forceinline__ unsigned constitutive(int model, const InstMat& P, const float (*Ft)[3], float (*Fn)[3],
-                                                 float* tau6) {
-    unsigned flags = 0;
-    float det;
-    if (DIM == 3)
-        det = Ft[0][0] * (Ft[1][1] * Ft[2][2] - Ft[1][2] * Ft[2][1]) -
-              Ft[0][1] * (Ft[1][0] * Ft[2][2] - Ft[1][2] * Ft[2][0]) +
-              Ft[0][2] * (Ft[1][0] * Ft[2][1] - Ft[1][1] * Ft[2][0]);
-    else
-        det = Ft[0][0] * Ft[1][1] - Ft[0][1] * Ft[1][0];
-    if (!(det > 0.f)) flags |= MPM_FLAG_INVERTED;
-    // M = F F^T - I = H + H^T + H H^T with H = F - I
-    float Hm[3][3], M[3][3], U[3][3];
+__device__ __forceinline__ void sym_mul(const float (*A)[3], const float (*B)[3], float (*C)[3]) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < DIM; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) Hm[a][b] = (a < DIM && b < DIM) ? Ft[a][b] - (a == b ? 1.f : 0.f) : 0.f;
+        for (int b = a; b < DIM; ++b) {
+            float s2 = 0.f;
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            float s = Hm[a][b] + Hm[b][a];
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) s += Hm[a][c] * Hm[b][c];
-            M[a][b] = s;
+            for (int c = 0; c < DIM; ++c) s2 += A[a][c] * B[c][b];
+            C[a][b] = s2;
+            C[b][a] = s2;
         }
+}
+
+constexpr float SERIES_MAX_NORM2 = 1.f / 64.f;  // |F F^T - I|_F^2 limit of the series path
+
+// Eigen path: Jacobi on M = F F^T - I, Hencky strain and return map on the
+// principal values, tau = U diag(sigma) U^T, F_new = U diag(exp(eps' - eps)) U^T F.
+template <int DIM>
+__device__ __forceinline__ void constitutive_eigen(int model, const InstMat& P, const float (*Ft)[3], float (*M)[3],
+                                                float (*Fn)[3], float* tau6) {
+    float U[3][3];
     jacobi_sym<DIM>(M, U);
     float eps[3], e2[3];
     float tr = 0.f;
@@ -401,6 +398,157 @@ __device__ __forceinline__ unsigned constitutive(int model, const InstMat& P, co
         tau6[1] = T[1][1];
         tau6[2] = T[0][1];
     }
+}
+
+
+template <int DIM>
+__device__ __forceinline__ unsigned constitutive(int model, const InstMat& P, const float (*Ft)[3], float (*Fn)[3],
+                                                 float* tau6) {
+    unsigned flags = 0;
+    float det;
+    if (DIM == 3)
+        det = Ft[0][0] * (Ft[1][1] * Ft[2][2] - Ft[1][2] * Ft[2][1]) -
+              Ft[0][1] * (Ft[1][0] * Ft[2][2] - Ft[1][2] * Ft[2][0]) +
+              Ft[0][2] * (Ft[1][0] * Ft[2][1] - Ft[1][1] * Ft[2][0]);
+    else
+        det = Ft[0][0] * Ft[1][1] - Ft[0][1] * Ft[1][0];
+    if (!(det > 0.f)) flags |= MPM_FLAG_INVERTED;
+    // M = F F^T - I = H + H^T + H H^T with H = F - I
+    float Hm[3][3], M[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Hm[a][b] = (a < DIM && b < DIM) ? Ft[a][b] - (a == b ? 1.f : 0.f) : 0.f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            float s = Hm[a][b] + Hm[b][a];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) s += Hm[a][c] * Hm[b][c];
+            M[a][b] = s;
+        }
+    float nrm2 = 0.f;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) nrm2 += M[a][b] * M[a][b];
+    if (nrm2 > SERIES_MAX_NORM2) {
+        constitutive_eigen<DIM>(model, P, Ft, M, Fn, tau6);
+        return flags;
+    }
+    // Series path (|M|_F <= 1/8): every quantity is a polynomial in the
+    // symmetric M, so no eigenvectors are needed.  Hencky strain
+    // E = log(I + M) / 2 by its Taylor series to degree 7 (truncation below
+    // 1e-7 relative at |M| = 1/8); the return map acts on dev(E) as a matrix;
+    // tau = 2 mu E' + lambda tr(E') I; F_new = expm(E' - E) F with expm - I to
+    // degree 5 (|E' - E| <= |E|).
+    float Q[3][3], L[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Q[a][b] = (a == b ? (1.f / 6.f) : 0.f) - M[a][b] * (1.f / 7.f);
+#pragma unroll
+    for (int c = 5; c >= 1; --c) {
+        sym_mul<DIM>(M, Q, L);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) Q[a][b] = (a == b ? 1.f / (float)c : 0.f) - L[a][b];
+    }
+    float E[3][3];
+    sym_mul<DIM>(M, Q, E);
+    float tr = 0.f;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) E[a][b] *= 0.5f;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) tr += E[a][a];
+    // D = E' - E
+    float Dm[3][3];
+    bool plastic = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Dm[a][b] = 0.f;
+    if (model == MPM_MODEL_DP) {
+        if (tr > 0.f) {
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                for (int b = 0; b < DIM; ++b) Dm[a][b] = -E[a][b];
+            plastic = true;
+        } else {
+            float nd2 = 0.f;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                for (int b = 0; b < DIM; ++b) {
+                    const float dv = E[a][b] - (a == b ? tr / (float)DIM : 0.f);
+                    nd2 += dv * dv;
+                }
+            const float nd = sqrtf(nd2);
+            const float dg = nd + P.dp_coef * tr * P.alpha;
+            if (dg > 0.f) {
+                const float sc = -dg * __builtin_amdgcn_rcpf(nd);
+#pragma unroll
+                for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                    for (int b = 0; b < DIM; ++b) Dm[a][b] = sc * (E[a][b] - (a == b ? tr / (float)DIM : 0.f));
+                plastic = true;
+            }
+        }
+    }
+    float tr2 = 0.f;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) tr2 += E[a][a] + Dm[a][a];
+    float T[3][3];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) T[a][b] = 2.f * P.mu * (E[a][b] + Dm[a][b]) + (a == b ? P.lam * tr2 : 0.f);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) Fn[a][b] = Ft[a][b];
+    if (plastic) {
+        float G[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) Q[a][b] = (a == b ? 1.f : 0.f) + Dm[a][b] * 0.2f;
+#pragma unroll
+        for (int c = 4; c >= 2; --c) {
+            sym_mul<DIM>(Dm, Q, L);
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                for (int b = 0; b < DIM; ++b) Q[a][b] = (a == b ? 1.f : 0.f) + L[a][b] * (1.f / (float)c);
+        }
+        sym_mul<DIM>(Dm, Q, G);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) {
+                float s2 = 0.f;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) s2 += G[a][c] * Ft[c][b];
+                Fn[a][b] += s2;
+            }
+    }
+    if (DIM == 3) {
+        tau6[0] = T[0][0];
+        tau6[1] = T[1][1];
+        tau6[2] = T[2][2];
+        tau6[3] = T[0][1];
+        tau6[4] = T[1][2];
+        tau6[5] = T[0][2];
+    } else {
+        tau6[0] = T[0][0];
+        tau6[1] = T[1][1];
+        tau6[2] = T[0][1];
+    }
     return flags;
 }
 
@@ -431,16 +579,89 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
     constexpr int MAXI = 2 * GS;
     __shared__ float xs[DIM][MAXI];
     __shared__ float fs[DD][MAXI];
-    __shared__ int nbr[T::NB];
     __shared__ int org[4];
     const int n_work = min(P.ctr->n_work, P.work_cap);
     const float dx = P.dxf, inv_dx = P.inv_dxf;
     const float cscale = 4.f * inv_dx * inv_dx;  // D_p^{-1} = (4/dx^2) I for quadratic B-splines
-    for (int w = blockIdx.x; w < n_work; w += gridDim.x) {
-        const int blk = P.w_block[w], s = P.w_start[w];
-        const int L = min(P.w_end[w] - s, MAXI);
-        if (threadIdx.x < T::NB) nbr[threadIdx.x] = P.b_nbr[blk * T::NB + threadIdx.x];
-        if (threadIdx.x == 0) {
+    // Software pipeline over work items: the gathers of the next item are
+    // issued during the current item's compute phases and carried in
+    // registers (source indices and tile slots after phase 0, particle data and
+    // grid tile after phase 1), then staged in LDS at the top of the loop.
+    constexpr int PER = MAXI / GS;                 // particles per thread
+    constexpr int TPER = (T::N + GS - 1) / GS;     // tile nodes per thread
+    const int tid = threadIdx.x;
+    uint32_t pq[PER];
+    int pphi[TPER];
+    float px[PER][DIM], pF[PER][DD];
+    uint32_t pid[PER], pin[PER];
+    float4 pt[TPER];
+    auto fetch_index = [&](int blk, int s, int L) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int r = tid + k * GS;
+            pq[k] = r < L ? osrc[s + r] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < TPER; ++k) {
+            const int t = tid + k * GS;
+            const int I = t % T::E, J = (t / T::E) % T::E, K = DIM == 3 ? t / (T::E * T::E) : 0;
+            const int d = (I >> 2) | ((J >> 2) << 1) | ((K >> 2) << 2);
+            pphi[k] = t < T::N ? P.b_nbr[blk * T::NB + d] : -1;
+        }
+    };
+    auto fetch_data = [&](int L) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int r = tid + k * GS;
+            if (r < L) {
+                const size_t q = pq[k];
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) px[k][a] = in.x[(size_t)a * n + q];
+#pragma unroll
+                for (int j = 0; j < DD; ++j) pF[k][j] = in.F[(size_t)j * n + q];
+                pid[k] = in.id ? in.id[q] : (uint32_t)q;
+                pin[k] = in.inst ? in.inst[q] : 0u;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < TPER; ++k) {
+            const int t = tid + k * GS;
+            const int I = t % T::E, J = (t / T::E) % T::E, K = DIM == 3 ? t / (T::E * T::E) : 0;
+            const int l = (I & 3) + BLK * ((J & 3) + BLK * (K & 3));
+            pt[k] = pphi[k] >= 0 ? P.grid[(size_t)pphi[k] * T::NPB + l] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    int w = blockIdx.x;
+    int blk = 0, s = 0, L = 0;
+    if (w < n_work) {
+        blk = P.w_block[w];
+        s = P.w_start[w];
+        L = min(P.w_end[w] - s, MAXI);
+        fetch_index(blk, s, L);
+        fetch_data(L);
+    }
+    while (w < n_work) {
+        // phase 0: stage the gathered item in LDS; ids travel with the
+        // particles (output positions s .. s+L-1 are contiguous, so every
+        // store coalesces; osrc named the input particle of each)
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int r = tid + k * GS;
+            if (r < L) {
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) xs[a][r] = px[k][a];
+#pragma unroll
+                for (int j = 0; j < DD; ++j) fs[j][r] = pF[k][j];
+                if (out.id) out.id[s + r] = pid[k];
+                if (out.inst) out.inst[s + r] = pin[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < TPER; ++k) {
+            const int t = tid + k * GS;
+            if (t < T::N) vt[t] = pt[k];
+        }
+        if (tid == 0) {
             int bc[3], inst;
             block_coords<DIM>(P, blk, bc, &inst);
             org[0] = bc[0] * BLK;
@@ -448,31 +669,17 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
             org[2] = bc[2] * BLK;
             org[3] = inst;
         }
-        // phase 0: issue every global gather of the work item up front
-        // (positions, deformation gradients, ids) and stage them in LDS.  The
-        // work item writes output positions s .. s+L-1 (contiguous, so every
-        // store below coalesces); osrc names the input particle of each.
-#pragma unroll 2
-        for (int r = threadIdx.x; r < L; r += GS) {
-            const size_t q = osrc[s + r];
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) xs[a][r] = in.x[(size_t)a * n + q];
-#pragma unroll
-            for (int k = 0; k < DD; ++k) fs[k][r] = in.F[(size_t)k * n + q];
-            if (out.id) out.id[s + r] = in.id ? in.id[q] : (uint32_t)q;
-            if (out.inst) out.inst[s + r] = in.inst ? in.inst[q] : 0u;
-        }
         __syncthreads();
+        const int wn = w + gridDim.x;
+        int nblk = 0, ns = 0, nL = 0;
+        if (wn < n_work) {
+            nblk = P.w_block[wn];
+            ns = P.w_start[wn];
+            nL = min(P.w_end[wn] - ns, MAXI);
+            fetch_index(nblk, ns, nL);
+        }
         const InstMat mat = material(P, org[3]);
         const float dt = mat.dt;
-        for (int t = threadIdx.x; t < T::N; t += GS) {
-            const int I = t % T::E, J = (t / T::E) % T::E, K = DIM == 3 ? t / (T::E * T::E) : 0;
-            const int d = (I >> 2) | ((J >> 2) << 1) | ((K >> 2) << 2);
-            const int phi = nbr[d];
-            const int l = (I & 3) + BLK * ((J & 3) + BLK * (K & 3));
-            vt[t] = phi >= 0 ? P.grid[(size_t)phi * T::NPB + l] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-        __syncthreads();
         // phase 1: grid gather, new position, velocity and affine matrix,
         // F_trial = (I + dt grad v) F (Eq. 17) kept in LDS
 #pragma unroll 1
@@ -568,6 +775,7 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
             if (!finite) raise_flag(P.ctr, MPM_FLAG_NAN);
         }
         __syncthreads();
+        if (wn < n_work) fetch_data(nL);  // in flight during phase 2
         // phase 2: constitutive update (its register live range is separate)
 #pragma unroll 1
         for (int r = threadIdx.x; r < L; r += GS) {
@@ -592,6 +800,10 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
             if (flags) raise_flag(P.ctr, flags);
         }
         __syncthreads();
+        w = wn;
+        blk = nblk;
+        s = ns;
+        L = nL;
     }
 }
 
@@ -634,9 +846,9 @@ hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, 
 
 // Output layout of the G2P of this build: osrc[o] = input index of the
 // particle that G2P stores at position o (blocks in sort order, rank-major
-// inside a block).  One workgroup per owner block.
+// inside a block).  One wave64 per owner block.
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_out_layout(DevParams P, const uint32_t* __restrict__ order,
+__global__ __launch_bounds__(64) void k_out_layout(DevParams P, const uint32_t* __restrict__ order,
                                                    const uint32_t* __restrict__ skeys, uint32_t* __restrict__ osrc) {
     __shared__ Interleave<DIM> il;
     const int nb = min(P.ctr->nb, P.block_cap);
@@ -645,18 +857,18 @@ __global__ __launch_bounds__(WG) void k_out_layout(DevParams P, const uint32_t* 
         if (cnt <= 0) continue;
         const int st = P.b_start[b], en = st + cnt;
         interleave_setup<DIM>(il, skeys, st, en);
-        for (int i = st + (int)threadIdx.x; i < en; i += WG) osrc[interleave_pos<DIM>(il, i, skeys[i])] = order[i];
+        for (int i = st + (int)threadIdx.x; i < en; i += 64) osrc[interleave_pos<DIM>(il, i, skeys[i])] = order[i];
         __syncthreads();
     }
 }
 
 hipError_t launch_out_layout(const DevParams& P, const uint32_t* order, const uint32_t* skeys, uint32_t* osrc,
                              hipStream_t s) {
-    const int g = P.dense ? 65536 : 8192;
+    const int g = P.dense ? 65536 : 32768;
     if (P.dim == 3)
-        k_out_layout<3><<<g, WG, 0, s>>>(P, order, skeys, osrc);
+        k_out_layout<3><<<g, 64, 0, s>>>(P, order, skeys, osrc);
     else
-        k_out_layout<2><<<g, WG, 0, s>>>(P, order, skeys, osrc);
+        k_out_layout<2><<<g, 64, 0, s>>>(P, order, skeys, osrc);
     return hipGetLastError();
 }
 

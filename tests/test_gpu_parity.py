@@ -36,6 +36,53 @@ def test_tiny_3d_one_step(ties):
     sim.close()
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_large_and_small_elastic_strain_one_step(dim):
+    """Deformation gradients R diag(exp(s)) with principal log-stretches s of
+    0.1 to 0.3 (|F F^T - I| beyond the series path's 1/8: eigen path) mixed in
+    the same waves with near-identity ones (series path), elastic and
+    Drucker-Prager, against the oracle."""
+    rng = np.random.default_rng(17 + dim)
+    for model in ("elastic", "dp"):
+        w = wl.tiny_3d(n=64, ties=False)
+        if dim == 2:
+            w = _tiny_2d_from(w)
+        w.model = model
+        n, d = w.n, w.dim
+        F = np.empty((n, d, d))
+        for p in range(n):
+            q, r = np.linalg.qr(rng.normal(size=(d, d)))
+            q = q * np.sign(np.diag(r))
+            if np.linalg.det(q) < 0:
+                q[:, 0] = -q[:, 0]
+            s = rng.normal(0, 0.2 if p % 2 else 0.01, d)
+            F[p] = q @ np.diag(np.exp(s))
+        w.F = F.reshape(n, d * d).T.astype(np.float32)
+        _announce("large/small strain", dim, model, n)
+        sim = _sim(w)
+        parts = gpu_step_parts(sim)
+        assert parts["status"][0] == 0, parts["status"]
+        print(compare_step(w, parts))
+        sim.close()
+
+
+def _tiny_2d_from(w3):
+    st = w3.state()
+    x = st["x"][:2] + 0.4
+    w = wl.Workload(name="tiny_2d", dim=2, dx=w3.dx, cells=(16, 16), gravity=(0.0, -9.81, 0.0), dt=1e-3,
+                    steps=1, model="dp", E=1e6, nu=0.3, rho=2000.0, friction_deg=30.0, ppc=4,
+                    p_vol0=w3.dx ** 2 / 4, p_mass=2000 * w3.dx ** 2 / 4,
+                    bc=(("separate", "separate"), ("sticky", "separate"), ("none", "none")))
+    rng = np.random.default_rng(4)
+    n = x.shape[1]
+    w.x = x.astype(np.float32)
+    w.v = rng.normal(0, 0.2, (2, n)).astype(np.float32)
+    w.C = rng.normal(0, 0.5, (4, n)).astype(np.float32)
+    w.F = np.tile(np.array([[1.0], [0.0], [0.0], [1.0]], np.float32), (1, n))
+    w.tau = rng.normal(0, 100.0, (3, n)).astype(np.float32)
+    return w
+
+
 def test_tiny_2d_one_step():
     w3 = wl.tiny_3d(n=40)
     w = wl.collapse_2d()
