@@ -222,7 +222,7 @@ int alloc_capacity_buffers(mpm_ctx* c) {
     const size_t cap = (size_t)c->block_cap;
     // room for the smallest work-item size mpm_set_tuning accepts
     c->work_cap = c->block_cap + c->max_particles / MIN_CHUNK + 1;
-    int scan_n = std::max({radix_hist_size(c->max_particles), (int)H, c->block_cap, 1});
+    int scan_n = std::max({(int)H, c->block_cap, 1});
     hipError_t e = hipSuccess;
     if (!c->dense) {
         e = e ? e : dalloc(&c->h_keys, H);
@@ -271,7 +271,7 @@ int build_once(mpm_ctx* c, const mpm_particles* p, hipStream_t s) {
     if (e != hipSuccess) return MPM_ERR_HIP;
     uint32_t *ko = c->k1, *vo = c->v0;
     if (n > 0) {
-        e = radix_sort(c->k1, c->k0, c->k1, c->v0, c->v1, n, c->key_bits, c->hist, c->partials, &ko, &vo, s);
+        e = radix_sort(c->k1, c->k0, c->k1, c->v0, c->v1, n, c->key_bits, c->hist, c->ctr, &ko, &vo, s);
         if (e != hipSuccess) return MPM_ERR_HIP;
     }
     c->skeys = ko;
@@ -290,6 +290,7 @@ int first_flag_code(unsigned f) {
     if (f & MPM_FLAG_DOMAIN) return MPM_ERR_DOMAIN;
     if (f & MPM_FLAG_INVERTED) return MPM_ERR_INVERTED;
     if (f & MPM_FLAG_NAN) return MPM_ERR_NAN;
+    if (f & MPM_FLAG_WAIT) return MPM_ERR_WAIT;
     return MPM_OK;
 }
 
@@ -322,6 +323,7 @@ const char* mpm_status_string(int status) {
         case MPM_ERR_INVERTED: return "MPM_ERR_INVERTED: deformation gradient with det <= 0";
         case MPM_ERR_NAN: return "MPM_ERR_NAN: non-finite value";
         case MPM_ERR_STATE: return "MPM_ERR_STATE: call out of order";
+        case MPM_ERR_WAIT: return "MPM_ERR_WAIT: a bounded device-side wait expired (step skipped)";
         default: return "unknown status";
     }
 }
@@ -331,7 +333,7 @@ int mpm_create(const mpm_params* q, mpm_ctx** out) {
     *out = nullptr;
     if (!q) return MPM_ERR_ARG;
     if (q->dim != 2 && q->dim != 3) return MPM_ERR_ARG;
-    if (!(q->dx > 0.0) || !(q->dt > 0.f) || q->max_particles < 1 || q->max_particles > (1 << 30)) return MPM_ERR_ARG;
+    if (!(q->dx > 0.0) || !(q->dt > 0.f) || q->max_particles < 1 || q->max_particles >= (1 << 30)) return MPM_ERR_ARG;
     if (q->model != MPM_MODEL_ELASTIC && q->model != MPM_MODEL_DP) return MPM_ERR_ARG;
     if (!(q->E > 0.f) || !(q->nu >= 0.f && q->nu < 0.5f) || !(q->p_mass > 0.f) || !(q->p_vol0 > 0.f)) return MPM_ERR_ARG;
     if (q->grid_mode != MPM_GRID_SPARSE && q->grid_mode != MPM_GRID_DENSE) return MPM_ERR_ARG;

@@ -38,6 +38,7 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
                                                  const float* __restrict__ tau, int n,
                                                  const uint32_t* __restrict__ order,
                                                  const uint32_t* __restrict__ skeys) {
+    if (P.ctr->flags & MPM_FLAG_WAIT) return;  // the sort of this build did not complete
     using T = Tile<DIM>;
     constexpr int NS = DIM == 3 ? 6 : 3;
     constexpr int NC = T::NPB;  // base cells per block
@@ -125,9 +126,10 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
 #pragma unroll
                     for (int k = 0; k < 3; ++k) dxn[a][k] = ((float)k - 0.5f - t[a]) * dx;
                 // Tensor-product factorisation along x: with a = w_y w_z, the
-                // contribution to node k is w_x b + A_0 (a w_x dx_x) - G_0 (a dw_x)
+                // contribution to node k is w_x b + (w_x dx_x) (a A_0) - dw_x (a G_0)
                 // where b = a (m v + A_1 dx_y + A_2 dx_z) - G_1 dw_y w_z - G_2 w_y dw_z
-                // (A = m_p C_p, G = dt V0 tau_p, columns A_j, G_j).
+                // (A = m_p C_p, G = dt V0 tau_p, columns A_j, G_j): three fused
+                // multiply-adds per node and momentum component, one for the mass.
                 if (DIM == 3) {
 #pragma unroll
                     for (int kz = 0; kz < 3; ++kz)
@@ -140,14 +142,24 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
 #pragma unroll
                             for (int a = 0; a < 3; ++a)
                                 be[a] = al * (mv[a] + A[a][1] * dy + A[a][2] * dz) - G[a][1] * gy - G[a][2] * gz;
+                            float ca[3], cg[3];
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                ca[a] = al * A[a][0];
+                                cg[a] = al * G[a][0];
+                            }
+                            const float alm = al * mp;
 #pragma unroll
                             for (int kx = 0; kx < 3; ++kx) {
                                 const int k = kx + 3 * (ky + 3 * kz);
-                                const float wx = wt[0][kx];
-                                const float ca = al * wx * dxn[0][kx], cg = al * dw[0][kx];
+                                const float wx = wt[0][kx], wd = wt[0][kx] * dxn[0][kx], dwx = dw[0][kx];
 #pragma unroll
-                                for (int a = 0; a < 3; ++a) acc[k][a] += wx * be[a] + A[a][0] * ca - G[a][0] * cg;
-                                acc[k][3] += al * wx * mp;
+                                for (int a = 0; a < 3; ++a) {
+                                    float r = fmaf(wx, be[a], acc[k][a]);
+                                    r = fmaf(wd, ca[a], r);
+                                    acc[k][a] = fmaf(-dwx, cg[a], r);
+                                }
+                                acc[k][3] = fmaf(wx, alm, acc[k][3]);
                             }
                         }
                 } else {
@@ -159,14 +171,19 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
                         float be[2];
 #pragma unroll
                         for (int a = 0; a < 2; ++a) be[a] = al * (mv[a] + A[a][1] * dy) - G[a][1] * gy;
+                        const float ca[2] = {al * A[0][0], al * A[1][0]}, cg[2] = {al * G[0][0], al * G[1][0]};
+                        const float alm = al * mp;
 #pragma unroll
                         for (int kx = 0; kx < 3; ++kx) {
                             const int k = kx + 3 * ky;
-                            const float wx = wt[0][kx];
-                            const float ca = al * wx * dxn[0][kx], cg = al * dw[0][kx];
+                            const float wx = wt[0][kx], wd = wt[0][kx] * dxn[0][kx], dwx = dw[0][kx];
 #pragma unroll
-                            for (int a = 0; a < 2; ++a) acc[k][a] += wx * be[a] + A[a][0] * ca - G[a][0] * cg;
-                            acc[k][3] += al * wx * mp;
+                            for (int a = 0; a < 2; ++a) {
+                                float r = fmaf(wx, be[a], acc[k][a]);
+                                r = fmaf(wd, ca[a], r);
+                                acc[k][a] = fmaf(-dwx, cg[a], r);
+                            }
+                            acc[k][3] = fmaf(wx, alm, acc[k][3]);
                         }
                     }
                 }
@@ -572,6 +589,7 @@ struct G2POut {
 template <int DIM, int GS>
 __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, int n,
                                             const uint32_t* __restrict__ osrc) {
+    if (P.ctr->flags & MPM_FLAG_WAIT) return;  // the sort of this build did not complete
     using T = Tile<DIM>;
     constexpr int NS = DIM == 3 ? 6 : 3;
     constexpr int DD = DIM * DIM;
@@ -850,6 +868,7 @@ hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, 
 template <int DIM>
 __global__ __launch_bounds__(64) void k_out_layout(DevParams P, const uint32_t* __restrict__ order,
                                                    const uint32_t* __restrict__ skeys, uint32_t* __restrict__ osrc) {
+    if (P.ctr->flags & MPM_FLAG_WAIT) return;  // the sort of this build did not complete
     __shared__ Interleave<DIM> il;
     const int nb = min(P.ctr->nb, P.block_cap);
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
