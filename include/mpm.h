@@ -65,15 +65,12 @@ typedef struct mpm_ctx mpm_ctx;
 #define MPM_ERR_INVERTED  6   /* a trial deformation gradient has det <= 0 */
 #define MPM_ERR_NAN       7   /* a non-finite value was produced */
 #define MPM_ERR_STATE     8   /* call out of order (e.g. p2g before a build) */
-#define MPM_ERR_WAIT      9   /* a bounded device-side wait expired; the step was skipped */
 
 /* bits of the sticky device status word */
 #define MPM_FLAG_OVERFLOW 1u
 #define MPM_FLAG_DOMAIN   2u
 #define MPM_FLAG_INVERTED 4u
 #define MPM_FLAG_NAN      8u
-#define MPM_FLAG_WAIT     16u /* the sort's look-back wait hit its bound (never in a correct
-                                 run); P2G, G2P and the reverse kernels then do nothing */
 
 /* boundary condition of one grid face (nodes within `bound` of the face) */
 #define MPM_BC_NONE     0   /* no constraint */

@@ -321,7 +321,6 @@ __global__ __launch_bounds__(WG) void k_g2p_adj(DevParams P, const float* __rest
                                                 OutBar ob, float* __restrict__ x_bar, float* __restrict__ F_bar, int n,
                                                 const uint32_t* __restrict__ order,
                                                 const uint32_t* __restrict__ skeys) {
-    if (P.ctr->flags & MPM_FLAG_WAIT) return;  // the sort of this build did not complete
     using T = Tile<DIM>;
     constexpr int NS = DIM == 3 ? 6 : 3;
     constexpr int DD = DIM * DIM;
@@ -524,7 +523,6 @@ template <int DIM>
 __global__ __launch_bounds__(64) void k_scatter_adj(DevParams P, const float* __restrict__ x, int n,
                                                     const uint32_t* __restrict__ order,
                                                     const uint32_t* __restrict__ skeys) {
-    if (P.ctr->flags & MPM_FLAG_WAIT) return;  // the sort of this build did not complete
     using T = Tile<DIM>;
     constexpr int NC = T::NPB;
     constexpr int NK = DIM == 3 ? 27 : 9;
@@ -697,7 +695,6 @@ struct PBar {
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_p2g_adj(DevParams P, PIn in, PBar bar, int n,
                                                 const uint32_t* __restrict__ order) {
-    if (P.ctr->flags & MPM_FLAG_WAIT) return;  // the sort of this build did not complete
     using T = Tile<DIM>;
     constexpr int NS = DIM == 3 ? 6 : 3;
     __shared__ float4 gt[T::N];

@@ -222,7 +222,7 @@ int alloc_capacity_buffers(mpm_ctx* c) {
     const size_t cap = (size_t)c->block_cap;
     // room for the smallest work-item size mpm_set_tuning accepts
     c->work_cap = c->block_cap + c->max_particles / MIN_CHUNK + 1;
-    int scan_n = std::max({(int)H, c->block_cap, 1});
+    int scan_n = std::max({radix_hist_size(c->max_particles), (int)H, c->block_cap, 1});
     hipError_t e = hipSuccess;
     if (!c->dense) {
         e = e ? e : dalloc(&c->h_keys, H);
@@ -271,7 +271,7 @@ int build_once(mpm_ctx* c, const mpm_particles* p, hipStream_t s) {
     if (e != hipSuccess) return MPM_ERR_HIP;
     uint32_t *ko = c->k1, *vo = c->v0;
     if (n > 0) {
-        e = radix_sort(c->k1, c->k0, c->k1, c->v0, c->v1, n, c->key_bits, c->hist, c->ctr, &ko, &vo, s);
+        e = radix_sort(c->k1, c->k0, c->k1, c->v0, c->v1, n, c->key_bits, c->hist, c->partials, &ko, &vo, s);
         if (e != hipSuccess) return MPM_ERR_HIP;
     }
     c->skeys = ko;
@@ -290,7 +290,6 @@ int first_flag_code(unsigned f) {
     if (f & MPM_FLAG_DOMAIN) return MPM_ERR_DOMAIN;
     if (f & MPM_FLAG_INVERTED) return MPM_ERR_INVERTED;
     if (f & MPM_FLAG_NAN) return MPM_ERR_NAN;
-    if (f & MPM_FLAG_WAIT) return MPM_ERR_WAIT;
     return MPM_OK;
 }
 
@@ -323,7 +322,6 @@ const char* mpm_status_string(int status) {
         case MPM_ERR_INVERTED: return "MPM_ERR_INVERTED: deformation gradient with det <= 0";
         case MPM_ERR_NAN: return "MPM_ERR_NAN: non-finite value";
         case MPM_ERR_STATE: return "MPM_ERR_STATE: call out of order";
-        case MPM_ERR_WAIT: return "MPM_ERR_WAIT: a bounded device-side wait expired (step skipped)";
         default: return "unknown status";
     }
 }

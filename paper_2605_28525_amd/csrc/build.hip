@@ -26,44 +26,61 @@
 
 namespace mpmx {
 
+constexpr int BIN_PER_THREAD = 4;  // particles per thread of k_bin (loads issued together)
+
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_bin(DevParams P, const float* __restrict__ x,
                                             const uint32_t* __restrict__ inst, int n, uint32_t* __restrict__ keys) {
-    const int i = blockIdx.x * WG + threadIdx.x;
-    if (i >= n) return;
-    int b[3] = {0, 0, 0};
-    unsigned bad = 0;
-    uint32_t in = 0;
-    if (P.n_inst > 1 && inst) {
-        in = inst[i];
-        if (in >= (uint32_t)P.n_inst) {
-            bad |= MPM_FLAG_DOMAIN;
-            in = (uint32_t)P.n_inst - 1;
+    const int i0 = blockIdx.x * WG * BIN_PER_THREAD + threadIdx.x;
+    float xv[BIN_PER_THREAD][3];
+    uint32_t iv[BIN_PER_THREAD];
+#pragma unroll
+    for (int k = 0; k < BIN_PER_THREAD; ++k) {
+        const int i = i0 + k * WG;
+        iv[k] = 0u;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) xv[k][a] = 0.f;
+        if (i < n) {
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) xv[k][a] = x[(size_t)a * n + i];
+            if (P.n_inst > 1 && inst) iv[k] = inst[i];
         }
     }
+    unsigned bad = 0;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        double f = floor(index_arg(x[(size_t)a * n + i], P.inv_dx));
-        if (!(f == f)) {
-            bad |= MPM_FLAG_NAN;
-            f = 0.0;
-        } else if (f < 0.0 || f + 2.0 > (double)P.cells[a]) {
+    for (int k = 0; k < BIN_PER_THREAD; ++k) {
+        const int i = i0 + k * WG;
+        if (i >= n) break;
+        uint32_t in = iv[k];
+        if (in >= (uint32_t)max(P.n_inst, 1)) {
             bad |= MPM_FLAG_DOMAIN;
-            f = fmin(fmax(f, 0.0), (double)(P.cells[a] - 2));
+            in = (uint32_t)max(P.n_inst, 1) - 1;
         }
-        b[a] = (int)f;
+        int b[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            double f = floor(index_arg(xv[k][a], P.inv_dx));
+            if (!(f == f)) {
+                bad |= MPM_FLAG_NAN;
+                f = 0.0;
+            } else if (f < 0.0 || f + 2.0 > (double)P.cells[a]) {
+                bad |= MPM_FLAG_DOMAIN;
+                f = fmin(fmax(f, 0.0), (double)(P.cells[a] - 2));
+            }
+            b[a] = (int)f;
+        }
+        uint32_t bl, cell;
+        if (DIM == 3) {
+            bl = ((uint32_t)(b[2] >> 2) * (uint32_t)P.nblk[1] + (uint32_t)(b[1] >> 2)) * (uint32_t)P.nblk[0] +
+                 (uint32_t)(b[0] >> 2);
+            cell = (b[0] & 3) | ((b[1] & 3) << 2) | ((b[2] & 3) << 4);
+        } else {
+            bl = (uint32_t)(b[1] >> 2) * (uint32_t)P.nblk[0] + (uint32_t)(b[0] >> 2);
+            cell = (b[0] & 3) | ((b[1] & 3) << 2);
+        }
+        keys[i] = (in << (P.blk_bits + 2 * DIM)) | (bl << (2 * DIM)) | cell;
     }
     if (bad) raise_flag(P.ctr, bad);
-    uint32_t bl, cell;
-    if (DIM == 3) {
-        bl = ((uint32_t)(b[2] >> 2) * (uint32_t)P.nblk[1] + (uint32_t)(b[1] >> 2)) * (uint32_t)P.nblk[0] +
-             (uint32_t)(b[0] >> 2);
-        cell = (b[0] & 3) | ((b[1] & 3) << 2) | ((b[2] & 3) << 4);
-    } else {
-        bl = (uint32_t)(b[1] >> 2) * (uint32_t)P.nblk[0] + (uint32_t)(b[0] >> 2);
-        cell = (b[0] & 3) | ((b[1] & 3) << 2);
-    }
-    keys[i] = (in << (P.blk_bits + 2 * DIM)) | (bl << (2 * DIM)) | cell;
 }
 
 __device__ int hash_insert(const DevParams& P, uint64_t K) {
@@ -145,54 +162,86 @@ __device__ __forceinline__ uint64_t neighbour_mask(uint64_t occ, int d) {
     return o;
 }
 
+constexpr int HI_ROUNDS = 4;  // sorted particles per lane of k_hash_insert (a wave covers 256)
+
+// Sorted particles in runs of 256 per wave.  A run of equal owner blocks is one
+// group; a group that continues from the previous round of the same wave is
+// merged, so each wave inserts each of its owner blocks once.  Per group: the
+// OR of its base-cell bits, the node masks of the owner and its 2^d - 1 upper
+// neighbours by bit dilation, one insert per touched block (lane d takes
+// neighbour d), and the owner segment's first / one-past-last sorted position
+// where the segment starts / ends inside this wave.
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_hash_insert(DevParams P, const uint32_t* __restrict__ skeys, int n) {
     constexpr int NB = 1 << DIM;
     constexpr int CB = 2 * DIM;
-    const int i = blockIdx.x * WG + threadIdx.x;
     const int lane = __lane_id();
-    const bool valid = i < n;
-    const uint32_t key = valid ? skeys[i] : 0u;
-    const uint32_t seg = key >> CB;                                   // instance and block
-    const uint32_t bl = seg & ((1u << P.blk_bits) - 1u);              // block within the instance
-    const int inst = (int)(seg >> P.blk_bits);
-    const uint32_t cell = key & ((1u << CB) - 1u);
-    int bc[3];
-    linear_to_block<DIM>(P, bl, bc);
-    const uint64_t ko = block_key<DIM>(P, bc[0], bc[1], bc[2], inst);
-    const bool is_start = valid && (i == 0 || (skeys[i - 1] >> CB) != seg);
-    const bool is_end = valid && (i == n - 1 || (skeys[i + 1] >> CB) != seg);
-
-    // one pass per distinct owner block in the wave (the keys are sorted, so
-    // usually one or two): OR the base-cell bits of its lanes, derive the node
-    // masks of the block and its upper neighbours, and let lane d insert
-    // neighbour d
-    unsigned long long todo = __ballot(valid);
-    while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const uint64_t K = readlane64(ko, leader);
-        const bool mine = valid && ko == K;
-        const unsigned long long grp = __ballot(mine);
-        const uint64_t occ = readlane64(wave_or64(mine ? (1ull << cell) : 0ull), leader);
-        const int lbx = readlane32(bc[0], leader), lby = readlane32(bc[1], leader), lbz = readlane32(bc[2], leader);
-        const int lin = readlane32(inst, leader);
+    const int base = ((blockIdx.x * WG + (int)threadIdx.x) >> 6) * 64 * HI_ROUNDS;
+    if (base >= n) return;  // whole wave
+    const int stop = min(base + 64 * HI_ROUNDS, n);
+    // owner segments (instance and block) just before and after this wave's range
+    const uint32_t seg_before = base > 0 ? (skeys[base - 1] >> CB) : ~0u;
+    const uint32_t seg_after = stop < n ? (skeys[stop] >> CB) : ~0u;
+    uint32_t key[HI_ROUNDS];
+#pragma unroll
+    for (int r = 0; r < HI_ROUNDS; ++r) {
+        const int i = base + r * 64 + lane;
+        key[r] = i < n ? skeys[i] : 0u;
+    }
+    bool have = false;
+    uint32_t p_seg = 0;
+    uint64_t p_occ = 0;
+    int p_first = 0, p_end = 0;
+    auto flush = [&]() {
+        const uint32_t bl = p_seg & ((1u << P.blk_bits) - 1u);
+        const int inst = (int)(p_seg >> P.blk_bits);
+        int bc[3];
+        linear_to_block<DIM>(P, bl, bc);
         int slot = -1;
         if (lane < NB) {
-            const uint64_t mymask = neighbour_mask<DIM>(occ, lane);
+            const uint64_t mymask = neighbour_mask<DIM>(p_occ, lane);
             if (mymask != 0ull) {
                 const uint64_t Kd =
-                    block_key<DIM>(P, lbx + (lane & 1), lby + ((lane >> 1) & 1), lbz + ((lane >> 2) & 1), lin);
+                    block_key<DIM>(P, bc[0] + (lane & 1), bc[1] + ((lane >> 1) & 1), bc[2] + ((lane >> 2) & 1), inst);
                 slot = hash_insert(P, Kd);
                 if (slot >= 0) atomicOr((unsigned long long*)&P.h_mask[slot], (unsigned long long)mymask);
             }
         }
-        const int so = readlane32(slot, 0);
-        if (mine && so >= 0) {
-            if (is_start) P.h_start[so] = i;
-            if (is_end) P.h_end[so] = i + 1;
+        if (lane == 0 && slot >= 0) {  // lane 0 holds the owner block
+            if (p_first > base || seg_before != p_seg) P.h_start[slot] = p_first;
+            if (p_end < stop || seg_after != p_seg) P.h_end[slot] = p_end;
         }
-        todo &= ~grp;
+    };
+#pragma unroll
+    for (int r = 0; r < HI_ROUNDS; ++r) {
+        const int i = base + r * 64 + lane;
+        const bool valid = i < n;
+        const uint32_t seg = key[r] >> CB;
+        const uint32_t cell = key[r] & ((1u << CB) - 1u);
+        unsigned long long todo = __ballot(valid);
+        while (todo) {
+            const int leader = __ffsll((long long)todo) - 1;
+            const uint32_t g = (uint32_t)readlane32((int)seg, leader);
+            const bool mine = valid && seg == g;
+            const unsigned long long grp = __ballot(mine);
+            const uint64_t occ = readlane64(wave_or64(mine ? (1ull << cell) : 0ull), leader);
+            const int first = base + r * 64 + leader;
+            const int last = base + r * 64 + (63 - __clzll((long long)grp));
+            if (have && g == p_seg) {
+                p_occ |= occ;
+                p_end = last + 1;
+            } else {
+                if (have) flush();
+                have = true;
+                p_seg = g;
+                p_occ = occ;
+                p_first = first;
+                p_end = last + 1;
+            }
+            todo &= ~grp;
+        }
     }
+    if (have) flush();
 }
 
 __global__ __launch_bounds__(WG) void k_compact_count(DevParams P, int H, unsigned* __restrict__ partials) {
@@ -349,10 +398,11 @@ static int grid_for(long long items, int cap_wgs = 8192) {
 
 hipError_t launch_bin(const DevParams& P, const float* x, const uint32_t* inst, int n, uint32_t* keys, hipStream_t s) {
     if (n <= 0) return hipSuccess;
+    const int g = (n + WG * BIN_PER_THREAD - 1) / (WG * BIN_PER_THREAD);
     if (P.dim == 3)
-        k_bin<3><<<(n + WG - 1) / WG, WG, 0, s>>>(P, x, inst, n, keys);
+        k_bin<3><<<g, WG, 0, s>>>(P, x, inst, n, keys);
     else
-        k_bin<2><<<(n + WG - 1) / WG, WG, 0, s>>>(P, x, inst, n, keys);
+        k_bin<2><<<g, WG, 0, s>>>(P, x, inst, n, keys);
     return hipGetLastError();
 }
 
@@ -360,10 +410,11 @@ hipError_t launch_build_sparse(const DevParams& P, const uint32_t* skeys, int n,
                                hipStream_t s) {
     k_hash_clear<<<grid_for(H), WG, 0, s>>>(P, H);
     if (n > 0) {
+        const int per_wg = WG * HI_ROUNDS;
         if (P.dim == 3)
-            k_hash_insert<3><<<(n + WG - 1) / WG, WG, 0, s>>>(P, skeys, n);
+            k_hash_insert<3><<<(n + per_wg - 1) / per_wg, WG, 0, s>>>(P, skeys, n);
         else
-            k_hash_insert<2><<<(n + WG - 1) / WG, WG, 0, s>>>(P, skeys, n);
+            k_hash_insert<2><<<(n + per_wg - 1) / per_wg, WG, 0, s>>>(P, skeys, n);
     }
     const int tiles = ((int)H + SCAN_TILE - 1) / SCAN_TILE;
     k_compact_count<<<tiles, WG, 0, s>>>(P, (int)H, partials);

@@ -279,7 +279,7 @@ int scan_partials_size(int n);
 hipError_t scan_partials(unsigned* partials, int tiles, unsigned* total_out, hipStream_t s);
 
 hipError_t radix_sort(const uint32_t* keys_in, uint32_t* k0, uint32_t* k1, uint32_t* v0, uint32_t* v1, int n,
-                      int key_bits, unsigned* hist, DevCounters* ctr, uint32_t** keys_out, uint32_t** vals_out,
+                      int key_bits, unsigned* hist, unsigned* partials, uint32_t** keys_out, uint32_t** vals_out,
                       hipStream_t s);
 int radix_hist_size(int n);
 

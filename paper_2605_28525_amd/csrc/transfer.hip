@@ -38,7 +38,6 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
                                                  const float* __restrict__ tau, int n,
                                                  const uint32_t* __restrict__ order,
                                                  const uint32_t* __restrict__ skeys) {
-    if (P.ctr->flags & MPM_FLAG_WAIT) return;  // the sort of this build did not complete
     using T = Tile<DIM>;
     constexpr int NS = DIM == 3 ? 6 : 3;
     constexpr int NC = T::NPB;  // base cells per block
@@ -589,7 +588,6 @@ struct G2POut {
 template <int DIM, int GS>
 __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, int n,
                                             const uint32_t* __restrict__ osrc) {
-    if (P.ctr->flags & MPM_FLAG_WAIT) return;  // the sort of this build did not complete
     using T = Tile<DIM>;
     constexpr int NS = DIM == 3 ? 6 : 3;
     constexpr int DD = DIM * DIM;
@@ -868,7 +866,6 @@ hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, 
 template <int DIM>
 __global__ __launch_bounds__(64) void k_out_layout(DevParams P, const uint32_t* __restrict__ order,
                                                    const uint32_t* __restrict__ skeys, uint32_t* __restrict__ osrc) {
-    if (P.ctr->flags & MPM_FLAG_WAIT) return;  // the sort of this build did not complete
     __shared__ Interleave<DIM> il;
     const int nb = min(P.ctr->nb, P.block_cap);
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {

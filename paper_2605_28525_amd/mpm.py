@@ -16,8 +16,8 @@ import numpy as np
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmpm.so")
 
 MPM_OK, MPM_ERR_ARG, MPM_ERR_HIP, MPM_ERR_NOMEM = 0, 1, 2, 3
-MPM_ERR_OVERFLOW, MPM_ERR_DOMAIN, MPM_ERR_INVERTED, MPM_ERR_NAN, MPM_ERR_STATE, MPM_ERR_WAIT = 4, 5, 6, 7, 8, 9
-MPM_FLAG_OVERFLOW, MPM_FLAG_DOMAIN, MPM_FLAG_INVERTED, MPM_FLAG_NAN, MPM_FLAG_WAIT = 1, 2, 4, 8, 16
+MPM_ERR_OVERFLOW, MPM_ERR_DOMAIN, MPM_ERR_INVERTED, MPM_ERR_NAN, MPM_ERR_STATE = 4, 5, 6, 7, 8
+MPM_FLAG_OVERFLOW, MPM_FLAG_DOMAIN, MPM_FLAG_INVERTED, MPM_FLAG_NAN = 1, 2, 4, 8
 MPM_BC = {"none": 0, "sticky": 1, "slip": 2, "separate": 3}
 MPM_MODEL = {"elastic": 0, "dp": 1}
 MPM_GRID_SPARSE, MPM_GRID_DENSE = 0, 1
