@@ -225,8 +225,9 @@ int mpm_get_active(mpm_ctx* ctx, uint64_t* keys, uint64_t* masks, int capacity, 
 int mpm_get_grid(mpm_ctx* ctx, float* out, int capacity_blocks, void* stream);
 
 /* Writes the particle permutation of mpm_g2p for the last build: order[i] =
- * index in the input set of the particle that mpm_g2p writes to position i.
- * Device pointer owned by the caller, n entries. */
+ * index in the input set of the particle that mpm_g2p writes to position i
+ * (recorded by mpm_p2g, so valid once mpm_p2g has run on the build).  Device
+ * pointer owned by the caller, n entries. */
 int mpm_get_order(mpm_ctx* ctx, uint32_t* order, int n, void* stream);
 
 /* ---- reverse mode (contexts created with MPM_FLAG_ADJOINT) -------------

@@ -281,7 +281,6 @@ int build_once(mpm_ctx* c, const mpm_particles* p, hipStream_t s) {
         e = launch_build_dense(c->P, ko, n, (int)c->n_blocks_total, c->partials, s);
     else
         e = launch_build_sparse(c->P, ko, n, 1u << c->H_log2, c->partials, s);
-    if (e == hipSuccess && n > 0) e = launch_out_layout(c->P, vo, ko, c->osrc, s);
     return hip_status(e);
 }
 
@@ -507,7 +506,8 @@ int mpm_p2g(mpm_ctx* c, const mpm_particles* p, void* stream) {
     if (!c->built || p->n != c->built_n) return MPM_ERR_STATE;
     if (p->n == 0) return MPM_OK;
     const int wgs = std::min(c->p2g_wgs, c->work_cap);
-    return hip_status(launch_p2g(c->P, p->x, p->v, p->C, p->tau, p->n, c->order, c->skeys, wgs, (hipStream_t)stream));
+    return hip_status(
+        launch_p2g(c->P, p->x, p->v, p->C, p->tau, p->n, c->order, c->skeys, c->osrc, wgs, (hipStream_t)stream));
 }
 
 int mpm_grid_update(mpm_ctx* c, void* stream) {

@@ -289,14 +289,12 @@ hipError_t launch_build_sparse(const DevParams& P, const uint32_t* skeys, int n,
 hipError_t launch_build_dense(const DevParams& P, const uint32_t* skeys, int n, int n_blocks, unsigned* partials,
                               hipStream_t s);
 hipError_t launch_p2g(const DevParams& P, const float* x, const float* v, const float* C, const float* tau, int n,
-                      const uint32_t* order, const uint32_t* skeys, int grid_blocks, hipStream_t s);
+                      const uint32_t* order, const uint32_t* skeys, uint32_t* osrc, int grid_blocks, hipStream_t s);
 hipError_t launch_grid_update(const DevParams& P, long long n_nodes_host, int grid_blocks, hipStream_t s);
 hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, const uint32_t* id_in,
                       const uint32_t* inst_in, float* x_out, float* v_out, float* C_out, float* F_out, float* tau_out,
                       uint32_t* id_out, uint32_t* inst_out, int n, const uint32_t* osrc, int block_size,
                       int grid_blocks, hipStream_t s);
-hipError_t launch_out_layout(const DevParams& P, const uint32_t* order, const uint32_t* skeys, uint32_t* osrc,
-                             hipStream_t s);
 hipError_t launch_clear_flags(DevCounters* c, hipStream_t s);
 hipError_t launch_g2p_adj(const DevParams& P, const float* x, const float* F, const float* const* out_bar, float* x_bar,
                           float* F_bar, int n, const uint32_t* order, const uint32_t* skeys, int grid_blocks,

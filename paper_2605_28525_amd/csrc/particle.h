@@ -171,13 +171,18 @@ __device__ void interleave_setup(Interleave<DIM>& L, const uint32_t* __restrict_
     __syncthreads();
 }
 
+// Output position of the particle of rank j in base cell c.
+template <int DIM>
+__device__ __forceinline__ int interleave_pos_cj(const Interleave<DIM>& L, int c, int j) {
+    if (j < IL_ROUNDS) return L.st + L.R[j] + __popcll(L.mask[j] & ((1ull << c) - 1ull));
+    return L.st + L.R[IL_ROUNDS] + L.op[c] + (j - IL_ROUNDS);
+}
+
 // Output position of the particle at sorted position i (sort key `key`).
 template <int DIM>
 __device__ __forceinline__ int interleave_pos(const Interleave<DIM>& L, int i, uint32_t key) {
     const int c = (int)(key & (Interleave<DIM>::NC - 1));
-    const int j = i - L.cs[c];
-    if (j < IL_ROUNDS) return L.st + L.R[j] + __popcll(L.mask[j] & ((1ull << c) - 1ull));
-    return L.st + L.R[IL_ROUNDS] + L.op[c] + (j - IL_ROUNDS);
+    return interleave_pos_cj<DIM>(L, c, i - L.cs[c]);
 }
 
 }  // namespace mpmx

@@ -37,13 +37,13 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
                                                  const float* __restrict__ v, const float* __restrict__ C,
                                                  const float* __restrict__ tau, int n,
                                                  const uint32_t* __restrict__ order,
-                                                 const uint32_t* __restrict__ skeys) {
+                                                 const uint32_t* __restrict__ skeys, uint32_t* __restrict__ osrc) {
     using T = Tile<DIM>;
     constexpr int NS = DIM == 3 ? 6 : 3;
     constexpr int NC = T::NPB;  // base cells per block
     constexpr int NK = DIM == 3 ? 27 : 9;
     __shared__ float tile[4][T::NP];
-    __shared__ int cs[NC], ce[NC];
+    __shared__ Interleave<DIM> il;  // cell ranges and the G2P output layout of the block
     __shared__ uint32_t ord[P2G_ORDER_STAGE];
     const int lane = threadIdx.x;
     const int nb = min(P.ctr->nb, P.block_cap);
@@ -53,28 +53,24 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
         if (cnt <= 0) continue;
         const int st = P.b_start[b], en = st + cnt;
         for (int t = lane; t < 4 * T::NP; t += 64) (&tile[0][0])[t] = 0.f;
-        for (int c = lane; c < NC; c += 64) cs[c] = ce[c] = 0;
         int bc[3], inst;
         block_coords<DIM>(P, b, bc, &inst);
         const InstMat mat = material(P, inst);
         const float mp = mat.p_mass;
         const float dtv = mat.dt * mat.p_vol0;
         const int org[3] = {bc[0] * BLK, bc[1] * BLK, bc[2] * BLK};
-        __syncthreads();
-        for (int i = st + lane; i < en; i += 64) {
-            if (i - st < P2G_ORDER_STAGE) ord[i - st] = order[i];
-            const uint32_t c = skeys[i] & (NC - 1);
-            if (i == st || (skeys[i - 1] & (NC - 1)) != c) cs[c] = i;
-            if (i == en - 1 || (skeys[i + 1] & (NC - 1)) != c) ce[c] = i + 1;
-        }
-        __syncthreads();
+        for (int i = st + lane; i < min(en, st + P2G_ORDER_STAGE); i += 64) ord[i - st] = order[i];
+        // cell ranges of the block and its G2P output layout (rank-major over
+        // the base cells); each lane records where G2P will store its cell's
+        // particles as it visits them (osrc)
+        interleave_setup<DIM>(il, skeys, st, en);
         float acc[NK][4];
 #pragma unroll
         for (int k = 0; k < NK; ++k) acc[k][0] = acc[k][1] = acc[k][2] = acc[k][3] = 0.f;
         int lb[3] = {lane & 3, (lane >> 2) & 3, DIM == 3 ? (lane >> 4) & 3 : 0};
         bool has = false;
         if (lane < NC) {
-            const int c0 = cs[lane], c1 = ce[lane];
+            const int c0 = il.cs[lane], c1 = il.ce[lane];
             has = c1 > c0;
             // software pipeline: the loads of particle i+1 are issued before the
             // 3^d-node accumulation of particle i
@@ -186,6 +182,7 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
                         }
                     }
                 }
+                osrc[interleave_pos_cj<DIM>(il, lane, i - c0)] = i - st < P2G_ORDER_STAGE ? ord[i - st] : order[i];
                 if (more) {
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
@@ -824,12 +821,12 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
 }
 
 hipError_t launch_p2g(const DevParams& P, const float* x, const float* v, const float* C, const float* tau, int n,
-                      const uint32_t* order, const uint32_t* skeys, int grid_blocks, hipStream_t s) {
+                      const uint32_t* order, const uint32_t* skeys, uint32_t* osrc, int grid_blocks, hipStream_t s) {
     const int g = P.dense ? 65536 : grid_blocks * 4;
     if (P.dim == 3)
-        k_p2g_cell<3><<<g, 64, 0, s>>>(P, x, v, C, tau, n, order, skeys);
+        k_p2g_cell<3><<<g, 64, 0, s>>>(P, x, v, C, tau, n, order, skeys, osrc);
     else
-        k_p2g_cell<2><<<g, 64, 0, s>>>(P, x, v, C, tau, n, order, skeys);
+        k_p2g_cell<2><<<g, 64, 0, s>>>(P, x, v, C, tau, n, order, skeys, osrc);
     return hipGetLastError();
 }
 
@@ -857,34 +854,6 @@ hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, 
         case 256 * 4 + 2: k_g2p<2, 256><<<grid_blocks, 256, 0, s>>>(P, in, out, n, osrc); break;
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
-}
-
-// Output layout of the G2P of this build: osrc[o] = input index of the
-// particle that G2P stores at position o (blocks in sort order, rank-major
-// inside a block).  One wave64 per owner block.
-template <int DIM>
-__global__ __launch_bounds__(64) void k_out_layout(DevParams P, const uint32_t* __restrict__ order,
-                                                   const uint32_t* __restrict__ skeys, uint32_t* __restrict__ osrc) {
-    __shared__ Interleave<DIM> il;
-    const int nb = min(P.ctr->nb, P.block_cap);
-    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
-        const int cnt = P.b_count[b];
-        if (cnt <= 0) continue;
-        const int st = P.b_start[b], en = st + cnt;
-        interleave_setup<DIM>(il, skeys, st, en);
-        for (int i = st + (int)threadIdx.x; i < en; i += 64) osrc[interleave_pos<DIM>(il, i, skeys[i])] = order[i];
-        __syncthreads();
-    }
-}
-
-hipError_t launch_out_layout(const DevParams& P, const uint32_t* order, const uint32_t* skeys, uint32_t* osrc,
-                             hipStream_t s) {
-    const int g = P.dense ? 65536 : 32768;
-    if (P.dim == 3)
-        k_out_layout<3><<<g, 64, 0, s>>>(P, order, skeys, osrc);
-    else
-        k_out_layout<2><<<g, 64, 0, s>>>(P, order, skeys, osrc);
     return hipGetLastError();
 }
 
