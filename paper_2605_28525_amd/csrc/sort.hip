@@ -9,7 +9,9 @@
 // a ballot) and adds each run's length to its digit with one LDS atomic.
 // Scatter: each wave ranks its keys round by round with a wave-wide digit match
 // (8 ballots) against per-wave running digit counts in LDS, which keeps the
-// sort stable without intra-tile barriers until the wave offsets are combined.
+// sort stable without intra-tile barriers until the wave offsets are combined;
+// the tile is then reordered by digit in LDS so that the global stores of each
+// digit's run are contiguous.
 #include "internal.h"
 
 namespace mpmx {
@@ -62,13 +64,16 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t* __restrict
                                                       const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
                                                       uint32_t* __restrict__ vout, int n, int shift,
                                                       const unsigned* __restrict__ hist, int n_tiles) {
-    __shared__ unsigned run[WG / 64][256];
-    __shared__ unsigned off[WG / 64][256];
+    __shared__ unsigned run[WG / 64][256];   // per-wave digit counts, then local offsets
+    __shared__ int delta[256];               // global minus local position, per digit
+    __shared__ unsigned lds_scan[WG / 64];
+    __shared__ uint32_t sk[SORT_TILE], sv[SORT_TILE];  // the tile ordered by digit
     for (int t = threadIdx.x; t < (WG / 64) * 256; t += WG) (&run[0][0])[t] = 0;
     __syncthreads();
     const int w = threadIdx.x >> 6, lane = __lane_id();
     const unsigned long long lt = (1ull << lane) - 1ull;
-    const int base = blockIdx.x * SORT_TILE + w * (SORT_TILE / (WG / 64));
+    const int tile0 = blockIdx.x * SORT_TILE;
+    const int base = tile0 + w * (SORT_TILE / (WG / 64));
     uint32_t k[SORT_ITEMS], v[SORT_ITEMS];
     unsigned rk[SORT_ITEMS];
 #pragma unroll
@@ -90,23 +95,45 @@ __global__ __launch_bounds__(WG) void k_radix_scatter(const uint32_t* __restrict
     }
     __syncthreads();
     {
+        // digit t: its first slot in the tile (exclusive scan over digits), the
+        // per-wave starts inside it, and the shift to its global position
         const int t = threadIdx.x;
-        unsigned o = hist[(size_t)t * n_tiles + blockIdx.x];
+        unsigned cnt = 0;
+#pragma unroll
+        for (int ww = 0; ww < WG / 64; ++ww) cnt += run[ww][t];
+        unsigned tot;
+        const unsigned start = wg_excl_scan(cnt, lds_scan, &tot);
+        delta[t] = (int)(hist[(size_t)t * n_tiles + blockIdx.x] - start);
+        unsigned o = start;
 #pragma unroll
         for (int ww = 0; ww < WG / 64; ++ww) {
-            off[ww][t] = o;
-            o += run[ww][t];
+            const unsigned c = run[ww][t];
+            run[ww][t] = o;
+            o += c;
         }
     }
     __syncthreads();
+    // stable placement inside the tile, ordered by digit
 #pragma unroll
     for (int r = 0; r < SORT_ITEMS; ++r) {
         const int pos = base + r * 64 + lane;
         if (pos < n) {
             const unsigned dg = (k[r] >> shift) & 255u;
-            const unsigned dst = off[w][dg] + rk[r];
-            kout[dst] = k[r];
-            vout[dst] = v[r];
+            const unsigned lp = run[w][dg] + rk[r];
+            sk[lp] = k[r];
+            sv[lp] = v[r];
+        }
+    }
+    __syncthreads();
+    // each digit's keys are contiguous in the tile and in the output: the
+    // stores of consecutive threads land on consecutive addresses
+    const int tile_n = min(SORT_TILE, n - tile0);
+    for (int j = threadIdx.x; j < tile_n; j += WG) {
+        const uint32_t kk = sk[j];
+        const unsigned dst = (unsigned)((int)j + delta[(kk >> shift) & 255u]);
+        if (dst < (unsigned)n) {
+            kout[dst] = kk;
+            vout[dst] = sv[j];
         }
     }
 }
