@@ -588,7 +588,8 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
     using T = Tile<DIM>;
     constexpr int NS = DIM == 3 ? 6 : 3;
     constexpr int DD = DIM * DIM;
-    __shared__ float4 vt[T::N];
+    constexpr int VSY = 20, VSZ = DIM == 3 ? 120 : 0;  // padded float4 tile: row / plane strides
+    __shared__ float4 vt[DIM == 3 ? 6 * VSZ : 6 * VSY];
     constexpr int MAXI = 2 * GS;
     __shared__ float xs[DIM][MAXI];
     __shared__ float fs[DD][MAXI];
@@ -672,7 +673,10 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
 #pragma unroll
         for (int k = 0; k < TPER; ++k) {
             const int t = tid + k * GS;
-            if (t < T::N) vt[t] = pt[k];
+            if (t < T::N) {
+                const int I = t % T::E, J = (t / T::E) % T::E, K = DIM == 3 ? t / (T::E * T::E) : 0;
+                vt[I + VSY * J + VSZ * K] = pt[k];
+            }
         }
         if (tid == 0) {
             int bc[3], inst;
@@ -722,7 +726,7 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
                     float S0[3] = {0, 0, 0}, S1[3] = {0, 0, 0}, S2[3] = {0, 0, 0};
 #pragma unroll
                     for (int kx = 0; kx < 3; ++kx) {
-                        const int idx = (lb[0] + kx) + T::E * ((lb[1] + ky) + (DIM == 3 ? T::E * (lb[2] + kz) : 0));
+                        const int idx = (lb[0] + kx) + VSY * (lb[1] + ky) + (DIM == 3 ? VSZ * (lb[2] + kz) : 0);
                         const float4 g = vt[idx];
                         const float vn[3] = {g.x, g.y, g.z};
                         const float wx = wt[0][kx], wdx = wt[0][kx] * dxn[0][kx], dwx = dw[0][kx];
