@@ -220,6 +220,26 @@ def ensemble_leg(steps, stream):
             "speedup": t_seq / t_batch, "unit": "particle-steps/s"}
 
 
+def measured_copy_gbs(mib=2048, reps=5):
+    """Device-to-device copy bandwidth of this GPU (read + write bytes / time),
+    the measured counterpart of the 8 TB/s spec peak."""
+    import torch
+    a = torch.empty(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * a.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def src_digest(*names):
     h = hashlib.sha256()
     for n in names:
@@ -351,6 +371,9 @@ def main():
         "build_ms_per_step": ph["build"],
         "build_roofline_frac": build_bytes / (ph["build"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "step_roofline_frac": step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        # against the bytes a step with G2P and the next P2G fused would move (192 B per particle)
+        "fused_bound_roofline_frac": 192.0 * n / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "measured_copy_GBps": measured_copy_gbs(),
         "active_blocks": nb,
         "active_fraction": n_slot / n_dense_nodes,
     }
