@@ -6,10 +6,10 @@
 // Their 3^d stencils cover a (4+2)^d node tile anchored at that block's origin,
 // which spans the block and its upper neighbours (2^d blocks).
 //
-//   P2G: a workgroup accumulates mass and momentum of its work item into an LDS
-//        tile (LDS float atomics), then flushes non-zero tile nodes to HBM with
-//        one global float atomic per channel, so global atomics fall from
-//        27 x 4 per particle to at most 4 per tile node.
+//   P2G: one wave per owner block accumulates the mass and momentum of the
+//        block's particles into an LDS tile, then flushes non-zero tile nodes to
+//        HBM with one global float atomic per channel, so global atomics fall
+//        from 27 x 4 per particle to at most 4 per tile node.
 //   G2P: a workgroup stages the tile's updated nodal velocities in LDS, then each
 //        thread gathers its 3^d nodes, updates the particle and writes it to its
 //        sorted position (structure-of-arrays, coalesced).
@@ -18,6 +18,8 @@
 // (both rounded once to float32, so small weights keep their relative accuracy)
 //   w = (u^2/2, 1/2 + t u, t^2/2),  dw/dxi = (-u, u - t, t).
 #include <stdlib.h>
+
+#include <type_traits>
 
 #include "internal.h"
 #include "particle.h"
@@ -30,8 +32,8 @@ namespace mpmx {
 // Inside a block the sorted order groups particles by the local index of their
 // base node (the low 2d bits of the sort key), and every particle with the same
 // base node scatters to the same 3^d nodes.  A lane therefore sums its cell's
-// particles into 27 x 4 registers and issues the LDS atomics once per cell, not
-// once per particle; the tile is then flushed to HBM as above.
+// particles into 27 x 4 registers and adds them to the LDS tile once per cell,
+// not once per particle; the tile is then flushed to HBM as above.
 template <int DIM>
 __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __restrict__ x,
                                                  const float* __restrict__ v, const float* __restrict__ C,
@@ -45,6 +47,7 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
     __shared__ float tile[4][T::NP];
     __shared__ Interleave<DIM> il;  // cell ranges and the G2P output layout of the block
     __shared__ uint32_t ord[P2G_ORDER_STAGE];
+    __shared__ int nbr[T::NB];  // compact indices of the blocks the tile covers
     const int lane = threadIdx.x;
     const int nb = min(P.ctr->nb, P.block_cap);
     const float dx = P.dxf, inv_dx = P.inv_dxf;
@@ -60,6 +63,7 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
         const float dtv = mat.dt * mat.p_vol0;
         const int org[3] = {bc[0] * BLK, bc[1] * BLK, bc[2] * BLK};
         for (int i = st + lane; i < min(en, st + P2G_ORDER_STAGE); i += 64) ord[i - st] = order[i];
+        if (lane < T::NB) nbr[lane] = P.b_nbr[(size_t)b * T::NB + lane];
         // cell ranges of the block and its G2P output layout (rank-major over
         // the base cells); each lane records where G2P will store its cell's
         // particles as it visits them (osrc)
@@ -68,30 +72,58 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
 #pragma unroll
         for (int k = 0; k < NK; ++k) acc[k][0] = acc[k][1] = acc[k][2] = acc[k][3] = 0.f;
         int lb[3] = {lane & 3, (lane >> 2) & 3, DIM == 3 ? (lane >> 4) & 3 : 0};
-        bool has = false;
-        if (lane < NC) {
-            const int c0 = il.cs[lane], c1 = il.ce[lane];
-            has = c1 > c0;
-            // software pipeline: the loads of particle i+1 are issued before the
-            // 3^d-node accumulation of particle i
-            float xp[3], vp[3], Cp[9], tp[6];
-            float xq[3], vq[3], Cq[9], tq[6];
-            auto load_particle = [&](int i, float* xo, float* vo, float* Co, float* to) {
-                const size_t q = i - st < P2G_ORDER_STAGE ? ord[i - st] : order[i];
+        const int c0 = lane < NC ? il.cs[lane] : 0, c1 = lane < NC ? il.ce[lane] : 0;
+        const bool has = c1 > c0;
+        // The walk over the lane's particles, with the source index read from
+        // the LDS copy of the permutation when the block fits it (the usual
+        // case) and from HBM otherwise: one uniform choice per block, so each
+        // variant uses one kind of load and the loads of the next particle stay
+        // in flight across the accumulation of the current one.
+        auto walk = [&](auto staged) {
+            constexpr bool STAGED = decltype(staged)::value;
+            auto src = [&](int i) -> uint32_t {
+                if constexpr (STAGED)
+                    return ord[i - st];
+                else
+                    return order[i];
+            };
+            // Software pipeline: the loads of particle i+1 are issued before the
+            // 3^d-node accumulation of particle i and consumed one iteration
+            // later.  They are issued on every iteration (the last one reloads
+            // its own particle), so the number of loads in flight never depends
+            // on the path taken and the wait for them lands after the
+            // accumulation, not before it.
+            float xn[3], vn[3], Cn[9], tn[6];
+            auto load_particle = [&](size_t q) {
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) {
-                    xo[a] = x[(size_t)a * n + q];
-                    vo[a] = v[(size_t)a * n + q];
+                    xn[a] = x[(size_t)a * n + q];
+                    vn[a] = v[(size_t)a * n + q];
                 }
 #pragma unroll
-                for (int k = 0; k < DIM * DIM; ++k) Co[k] = C[(size_t)k * n + q];
+                for (int k = 0; k < DIM * DIM; ++k) Cn[k] = C[(size_t)k * n + q];
 #pragma unroll
-                for (int k = 0; k < NS; ++k) to[k] = tau[(size_t)k * n + q];
+                for (int k = 0; k < NS; ++k) tn[k] = tau[(size_t)k * n + q];
             };
-            if (has) load_particle(c0, xp, vp, Cp, tp);
+            uint32_t qn = 0;
+            if (has) {
+                qn = src(c0);
+                load_particle(qn);
+            }
             for (int i = c0; i < c1; ++i) {
-                const bool more = i + 1 < c1;
-                if (more) load_particle(i + 1, xq, vq, Cq, tq);
+                float xp[3] = {0, 0, 0}, vp[3] = {0, 0, 0}, Cp[9], tp[6];
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    xp[a] = xn[a];
+                    vp[a] = vn[a];
+                }
+#pragma unroll
+                for (int k = 0; k < DIM * DIM; ++k) Cp[k] = Cn[k];
+#pragma unroll
+                for (int k = 0; k < NS; ++k) tp[k] = tn[k];
+                const uint32_t qp = qn;
+                qn = src(min(i + 1, c1 - 1));
+                load_particle(qn);
                 float t[3] = {0, 0, 0}, u[3] = {1, 1, 1};
                 particle_frame<DIM>(P, xp, org, lb, t, u);
                 float wt[3][3], dw[3][3];
@@ -182,20 +214,14 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
                         }
                     }
                 }
-                osrc[interleave_pos_cj<DIM>(il, lane, i - c0)] = i - st < P2G_ORDER_STAGE ? ord[i - st] : order[i];
-                if (more) {
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        xp[a] = xq[a];
-                        vp[a] = vq[a];
-                    }
-#pragma unroll
-                    for (int k = 0; k < 9; ++k) Cp[k] = Cq[k];
-#pragma unroll
-                    for (int k = 0; k < 6; ++k) tp[k] = tq[k];
-                }
+                // the G2P output position of this particle records its source
+                osrc[interleave_pos_cj<DIM>(il, lane, i - c0)] = qp;
             }
-        }
+        };
+        if (cnt <= P2G_ORDER_STAGE)
+            walk(std::true_type{});
+        else
+            walk(std::false_type{});
         // Merge the cell sums into the tile.  For a fixed offset k, distinct
         // cells address distinct nodes, so each offset is a conflict-free
         // read-add-write; the barrier orders successive offsets, which may hit
@@ -221,7 +247,7 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
             const float m = tile[3][tp], p0 = tile[0][tp], p1 = tile[1][tp], p2 = DIM == 3 ? tile[2][tp] : 0.f;
             if (m != 0.f || p0 != 0.f || p1 != 0.f || p2 != 0.f) {
                 const int d = (I >> 2) | ((J >> 2) << 1) | ((K >> 2) << 2);
-                const int phi = P.b_nbr[(size_t)b * T::NB + d];
+                const int phi = nbr[d];
                 if (phi >= 0) {
                     const int l = (I & 3) + BLK * ((J & 3) + BLK * (K & 3));
                     float* g = reinterpret_cast<float*>(&P.grid[(size_t)phi * T::NPB + l]);
