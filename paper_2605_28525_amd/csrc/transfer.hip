@@ -619,68 +619,96 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
     constexpr int MAXI = 2 * GS;
     __shared__ float xs[DIM][MAXI];
     __shared__ float fs[DD][MAXI];
-    __shared__ int org[4];
     const int n_work = min(P.ctr->n_work, P.work_cap);
     const float dx = P.dxf, inv_dx = P.inv_dxf;
     const float cscale = 4.f * inv_dx * inv_dx;  // D_p^{-1} = (4/dx^2) I for quadratic B-splines
-    // Software pipeline over work items: the gathers of the next item are
-    // issued during the current item's compute phases and carried in
-    // registers (source indices and tile slots after phase 0, particle data and
-    // grid tile after phase 1), then staged in LDS at the top of the loop.
+    // Software pipeline over the items w, w + G, w + 2G, ... of a workgroup
+    // (G workgroups).  While item w is computed, later items are being
+    // gathered: the work record of item w + 2G and the source indices, tile
+    // slots and block key of item w + G are loaded after phase 0, the particle
+    // data, grid tile and material of item w + G after phase 1.  Each load is
+    // consumed at least one compute phase after it was issued, so the
+    // dependent chain record -> indices -> data stays off the critical path.
+    // Every lane issues every load (indices past an item or the tile are
+    // clamped into range and the values are discarded), so the number of
+    // loads in flight does not depend on the lane's position in the item.
     constexpr int PER = MAXI / GS;                 // particles per thread
     constexpr int TPER = (T::N + GS - 1) / GS;     // tile nodes per thread
     const int tid = threadIdx.x;
+    const int G = gridDim.x;
+    struct Rec {
+        int blk, s, e;  // raw record; the item length is formed where it is used
+    };
     uint32_t pq[PER];
     int pphi[TPER];
+    uint64_t pkey = 0;
     float px[PER][DIM], pF[PER][DD];
     uint32_t pid[PER], pin[PER];
     float4 pt[TPER];
-    auto fetch_index = [&](int blk, int s, int L) {
+    InstMat pmat;
+    auto fetch_rec = [&](int i) {
+        i = min(i, n_work - 1);  // past the end: the last record, never computed
+        // The record is the same in every lane; the empty asm hides that, so
+        // the values stay in vector registers and no read-first-lane right
+        // after the loads waits for them.
+        asm volatile("" : "+v"(i));
+        Rec r;
+        r.blk = P.w_block[i];
+        r.s = P.w_start[i];
+        r.e = P.w_end[i];
+        return r;
+    };
+    auto fetch_index = [&](const Rec& R) {
+        const int RL = min(R.e - R.s, MAXI);
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int r = tid + k * GS;
-            pq[k] = r < L ? osrc[s + r] : 0u;
-        }
+        for (int k = 0; k < PER; ++k) pq[k] = osrc[R.s + min(tid + k * GS, RL - 1)];
 #pragma unroll
         for (int k = 0; k < TPER; ++k) {
-            const int t = tid + k * GS;
+            const int t = min(tid + k * GS, T::N - 1);
             const int I = t % T::E, J = (t / T::E) % T::E, K = DIM == 3 ? t / (T::E * T::E) : 0;
             const int d = (I >> 2) | ((J >> 2) << 1) | ((K >> 2) << 2);
-            pphi[k] = t < T::N ? P.b_nbr[blk * T::NB + d] : -1;
+            pphi[k] = P.b_nbr[R.blk * T::NB + d];
         }
+        // block key (sparse grids); a dense grid has no key table and reads a
+        // discarded word of the neighbour table instead, so that the load is
+        // unconditional and its value is not needed before the next item
+        const uint64_t* kp = P.dense ? reinterpret_cast<const uint64_t*>(P.b_nbr + (size_t)R.blk * T::NB)
+                                     : P.b_keys + R.blk;
+        pkey = *kp;
     };
-    auto fetch_data = [&](int L) {
+    auto fetch_data = [&]() {
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
-            const int r = tid + k * GS;
-            if (r < L) {
-                const size_t q = pq[k];
+            const size_t q = pq[k];
 #pragma unroll
-                for (int a = 0; a < DIM; ++a) px[k][a] = in.x[(size_t)a * n + q];
+            for (int a = 0; a < DIM; ++a) px[k][a] = in.x[(size_t)a * n + q];
 #pragma unroll
-                for (int j = 0; j < DD; ++j) pF[k][j] = in.F[(size_t)j * n + q];
-                pid[k] = in.id ? in.id[q] : (uint32_t)q;
-                pin[k] = in.inst ? in.inst[q] : 0u;
-            }
+            for (int j = 0; j < DD; ++j) pF[k][j] = in.F[(size_t)j * n + q];
+            pid[k] = in.id ? in.id[q] : (uint32_t)q;
+            pin[k] = in.inst ? in.inst[q] : 0u;
         }
 #pragma unroll
         for (int k = 0; k < TPER; ++k) {
-            const int t = tid + k * GS;
+            const int t = min(tid + k * GS, T::N - 1);
             const int I = t % T::E, J = (t / T::E) % T::E, K = DIM == 3 ? t / (T::E * T::E) : 0;
             const int l = (I & 3) + BLK * ((J & 3) + BLK * (K & 3));
-            pt[k] = pphi[k] >= 0 ? P.grid[(size_t)pphi[k] * T::NPB + l] : make_float4(0.f, 0.f, 0.f, 0.f);
+            // a missing neighbour block (slot < 0) is zeroed when staged
+            pt[k] = P.grid[(size_t)max(pphi[k], 0) * T::NPB + l];
         }
+        int bc[3], inst = 0;
+        if (!P.dense) unblock_key<DIM>(P, pkey, bc, &inst);
+        pmat = material(P, inst);
     };
     int w = blockIdx.x;
-    int blk = 0, s = 0, L = 0;
-    if (w < n_work) {
-        blk = P.w_block[w];
-        s = P.w_start[w];
-        L = min(P.w_end[w] - s, MAXI);
-        fetch_index(blk, s, L);
-        fetch_data(L);
-    }
+    if (w >= n_work) return;
+    Rec cur = fetch_rec(w);
+    fetch_index(cur);
+    fetch_data();
+    Rec nxt = fetch_rec(w + G);
     while (w < n_work) {
+        const int s = cur.s, L = min(cur.e - cur.s, MAXI);
+        const uint64_t key = P.dense ? (uint64_t)cur.blk : pkey;
+        const InstMat mat = pmat;
         // phase 0: stage the gathered item in LDS; ids travel with the
         // particles (output positions s .. s+L-1 are contiguous, so every
         // store coalesces; osrc named the input particle of each)
@@ -701,27 +729,19 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
             const int t = tid + k * GS;
             if (t < T::N) {
                 const int I = t % T::E, J = (t / T::E) % T::E, K = DIM == 3 ? t / (T::E * T::E) : 0;
-                vt[I + VSY * J + VSZ * K] = pt[k];
+                vt[I + VSY * J + VSZ * K] = pphi[k] >= 0 ? pt[k] : make_float4(0.f, 0.f, 0.f, 0.f);
             }
         }
-        if (tid == 0) {
-            int bc[3], inst;
-            block_coords<DIM>(P, blk, bc, &inst);
-            org[0] = bc[0] * BLK;
-            org[1] = bc[1] * BLK;
-            org[2] = bc[2] * BLK;
-            org[3] = inst;
-        }
         __syncthreads();
-        const int wn = w + gridDim.x;
-        int nblk = 0, ns = 0, nL = 0;
-        if (wn < n_work) {
-            nblk = P.w_block[wn];
-            ns = P.w_start[wn];
-            nL = min(P.w_end[wn] - ns, MAXI);
-            fetch_index(nblk, ns, nL);
-        }
-        const InstMat mat = material(P, org[3]);
+        fetch_index(nxt);
+        const Rec nn = fetch_rec(w + 2 * G);
+        int org[3], inst = 0;
+        if (P.dense)
+            linear_to_block<DIM>(P, (uint32_t)key, org);
+        else
+            unblock_key<DIM>(P, key, org, &inst);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) org[a] *= BLK;
         const float dt = mat.dt;
         // phase 1: grid gather, new position, velocity and affine matrix,
         // F_trial = (I + dt grad v) F (Eq. 17) kept in LDS
@@ -818,7 +838,7 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
             if (!finite) raise_flag(P.ctr, MPM_FLAG_NAN);
         }
         __syncthreads();
-        if (wn < n_work) fetch_data(nL);  // in flight during phase 2
+        fetch_data();  // in flight during phase 2
         // phase 2: constitutive update (its register live range is separate)
 #pragma unroll 1
         for (int r = threadIdx.x; r < L; r += GS) {
@@ -843,10 +863,9 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
             if (flags) raise_flag(P.ctr, flags);
         }
         __syncthreads();
-        w = wn;
-        blk = nblk;
-        s = ns;
-        L = nL;
+        w += G;
+        cur = nxt;
+        nxt = nn;
     }
 }
 
