@@ -94,6 +94,16 @@ typedef struct mpm_ctx mpm_ctx;
                                     nodal velocity, grid adjoint, per-particle
                                     scratch); the grid update then also records u.
                                     Walls only: not allowed with a heightmap. */
+#define MPM_FLAG_FULL_SORT    4  /* sort from scratch on every build.  By default a
+                                    sparse build of a context without MPM_FLAG_ADJOINT
+                                    that follows a build of the same number of
+                                    particles re-sorts incrementally: particles that
+                                    keep their owner block keep their order, the
+                                    others are routed through the previous build's
+                                    hash table.  Either way each owner block's
+                                    particles are contiguous with base cells
+                                    ascending; block order and the order of movers
+                                    inside a cell differ between the two. */
 
 /* Material and time step of one instance of an ensemble (see n_instances). */
 typedef struct mpm_instance {
@@ -166,10 +176,15 @@ const char* mpm_status_string(int status);
  * addressing table (packed key, Eq. 22; 64-bit mixer, Eq. 23; slot h & (H-1),
  * Eq. 24; linear probing, Eq. 25), records the node-level active mask of each
  * block, and compacts the occupied slots into Phi in [0, n_blocks) by a prefix
- * scan.  A pure function of the positions.  If more blocks are touched than
- * block_capacity, or a probe sequence finds no slot, MPM_FLAG_OVERFLOW is
- * latched (with MPM_FLAG_SYNC_REBUILD the call rebuilds instead, Algorithm 7).
- * In MPM_GRID_DENSE mode Phi is the linear block index of the whole domain. */
+ * scan.  The active set (blocks and node masks) is a pure function of the
+ * positions.  The particle order is one in which each owner block's particles
+ * are contiguous with their base cells ascending; after a build of the same
+ * number of particles it is derived incrementally from that build's order
+ * (see MPM_FLAG_FULL_SORT).  If more blocks are touched than block_capacity,
+ * or a probe sequence finds no slot, MPM_FLAG_OVERFLOW is latched (with
+ * MPM_FLAG_SYNC_REBUILD the call rebuilds instead, Algorithm 7, sorting from
+ * scratch).  In MPM_GRID_DENSE mode Phi is the linear block index of the whole
+ * domain. */
 int mpm_sparse_build(mpm_ctx* ctx, const mpm_particles* p, void* stream);
 
 /* P2G onto the compact storage (Eqs. 6, 7, 9): clears the active blocks and
@@ -184,7 +199,7 @@ int mpm_grid_update(mpm_ctx* ctx, void* stream);
 
 /* G2P (Eqs. 13-17) and the constitutive update.  Reads `in` through the sort
  * permutation of the last build and writes the advanced state to `out`
- * grouped by owner block in Phi's sort order; inside a block's range the
+ * grouped by owner block in the build's particle order; inside a block's range the
  * particles are stored rank-major over the block's cells (first particle of
  * each occupied cell, then the second, ... up to rank 31, then the rest cell
  * by cell), which makes the next step's P2G loads contiguous.

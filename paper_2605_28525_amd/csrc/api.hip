@@ -58,6 +58,15 @@ struct mpm_ctx {
     DevParams P{};
     bool built = false;
     int built_n = -1;
+    // incremental re-sort: the block segments, hash table and sorted keys of
+    // the last build (for seg_n particles) are intact and may seed the next sort
+    bool seg_valid = false;
+    int seg_n = -1;
+    uint32_t *rs_stay = nullptr, *rs_in = nullptr, *rs_off = nullptr, *rs_oldblk = nullptr;
+    unsigned *rs_cnt = nullptr, *rs_start = nullptr;
+    uint64_t* nh_keys = nullptr;
+    uint32_t* nh_cnt = nullptr;
+    int* nh_idx = nullptr;
     uint32_t* order = nullptr;
     uint32_t* skeys = nullptr;
     uint32_t* osrc = nullptr;  // G2P output position -> input index (the spare sort value buffer)
@@ -104,6 +113,16 @@ void free_capacity_buffers(mpm_ctx* c) {
     dfree(c->grid_u);
     dfree(c->grid_bar);
     dfree(c->partials);
+    dfree(c->rs_stay);
+    dfree(c->rs_in);
+    dfree(c->rs_off);
+    dfree(c->rs_oldblk);
+    dfree(c->rs_cnt);
+    dfree(c->rs_start);
+    dfree(c->nh_keys);
+    dfree(c->nh_cnt);
+    dfree(c->nh_idx);
+    c->seg_valid = false;
 }
 
 void free_all(mpm_ctx* c) {
@@ -211,6 +230,15 @@ void fill_params(mpm_ctx* c) {
     P.n_inst = c->n_inst;
     P.blk_bits = c->blk_bits;
     P.inst = c->inst;
+    P.rs_stay = c->rs_stay;
+    P.rs_in = c->rs_in;
+    P.rs_off = c->rs_off;
+    P.rs_cnt = c->rs_cnt;
+    P.rs_start = c->rs_start;
+    P.rs_oldblk = c->rs_oldblk;
+    P.nh_keys = c->nh_keys;
+    P.nh_cnt = c->nh_cnt;
+    P.nh_idx = c->nh_idx;
     fill_material(c);
 }
 
@@ -222,7 +250,8 @@ int alloc_capacity_buffers(mpm_ctx* c) {
     const size_t cap = (size_t)c->block_cap;
     // room for the smallest work-item size mpm_set_tuning accepts
     c->work_cap = c->block_cap + c->max_particles / MIN_CHUNK + 1;
-    int scan_n = std::max({radix_hist_size(c->max_particles), (int)H, c->block_cap, 1});
+    int scan_n = std::max({radix_hist_size(c->max_particles), (int)H, 2 * c->block_cap, 1});
+    const bool resort = !c->dense && !c->adjoint;  // the incremental re-sort serves these contexts
     hipError_t e = hipSuccess;
     if (!c->dense) {
         e = e ? e : dalloc(&c->h_keys, H);
@@ -247,12 +276,33 @@ int alloc_capacity_buffers(mpm_ctx* c) {
         e = e ? e : dalloc(&c->grid_bar, cap * NPB);
     }
     e = e ? e : dalloc(&c->partials, (size_t)scan_partials_size(scan_n));
+    if (resort) {
+        e = e ? e : dalloc(&c->rs_stay, cap * NPB);
+        e = e ? e : dalloc(&c->rs_in, 2 * cap * NPB);
+        e = e ? e : dalloc(&c->rs_off, 2 * cap * NPB);
+        e = e ? e : dalloc(&c->rs_oldblk, cap);
+        e = e ? e : dalloc(&c->rs_cnt, 2 * cap);
+        e = e ? e : dalloc(&c->rs_start, 2 * cap);
+        e = e ? e : dalloc(&c->nh_keys, H);
+        e = e ? e : dalloc(&c->nh_cnt, H * NPB);
+        e = e ? e : dalloc(&c->nh_idx, H);
+    }
     if (e != hipSuccess) {
         (void)hipGetLastError();
         free_capacity_buffers(c);
         return MPM_ERR_NOMEM;
     }
     fill_params(c);
+    if (resort) {
+        // zeroed mover counters and an empty second table, as every re-sort leaves them
+        e = launch_resort_init(c->P, (unsigned)H, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            free_capacity_buffers(c);
+            return MPM_ERR_HIP;
+        }
+    }
     return MPM_OK;
 }
 
@@ -265,14 +315,29 @@ bool particles_ok(const mpm_ctx* c, const mpm_particles* p, bool need_state) {
 
 int hip_status(hipError_t e) { return e == hipSuccess ? MPM_OK : MPM_ERR_HIP; }
 
-int build_once(mpm_ctx* c, const mpm_particles* p, hipStream_t s) {
+// One build.  `reuse`: the previous build's segments, hash table and sorted
+// keys (same particle count) seed an incremental re-sort instead of the full
+// radix sort; the new sorted keys then take the previous ones' buffer.
+int build_once(mpm_ctx* c, const mpm_particles* p, hipStream_t s, bool reuse) {
     const int n = p->n;
-    hipError_t e = launch_bin(c->P, p->x, p->inst, n, c->k1, s);
-    if (e != hipSuccess) return MPM_ERR_HIP;
+    hipError_t e;
     uint32_t *ko = c->k1, *vo = c->v0;
-    if (n > 0) {
-        e = radix_sort(c->k1, c->k0, c->k1, c->v0, c->v1, n, c->key_bits, c->hist, c->partials, &ko, &vo, s);
+    if (reuse && n > 0) {
+        uint32_t* prev = c->skeys;
+        uint32_t* fresh = prev == c->k0 ? c->k1 : c->k0;
+        vo = c->order;
+        e = launch_bin(c->P, p->x, p->inst, n, fresh, s);
         if (e != hipSuccess) return MPM_ERR_HIP;
+        e = launch_resort(c->P, prev, fresh, prev, vo, n, 1u << c->H_log2, c->partials, s);
+        if (e != hipSuccess) return MPM_ERR_HIP;
+        ko = prev;
+    } else {
+        e = launch_bin(c->P, p->x, p->inst, n, c->k1, s);
+        if (e != hipSuccess) return MPM_ERR_HIP;
+        if (n > 0) {
+            e = radix_sort(c->k1, c->k0, c->k1, c->v0, c->v1, n, c->key_bits, c->hist, c->partials, &ko, &vo, s);
+            if (e != hipSuccess) return MPM_ERR_HIP;
+        }
     }
     c->skeys = ko;
     c->order = vo;
@@ -472,7 +537,10 @@ int mpm_set_material(mpm_ctx* c, float E, float nu, float friction_deg, float dt
 int mpm_sparse_build(mpm_ctx* c, const mpm_particles* p, void* stream) {
     if (!c || !particles_ok(c, p, false)) return MPM_ERR_ARG;
     hipStream_t s = (hipStream_t)stream;
-    int st = build_once(c, p, s);
+    const bool reuse = c->seg_valid && c->seg_n == p->n && !(c->prm.flags & MPM_FLAG_FULL_SORT);
+    c->built = false;
+    c->seg_valid = false;
+    int st = build_once(c, p, s, reuse);
     if (st != MPM_OK) return st;
     if (!c->dense && (c->prm.flags & MPM_FLAG_SYNC_REBUILD)) {
         // Algorithm 7: on overflow, double the table (and the block capacity)
@@ -492,12 +560,14 @@ int mpm_sparse_build(mpm_ctx* c, const mpm_particles* p, void* stream) {
             if (hipMemcpyAsync(&c->ctr->flags, &keep, sizeof(unsigned), hipMemcpyHostToDevice, s) != hipSuccess)
                 return MPM_ERR_HIP;
             if (hipStreamSynchronize(s) != hipSuccess) return MPM_ERR_HIP;
-            st = build_once(c, p, s);
+            st = build_once(c, p, s, false);
             if (st != MPM_OK) return st;
         }
     }
     c->built = true;
     c->built_n = p->n;
+    c->seg_valid = !c->dense && !c->adjoint && c->rs_in != nullptr;
+    c->seg_n = p->n;
     return MPM_OK;
 }
 

@@ -3,7 +3,9 @@
 //   k_bin           base node per particle (float64 index arithmetic), owner
 //                   block and a u32 sort key = linear block id << 2d | local
 //                   cell of the base node;
-//   radix sort      (sort.hip) groups particles by owner block;
+//   sort            groups particles by owner block: the radix sort of
+//                   sort.hip, or after a build of as many particles the
+//                   incremental re-sort of resort.hip;
 //   k_hash_clear    keys <- EMPTY, masks <- 0 (Algorithm 5, initialisation);
 //   k_hash_insert   per sorted particle: the stencil touches its owner block and
 //                   only the upper neighbours it spills into (base local index
@@ -96,17 +98,6 @@ __device__ int hash_insert(const DevParams& P, uint64_t K) {
         s = (s + 1) & P.h_mask_bits;
     }
     raise_flag(P.ctr, MPM_FLAG_OVERFLOW);
-    return -1;
-}
-
-__device__ int hash_lookup(const DevParams& P, uint64_t K) {
-    unsigned s = (unsigned)mix64(K) & P.h_mask_bits;
-    for (int r = 0; r < P.n_probe; ++r) {
-        uint64_t cur = P.h_keys[s];
-        if (cur == K) return P.h_vals[s];
-        if (cur == EMPTY_KEY) return -1;
-        s = (s + 1) & P.h_mask_bits;
-    }
     return -1;
 }
 

@@ -39,7 +39,9 @@ struct DevCounters {
     int n_touched;   // occupied hash slots (may exceed capacity on overflow)
     int n_work;      // P2G/G2P work items
     unsigned flags;  // sticky MPM_FLAG_* bits
-    int pad[4];
+    int rs_n_new;    // incremental re-sort: blocks without a previous slot
+    int rs_n_ent;    //   entries (previous blocks, then new blocks)
+    int pad[2];
 };
 
 // Per-instance material and step constants (one entry for a single simulation).
@@ -103,6 +105,17 @@ struct DevParams {
     float* param_bar;    // accumulated dL/dE, dL/dphi (per degree)
     float E;
     float dalpha_dphi;   // d alpha / d phi, per degree
+    // incremental re-sort (resort.hip): per entry (previous block, then new
+    // block) and base cell, NC = 4^d columns
+    uint32_t* rs_stay;    // stayers per previous block and cell
+    uint32_t* rs_in;      // movers per entry and cell, then the movers placed so far
+    uint32_t* rs_off;     // first sorted position per entry and cell
+    unsigned* rs_cnt;     // particles per entry
+    unsigned* rs_start;   // first sorted position per entry
+    uint32_t* rs_oldblk;  // owner-block part of the sort key of each previous block
+    uint64_t* nh_keys;    // second hash table (same size as the block table): blocks
+    uint32_t* nh_cnt;     //   with no previous slot, their movers per cell,
+    int* nh_idx;          //   and their entry index
     // ensembles
     int n_inst;          // 1 = single simulation
     int blk_bits;        // bits of the linear block id inside the sort key
@@ -224,6 +237,19 @@ __device__ __forceinline__ InstMat material(const DevParams& P, int inst) {
     return m;
 }
 
+// Compact index of block key K in the block hash table (Eqs. 23-25), -1 if
+// the key has no slot or its block did not fit the capacity.
+__device__ __forceinline__ int hash_lookup(const DevParams& P, uint64_t K) {
+    unsigned s = (unsigned)mix64(K) & P.h_mask_bits;
+    for (int r = 0; r < P.n_probe; ++r) {
+        const uint64_t cur = P.h_keys[s];
+        if (cur == K) return P.h_vals[s];
+        if (cur == EMPTY_KEY) return -1;
+        s = (s + 1) & P.h_mask_bits;
+    }
+    return -1;
+}
+
 __device__ __forceinline__ unsigned long long wave_ballot(bool p) { return __ballot(p); }
 
 __device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
@@ -284,6 +310,9 @@ hipError_t radix_sort(const uint32_t* keys_in, uint32_t* k0, uint32_t* k1, uint3
 int radix_hist_size(int n);
 
 hipError_t launch_bin(const DevParams& P, const float* x, const uint32_t* inst, int n, uint32_t* keys, hipStream_t s);
+hipError_t launch_resort(const DevParams& P, uint32_t* keys_prev, const uint32_t* keys_new, uint32_t* keys_out,
+                         uint32_t* vals_out, int n, unsigned H, unsigned* partials, hipStream_t s);
+hipError_t launch_resort_init(const DevParams& P, unsigned H, hipStream_t s);
 hipError_t launch_build_sparse(const DevParams& P, const uint32_t* skeys, int n, unsigned H, unsigned* partials,
                                hipStream_t s);
 hipError_t launch_build_dense(const DevParams& P, const uint32_t* skeys, int n, int n_blocks, unsigned* partials,

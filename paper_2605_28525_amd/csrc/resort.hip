@@ -1,0 +1,354 @@
+// Incremental re-sort of the particles by owner block: the alternative to the
+// full radix sort (sort.hip) for a build that follows a build of the same
+// number of particles on the same context.
+//
+// The particle at position i of a step's G2P output belongs to the owner
+// segment [b_start, b_start + b_count) of the previous build that contains i,
+// and a step moves a particle by a fraction of a cell, so nearly all particles
+// keep their owner block.  What the later stages need is a grouping, not a
+// global order: each owner block's particles contiguous, base cells ascending
+// inside the block.  The new layout keeps the previous blocks in their
+// previous order and appends the blocks that had no slot before:
+//   count    one wave per previous block: the particles whose new key has the
+//            block's owner part ("stayers") are counted per base cell; every
+//            other particle ("mover") looks its new block up in the previous
+//            hash table and adds to that block's per-cell mover count, or, for
+//            a block without a previous slot, claims a slot of a second hash
+//            table and counts there;
+//   new      compaction of the second table: its blocks become the entries
+//            after the previous blocks;
+//   offsets  per entry, particles per base cell = stayers + movers; exclusive
+//            scans over the entries (first position) and over the cells;
+//   place    one wave per previous block: stayers keep their relative order
+//            (per-cell ranks from a wave-wide match), movers go after the
+//            stayers of their cell, in the order their atomic slot claims land;
+//   reset    the per-entry mover counts and the second table are cleared for
+//            the next build.
+// Cost: two reads of the new keys and one write of keys and values, against
+// 2-4 full read/write passes of the radix sort.
+#include "internal.h"
+
+namespace mpmx {
+
+namespace {
+
+// Lanes whose value v (its low BITS bits) equals this lane's, among lanes with
+// `valid` set.  Every lane of the wave must call it.
+template <int BITS>
+__device__ __forceinline__ unsigned long long match_bits(unsigned v, bool valid) {
+    unsigned long long m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+        const bool bit = (v >> b) & 1u;
+        const unsigned long long bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+// 64-bit block key (Eq. 22, instance folded in) of the owner part of a sort key.
+template <int DIM>
+__device__ __forceinline__ uint64_t owner_block_key(const DevParams& P, uint32_t owner) {
+    const uint32_t bl = owner & ((1u << P.blk_bits) - 1u);
+    const int inst = (int)(owner >> P.blk_bits);
+    int bc[3];
+    linear_to_block<DIM>(P, bl, bc);
+    return block_key<DIM>(P, bc[0], bc[1], bc[2], inst);
+}
+
+// Second table: same size, hash and probing as the block table.
+__device__ int nh_insert(const DevParams& P, uint64_t K) {
+    unsigned s = (unsigned)mix64(K) & P.h_mask_bits;
+    for (int r = 0; r < P.n_probe; ++r) {
+        const uint64_t cur = __hip_atomic_load(&P.nh_keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == K) return (int)s;
+        if (cur == EMPTY_KEY) {
+            const uint64_t old = atomicCAS((unsigned long long*)&P.nh_keys[s], (unsigned long long)EMPTY_KEY,
+                                           (unsigned long long)K);
+            if (old == EMPTY_KEY || old == K) return (int)s;
+        }
+        s = (s + 1) & P.h_mask_bits;
+    }
+    return -1;
+}
+
+__device__ int nh_lookup(const DevParams& P, uint64_t K) {
+    unsigned s = (unsigned)mix64(K) & P.h_mask_bits;
+    for (int r = 0; r < P.n_probe; ++r) {
+        const uint64_t cur = P.nh_keys[s];
+        if (cur == K) return (int)s;
+        if (cur == EMPTY_KEY) return -1;
+        s = (s + 1) & P.h_mask_bits;
+    }
+    return -1;
+}
+
+}  // namespace
+
+// count: one wave per previous block e (its segment of the previous order).
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_rs_count(DevParams P, const uint32_t* __restrict__ keys_prev,
+                                                 const uint32_t* __restrict__ keys_new) {
+    constexpr int CB = 2 * DIM, NC = 1 << CB;
+    __shared__ unsigned cnt[WG / 64][64];
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    const int nb = min(P.ctr->nb, P.block_cap);
+    for (int e = blockIdx.x * (WG / 64) + w; e < nb; e += gridDim.x * (WG / 64)) {
+        const int s = P.b_start[e], c = P.b_count[e];
+        cnt[w][lane] = 0u;
+        uint32_t owner = ~0u;
+        if (c > 0) {
+            owner = keys_prev[s] >> CB;
+            for (int i0 = s; i0 < s + c; i0 += 64) {
+                const int i = i0 + lane;
+                const bool valid = i < s + c;
+                const uint32_t k = valid ? keys_new[i] : 0u;
+                const bool stay = valid && (k >> CB) == owner;
+                const uint32_t cell = k & (NC - 1);
+                const unsigned long long m = match_bits<CB>(cell, stay);
+                if (stay && (m & lt) == 0ull) cnt[w][cell] += (unsigned)__popcll(m);  // one leader per cell
+                if (valid && !stay) {
+                    const uint64_t K = owner_block_key<DIM>(P, k >> CB);
+                    const int phi = hash_lookup(P, K);
+                    if (phi >= 0) {
+                        atomicAdd(&P.rs_in[(size_t)phi * NC + cell], 1u);
+                    } else {
+                        const int slot = nh_insert(P, K);
+                        if (slot >= 0)
+                            atomicAdd(&P.nh_cnt[(size_t)slot * NC + cell], 1u);
+                        else
+                            raise_flag(P.ctr, MPM_FLAG_OVERFLOW);
+                    }
+                }
+            }
+        }
+        if (lane < NC) P.rs_stay[(size_t)e * NC + lane] = cnt[w][lane];
+        if (lane == 0) P.rs_oldblk[e] = owner;
+    }
+}
+
+// new: occupied slots of the second table, counted per tile ...
+__global__ __launch_bounds__(WG) void k_rs_new_count(DevParams P, int H, unsigned* __restrict__ partials) {
+    __shared__ unsigned lds[WG / 64];
+    const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    unsigned s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        const int idx = base + j;
+        if (idx < H && P.nh_keys[idx] != EMPTY_KEY) ++s;
+    }
+    unsigned tot;
+    wg_excl_scan(s, lds, &tot);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// ... then numbered after the previous blocks (slot order), with their mover
+// counts moved into the entry rows.
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_rs_new_write(DevParams P, int H, const unsigned* __restrict__ partials) {
+    constexpr int NC = 1 << (2 * DIM);
+    __shared__ unsigned lds[WG / 64];
+    const int nb = min(P.ctr->nb, P.block_cap);
+    const int max_ent = 2 * P.block_cap;
+    const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    bool occ[SCAN_ITEMS];
+    unsigned s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        const int idx = base + j;
+        occ[j] = idx < H && P.nh_keys[idx] != EMPTY_KEY;
+        s += occ[j];
+    }
+    unsigned tot;
+    unsigned j = wg_excl_scan(s, lds, &tot) + partials[blockIdx.x];
+    bool over = false;
+#pragma unroll
+    for (int q = 0; q < SCAN_ITEMS; ++q) {
+        if (!occ[q]) continue;
+        const int slot = base + q;
+        const int e = nb + (int)j;
+        uint32_t* src = &P.nh_cnt[(size_t)slot * NC];
+        if (e < max_ent) {
+            P.nh_idx[slot] = e;
+            uint32_t* dst = &P.rs_in[(size_t)e * NC];
+            for (int c = 0; c < NC; ++c) dst[c] = src[c];
+        } else {
+            P.nh_idx[slot] = -1;
+            over = true;
+        }
+        for (int c = 0; c < NC; ++c) src[c] = 0u;
+        ++j;
+    }
+    if (over) raise_flag(P.ctr, MPM_FLAG_OVERFLOW);
+    if (blockIdx.x == 0 && threadIdx.x == 0) P.ctr->rs_n_ent = min(nb + P.ctr->rs_n_new, max_ent);
+}
+
+// Particles of entry e in base cell `lane` (0 for lanes >= NC).
+template <int DIM>
+__device__ __forceinline__ unsigned entry_cell_count(const DevParams& P, int e, int nb, int lane) {
+    constexpr int NC = 1 << (2 * DIM);
+    if (lane >= NC) return 0u;
+    const unsigned st = e < nb ? P.rs_stay[(size_t)e * NC + lane] : 0u;
+    return st + P.rs_in[(size_t)e * NC + lane];
+}
+
+// offsets, first half: particles per entry (one wave per entry).
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_rs_entry_count(DevParams P) {
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
+    const int nb = min(P.ctr->nb, P.block_cap);
+    const int ne = P.ctr->rs_n_ent;
+    for (int e = blockIdx.x * (WG / 64) + w; e < ne; e += gridDim.x * (WG / 64)) {
+        const unsigned tot = wave_incl_scan(entry_cell_count<DIM>(P, e, nb, lane));
+        if (lane == 63) P.rs_cnt[e] = tot;
+    }
+}
+
+// offsets, second half: first position per entry and cell; the mover counts
+// become the counters of movers placed.
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_rs_offsets(DevParams P) {
+    constexpr int NC = 1 << (2 * DIM);
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
+    const int nb = min(P.ctr->nb, P.block_cap);
+    const int ne = P.ctr->rs_n_ent;
+    for (int e = blockIdx.x * (WG / 64) + w; e < ne; e += gridDim.x * (WG / 64)) {
+        const unsigned v = entry_cell_count<DIM>(P, e, nb, lane);
+        const unsigned ex = wave_incl_scan(v) - v;
+        if (lane < NC) {
+            P.rs_off[(size_t)e * NC + lane] = P.rs_start[e] + ex;
+            P.rs_in[(size_t)e * NC + lane] = 0u;
+        }
+    }
+}
+
+// place: one wave per previous block, segment in the previous order.
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_rs_place(DevParams P, const uint32_t* __restrict__ keys_new,
+                                                 uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+                                                 int n) {
+    constexpr int CB = 2 * DIM, NC = 1 << CB;
+    __shared__ unsigned run[WG / 64][64];
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    const int nb = min(P.ctr->nb, P.block_cap);
+    const int ne = P.ctr->rs_n_ent;
+    bool bad = false;
+    for (int e = blockIdx.x * (WG / 64) + w; e < nb; e += gridDim.x * (WG / 64)) {
+        const int s = P.b_start[e], c = P.b_count[e];
+        if (c <= 0) continue;
+        const uint32_t owner = P.rs_oldblk[e];
+        run[w][lane] = lane < NC ? P.rs_off[(size_t)e * NC + lane] : 0u;
+        for (int i0 = s; i0 < s + c; i0 += 64) {
+            const int i = i0 + lane;
+            const bool valid = i < s + c;
+            const uint32_t k = valid ? keys_new[i] : 0u;
+            const bool stay = valid && (k >> CB) == owner;
+            const uint32_t cell = k & (NC - 1);
+            const unsigned long long m = match_bits<CB>(cell, stay);
+            long long pos = -1;
+            if (stay) {
+                const unsigned b0 = run[w][cell];
+                pos = (long long)b0 + __popcll(m & lt);
+                if ((m & lt) == 0ull) run[w][cell] = b0 + (unsigned)__popcll(m);
+            } else if (valid) {
+                const uint64_t K = owner_block_key<DIM>(P, k >> CB);
+                int e2 = hash_lookup(P, K);
+                unsigned b0 = 0u;
+                if (e2 >= 0) {
+                    b0 = P.rs_off[(size_t)e2 * NC + cell] + P.rs_stay[(size_t)e2 * NC + cell];
+                } else {
+                    const int slot = nh_lookup(P, K);
+                    e2 = slot >= 0 ? P.nh_idx[slot] : -1;
+                    if (e2 >= 0 && e2 < ne) b0 = P.rs_off[(size_t)e2 * NC + cell];
+                    else e2 = -1;
+                }
+                if (e2 >= 0) pos = (long long)b0 + atomicAdd(&P.rs_in[(size_t)e2 * NC + cell], 1u);
+            }
+            if (pos >= 0 && pos < n) {
+                keys_out[pos] = k;
+                vals_out[pos] = (uint32_t)i;
+            } else if (valid) {
+                bad = true;
+            }
+        }
+    }
+    if (bad) raise_flag(P.ctr, MPM_FLAG_OVERFLOW);
+}
+
+// reset: mover counters of every entry and the second table's keys.
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_rs_reset(DevParams P, unsigned H) {
+    constexpr int NC = 1 << (2 * DIM);
+    const long long rows = (long long)P.ctr->rs_n_ent * NC;
+    const long long all = rows > (long long)H ? rows : (long long)H;
+    for (long long t = (long long)blockIdx.x * WG + threadIdx.x; t < all; t += (long long)gridDim.x * WG) {
+        if (t < rows) P.rs_in[t] = 0u;
+        if (t < (long long)H) P.nh_keys[t] = EMPTY_KEY;
+    }
+}
+
+// Initial state of the buffers the re-sort expects between builds.
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_rs_init(DevParams P, unsigned H) {
+    constexpr int NC = 1 << (2 * DIM);
+    const long long rows = 2ll * P.block_cap * NC;
+    const long long hrows = (long long)H * NC;
+    const long long all = rows > hrows ? rows : hrows;
+    for (long long t = (long long)blockIdx.x * WG + threadIdx.x; t < all; t += (long long)gridDim.x * WG) {
+        if (t < rows) P.rs_in[t] = 0u;
+        if (t < hrows) P.nh_cnt[t] = 0u;
+        if (t < (long long)H) P.nh_keys[t] = EMPTY_KEY;
+    }
+}
+
+namespace {
+int grid_for_waves(long long waves) {
+    const long long g = (waves + WG / 64 - 1) / (WG / 64);
+    return (int)(g < 1 ? 1 : (g > 16384 ? 16384 : g));
+}
+}  // namespace
+
+hipError_t launch_resort_init(const DevParams& P, unsigned H, hipStream_t s) {
+    if (P.dim == 3)
+        k_rs_init<3><<<4096, WG, 0, s>>>(P, H);
+    else
+        k_rs_init<2><<<4096, WG, 0, s>>>(P, H);
+    return hipGetLastError();
+}
+
+hipError_t launch_resort(const DevParams& P, uint32_t* keys_prev, const uint32_t* keys_new, uint32_t* keys_out,
+                         uint32_t* vals_out, int n, unsigned H, unsigned* partials, hipStream_t s) {
+    const int gw = grid_for_waves(P.block_cap);
+    const int ge = grid_for_waves(2ll * P.block_cap);
+    const int htiles = (int)((H + SCAN_TILE - 1) / SCAN_TILE);
+    if (P.dim == 3)
+        k_rs_count<3><<<gw, WG, 0, s>>>(P, keys_prev, keys_new);
+    else
+        k_rs_count<2><<<gw, WG, 0, s>>>(P, keys_prev, keys_new);
+    k_rs_new_count<<<htiles, WG, 0, s>>>(P, (int)H, partials);
+    hipError_t e = scan_partials(partials, htiles, (unsigned*)&P.ctr->rs_n_new, s);
+    if (e != hipSuccess) return e;
+    if (P.dim == 3) {
+        k_rs_new_write<3><<<htiles, WG, 0, s>>>(P, (int)H, partials);
+        k_rs_entry_count<3><<<ge, WG, 0, s>>>(P);
+    } else {
+        k_rs_new_write<2><<<htiles, WG, 0, s>>>(P, (int)H, partials);
+        k_rs_entry_count<2><<<ge, WG, 0, s>>>(P);
+    }
+    e = scan_exclusive(P.rs_cnt, P.rs_start, 2 * P.block_cap, &P.ctr->rs_n_ent, partials, nullptr, s);
+    if (e != hipSuccess) return e;
+    if (P.dim == 3) {
+        k_rs_offsets<3><<<ge, WG, 0, s>>>(P);
+        k_rs_place<3><<<gw, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n);
+        k_rs_reset<3><<<4096, WG, 0, s>>>(P, H);
+    } else {
+        k_rs_offsets<2><<<ge, WG, 0, s>>>(P);
+        k_rs_place<2><<<gw, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n);
+        k_rs_reset<2><<<4096, WG, 0, s>>>(P, H);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mpmx

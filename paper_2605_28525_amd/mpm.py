@@ -23,6 +23,7 @@ MPM_MODEL = {"elastic": 0, "dp": 1}
 MPM_GRID_SPARSE, MPM_GRID_DENSE = 0, 1
 MPM_FLAG_SYNC_REBUILD = 1
 MPM_FLAG_ADJOINT = 2
+MPM_FLAG_FULL_SORT = 4
 
 
 class mpm_instance(ctypes.Structure):
