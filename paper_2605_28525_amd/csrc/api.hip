@@ -328,7 +328,8 @@ int build_once(mpm_ctx* c, const mpm_particles* p, hipStream_t s, bool reuse) {
         vo = c->order;
         e = launch_bin(c->P, p->x, p->inst, n, fresh, s);
         if (e != hipSuccess) return MPM_ERR_HIP;
-        e = launch_resort(c->P, prev, fresh, prev, vo, n, 1u << c->H_log2, c->partials, s);
+        uint32_t* spare = vo == c->v0 ? c->v1 : c->v0;  // the next osrc, free until P2G
+        e = launch_resort(c->P, prev, fresh, prev, vo, spare, n, 1u << c->H_log2, c->partials, s);
         if (e != hipSuccess) return MPM_ERR_HIP;
         ko = prev;
     } else {

@@ -41,7 +41,8 @@ struct DevCounters {
     unsigned flags;  // sticky MPM_FLAG_* bits
     int rs_n_new;    // incremental re-sort: blocks without a previous slot
     int rs_n_ent;    //   entries (previous blocks, then new blocks)
-    int pad[2];
+    int rs_n_mov;    //   particles that changed owner block (0 between builds)
+    int pad;
 };
 
 // Per-instance material and step constants (one entry for a single simulation).
@@ -311,7 +312,7 @@ int radix_hist_size(int n);
 
 hipError_t launch_bin(const DevParams& P, const float* x, const uint32_t* inst, int n, uint32_t* keys, hipStream_t s);
 hipError_t launch_resort(const DevParams& P, uint32_t* keys_prev, const uint32_t* keys_new, uint32_t* keys_out,
-                         uint32_t* vals_out, int n, unsigned H, unsigned* partials, hipStream_t s);
+                         uint32_t* vals_out, uint32_t* movers, int n, unsigned H, unsigned* partials, hipStream_t s);
 hipError_t launch_resort_init(const DevParams& P, unsigned H, hipStream_t s);
 hipError_t launch_build_sparse(const DevParams& P, const uint32_t* skeys, int n, unsigned H, unsigned* partials,
                                hipStream_t s);

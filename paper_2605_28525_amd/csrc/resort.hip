@@ -11,21 +11,27 @@
 // previous order and appends the blocks that had no slot before:
 //   count    one wave per previous block: the particles whose new key has the
 //            block's owner part ("stayers") are counted per base cell; every
-//            other particle ("mover") looks its new block up in the previous
-//            hash table and adds to that block's per-cell mover count, or, for
-//            a block without a previous slot, claims a slot of a second hash
-//            table and counts there;
+//            other particle ("mover") is appended to a mover list;
+//   route    one thread per mover: its new block is looked up in the previous
+//            hash table and the block's per-cell mover count incremented, or,
+//            for a block without a previous slot, a slot of a second hash
+//            table is claimed and counted;
 //   new      compaction of the second table: its blocks become the entries
 //            after the previous blocks;
 //   offsets  per entry, particles per base cell = stayers + movers; exclusive
 //            scans over the entries (first position) and over the cells;
 //   place    one wave per previous block: stayers keep their relative order
-//            (per-cell ranks from a wave-wide match), movers go after the
-//            stayers of their cell, in the order their atomic slot claims land;
+//            (per-cell ranks from a wave-wide match); then one thread per
+//            mover: movers go after the stayers of their cell, in the order
+//            their atomic slot claims land;
 //   reset    the per-entry mover counts and the second table are cleared for
 //            the next build.
 // Cost: two reads of the new keys and one write of keys and values, against
-// 2-4 full read/write passes of the radix sort.
+// 2-4 full read/write passes of the radix sort.  The per-block kernels only
+// stream keys; the dependent lookups of the few movers run one per thread, so
+// their latencies overlap instead of stalling a block's wave.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace mpmx {
@@ -85,10 +91,13 @@ __device__ int nh_lookup(const DevParams& P, uint64_t K) {
 
 }  // namespace
 
+constexpr int RS_BATCH = 8;  // 64-particle chunks of a segment whose keys are loaded together
+
 // count: one wave per previous block e (its segment of the previous order).
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_rs_count(DevParams P, const uint32_t* __restrict__ keys_prev,
-                                                 const uint32_t* __restrict__ keys_new) {
+                                                 const uint32_t* __restrict__ keys_new,
+                                                 uint32_t* __restrict__ movers, int n) {
     constexpr int CB = 2 * DIM, NC = 1 << CB;
     __shared__ unsigned cnt[WG / 64][64];
     const int lane = __lane_id(), w = threadIdx.x >> 6;
@@ -100,31 +109,59 @@ __global__ __launch_bounds__(WG) void k_rs_count(DevParams P, const uint32_t* __
         uint32_t owner = ~0u;
         if (c > 0) {
             owner = keys_prev[s] >> CB;
-            for (int i0 = s; i0 < s + c; i0 += 64) {
-                const int i = i0 + lane;
-                const bool valid = i < s + c;
-                const uint32_t k = valid ? keys_new[i] : 0u;
-                const bool stay = valid && (k >> CB) == owner;
-                const uint32_t cell = k & (NC - 1);
-                const unsigned long long m = match_bits<CB>(cell, stay);
-                if (stay && (m & lt) == 0ull) cnt[w][cell] += (unsigned)__popcll(m);  // one leader per cell
-                if (valid && !stay) {
-                    const uint64_t K = owner_block_key<DIM>(P, k >> CB);
-                    const int phi = hash_lookup(P, K);
-                    if (phi >= 0) {
-                        atomicAdd(&P.rs_in[(size_t)phi * NC + cell], 1u);
-                    } else {
-                        const int slot = nh_insert(P, K);
-                        if (slot >= 0)
-                            atomicAdd(&P.nh_cnt[(size_t)slot * NC + cell], 1u);
-                        else
-                            raise_flag(P.ctr, MPM_FLAG_OVERFLOW);
+            const int end = s + c;
+            for (int i0 = s; i0 < end; i0 += 64 * RS_BATCH) {
+                uint32_t k[RS_BATCH];
+#pragma unroll
+                for (int r = 0; r < RS_BATCH; ++r) {
+                    const int i = i0 + r * 64 + lane;
+                    k[r] = i < end ? keys_new[i] : 0u;
+                }
+#pragma unroll
+                for (int r = 0; r < RS_BATCH; ++r) {
+                    if (i0 + r * 64 >= end) break;  // uniform
+                    const int i = i0 + r * 64 + lane;
+                    const bool valid = i < end;
+                    const bool stay = valid && (k[r] >> CB) == owner;
+                    const uint32_t cell = k[r] & (NC - 1);
+                    const unsigned long long m = match_bits<CB>(cell, stay);
+                    if (stay && (m & lt) == 0ull) cnt[w][cell] += (unsigned)__popcll(m);  // one leader per cell
+                    const unsigned long long mv = __ballot(valid && !stay);
+                    if (mv) {  // uniform
+                        unsigned base = 0u;
+                        if (lane == 0) base = (unsigned)atomicAdd(&P.ctr->rs_n_mov, (int)__popcll(mv));
+                        base = (unsigned)__shfl((int)base, 0);
+                        const unsigned slot = base + (unsigned)__popcll(mv & lt);
+                        if (valid && !stay && slot < (unsigned)n) movers[slot] = (uint32_t)i;
                     }
                 }
             }
         }
         if (lane < NC) P.rs_stay[(size_t)e * NC + lane] = cnt[w][lane];
         if (lane == 0) P.rs_oldblk[e] = owner;
+    }
+}
+
+// route: one thread per mover.
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_rs_route(DevParams P, const uint32_t* __restrict__ keys_new,
+                                                 const uint32_t* __restrict__ movers, int n) {
+    constexpr int CB = 2 * DIM, NC = 1 << CB;
+    const int m = min(P.ctr->rs_n_mov, n);
+    for (int t = blockIdx.x * WG + threadIdx.x; t < m; t += gridDim.x * WG) {
+        const uint32_t k = keys_new[movers[t]];
+        const uint32_t cell = k & (NC - 1);
+        const uint64_t K = owner_block_key<DIM>(P, k >> CB);
+        const int phi = hash_lookup(P, K);
+        if (phi >= 0) {
+            atomicAdd(&P.rs_in[(size_t)phi * NC + cell], 1u);
+        } else {
+            const int slot = nh_insert(P, K);
+            if (slot >= 0)
+                atomicAdd(&P.nh_cnt[(size_t)slot * NC + cell], 1u);
+            else
+                raise_flag(P.ctr, MPM_FLAG_OVERFLOW);
+        }
     }
 }
 
@@ -223,7 +260,7 @@ __global__ __launch_bounds__(WG) void k_rs_offsets(DevParams P) {
     }
 }
 
-// place: one wave per previous block, segment in the previous order.
+// place, stayers: one wave per previous block, segment in the previous order.
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_rs_place(DevParams P, const uint32_t* __restrict__ keys_new,
                                                  uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
@@ -233,45 +270,81 @@ __global__ __launch_bounds__(WG) void k_rs_place(DevParams P, const uint32_t* __
     const int lane = __lane_id(), w = threadIdx.x >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
     const int nb = min(P.ctr->nb, P.block_cap);
-    const int ne = P.ctr->rs_n_ent;
     bool bad = false;
     for (int e = blockIdx.x * (WG / 64) + w; e < nb; e += gridDim.x * (WG / 64)) {
         const int s = P.b_start[e], c = P.b_count[e];
         if (c <= 0) continue;
         const uint32_t owner = P.rs_oldblk[e];
         run[w][lane] = lane < NC ? P.rs_off[(size_t)e * NC + lane] : 0u;
-        for (int i0 = s; i0 < s + c; i0 += 64) {
-            const int i = i0 + lane;
-            const bool valid = i < s + c;
-            const uint32_t k = valid ? keys_new[i] : 0u;
-            const bool stay = valid && (k >> CB) == owner;
-            const uint32_t cell = k & (NC - 1);
-            const unsigned long long m = match_bits<CB>(cell, stay);
-            long long pos = -1;
-            if (stay) {
-                const unsigned b0 = run[w][cell];
-                pos = (long long)b0 + __popcll(m & lt);
-                if ((m & lt) == 0ull) run[w][cell] = b0 + (unsigned)__popcll(m);
-            } else if (valid) {
-                const uint64_t K = owner_block_key<DIM>(P, k >> CB);
-                int e2 = hash_lookup(P, K);
-                unsigned b0 = 0u;
-                if (e2 >= 0) {
-                    b0 = P.rs_off[(size_t)e2 * NC + cell] + P.rs_stay[(size_t)e2 * NC + cell];
-                } else {
-                    const int slot = nh_lookup(P, K);
-                    e2 = slot >= 0 ? P.nh_idx[slot] : -1;
-                    if (e2 >= 0 && e2 < ne) b0 = P.rs_off[(size_t)e2 * NC + cell];
-                    else e2 = -1;
+        const int end = s + c;
+        for (int i0 = s; i0 < end; i0 += 64 * RS_BATCH) {
+            uint32_t k[RS_BATCH];
+#pragma unroll
+            for (int r = 0; r < RS_BATCH; ++r) {
+                const int i = i0 + r * 64 + lane;
+                k[r] = i < end ? keys_new[i] : 0u;
+            }
+#pragma unroll
+            for (int r = 0; r < RS_BATCH; ++r) {
+                if (i0 + r * 64 >= end) break;  // uniform
+                const int i = i0 + r * 64 + lane;
+                const bool stay = i < end && (k[r] >> CB) == owner;
+                const uint32_t cell = k[r] & (NC - 1);
+                const unsigned long long m = match_bits<CB>(cell, stay);
+                if (stay) {
+                    const unsigned b0 = run[w][cell];
+                    const unsigned pos = b0 + (unsigned)__popcll(m & lt);
+                    if ((m & lt) == 0ull) run[w][cell] = b0 + (unsigned)__popcll(m);
+                    if (pos < (unsigned)n) {
+                        keys_out[pos] = k[r];
+                        vals_out[pos] = (uint32_t)i;
+                    } else {
+                        bad = true;
+                    }
                 }
-                if (e2 >= 0) pos = (long long)b0 + atomicAdd(&P.rs_in[(size_t)e2 * NC + cell], 1u);
             }
-            if (pos >= 0 && pos < n) {
-                keys_out[pos] = k;
-                vals_out[pos] = (uint32_t)i;
-            } else if (valid) {
-                bad = true;
-            }
+        }
+    }
+    if (bad) raise_flag(P.ctr, MPM_FLAG_OVERFLOW);
+}
+
+// place, movers: one thread per mover, after the stayers of its cell.
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_rs_place_movers(DevParams P, const uint32_t* __restrict__ keys_new,
+                                                        const uint32_t* __restrict__ movers,
+                                                        uint32_t* __restrict__ keys_out,
+                                                        uint32_t* __restrict__ vals_out, int n) {
+    constexpr int CB = 2 * DIM, NC = 1 << CB;
+    const int m = min(P.ctr->rs_n_mov, n);
+    const int ne = P.ctr->rs_n_ent;
+    bool bad = false;
+    for (int t = blockIdx.x * WG + threadIdx.x; t < m; t += gridDim.x * WG) {
+        const uint32_t i = movers[t];
+        const uint32_t k = keys_new[i];
+        const uint32_t cell = k & (NC - 1);
+        const uint64_t K = owner_block_key<DIM>(P, k >> CB);
+        int e2 = hash_lookup(P, K);
+        unsigned b0 = 0u;
+        if (e2 >= 0) {
+            b0 = P.rs_off[(size_t)e2 * NC + cell] + P.rs_stay[(size_t)e2 * NC + cell];
+        } else {
+            const int slot = nh_lookup(P, K);
+            e2 = slot >= 0 ? P.nh_idx[slot] : -1;
+            if (e2 >= 0 && e2 < ne)
+                b0 = P.rs_off[(size_t)e2 * NC + cell];
+            else
+                e2 = -1;
+        }
+        if (e2 < 0) {
+            bad = true;
+            continue;
+        }
+        const unsigned pos = b0 + atomicAdd(&P.rs_in[(size_t)e2 * NC + cell], 1u);
+        if (pos < (unsigned)n) {
+            keys_out[pos] = k;
+            vals_out[pos] = i;
+        } else {
+            bad = true;
         }
     }
     if (bad) raise_flag(P.ctr, MPM_FLAG_OVERFLOW);
@@ -287,6 +360,7 @@ __global__ __launch_bounds__(WG) void k_rs_reset(DevParams P, unsigned H) {
         if (t < rows) P.rs_in[t] = 0u;
         if (t < (long long)H) P.nh_keys[t] = EMPTY_KEY;
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) P.ctr->rs_n_mov = 0;
 }
 
 // Initial state of the buffers the re-sort expects between builds.
@@ -319,14 +393,18 @@ hipError_t launch_resort_init(const DevParams& P, unsigned H, hipStream_t s) {
 }
 
 hipError_t launch_resort(const DevParams& P, uint32_t* keys_prev, const uint32_t* keys_new, uint32_t* keys_out,
-                         uint32_t* vals_out, int n, unsigned H, unsigned* partials, hipStream_t s) {
+                         uint32_t* vals_out, uint32_t* movers, int n, unsigned H, unsigned* partials, hipStream_t s) {
     const int gw = grid_for_waves(P.block_cap);
     const int ge = grid_for_waves(2ll * P.block_cap);
+    const int gm = (int)std::min<long long>(((long long)n + WG - 1) / WG, 2048);  // grid-stride over the movers
     const int htiles = (int)((H + SCAN_TILE - 1) / SCAN_TILE);
-    if (P.dim == 3)
-        k_rs_count<3><<<gw, WG, 0, s>>>(P, keys_prev, keys_new);
-    else
-        k_rs_count<2><<<gw, WG, 0, s>>>(P, keys_prev, keys_new);
+    if (P.dim == 3) {
+        k_rs_count<3><<<gw, WG, 0, s>>>(P, keys_prev, keys_new, movers, n);
+        k_rs_route<3><<<gm, WG, 0, s>>>(P, keys_new, movers, n);
+    } else {
+        k_rs_count<2><<<gw, WG, 0, s>>>(P, keys_prev, keys_new, movers, n);
+        k_rs_route<2><<<gm, WG, 0, s>>>(P, keys_new, movers, n);
+    }
     k_rs_new_count<<<htiles, WG, 0, s>>>(P, (int)H, partials);
     hipError_t e = scan_partials(partials, htiles, (unsigned*)&P.ctr->rs_n_new, s);
     if (e != hipSuccess) return e;
@@ -342,10 +420,12 @@ hipError_t launch_resort(const DevParams& P, uint32_t* keys_prev, const uint32_t
     if (P.dim == 3) {
         k_rs_offsets<3><<<ge, WG, 0, s>>>(P);
         k_rs_place<3><<<gw, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n);
+        k_rs_place_movers<3><<<gm, WG, 0, s>>>(P, keys_new, movers, keys_out, vals_out, n);
         k_rs_reset<3><<<4096, WG, 0, s>>>(P, H);
     } else {
         k_rs_offsets<2><<<ge, WG, 0, s>>>(P);
         k_rs_place<2><<<gw, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n);
+        k_rs_place_movers<2><<<gm, WG, 0, s>>>(P, keys_new, movers, keys_out, vals_out, n);
         k_rs_reset<2><<<4096, WG, 0, s>>>(P, H);
     }
     return hipGetLastError();
