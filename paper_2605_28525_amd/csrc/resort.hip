@@ -10,8 +10,10 @@
 // inside the block.  The new layout keeps the previous blocks in their
 // previous order and appends the blocks that had no slot before:
 //   count    one wave per previous block: the particles whose new key has the
-//            block's owner part ("stayers") are counted per base cell; every
-//            other particle ("mover") is appended to a mover list;
+//            block's owner part ("stayers") are counted per base cell, the
+//            others ("movers") per block;
+//   list     the movers of each block are written, in segment order, at the
+//            block's exclusive prefix of the mover counts;
 //   route    one thread per mover: its new block is looked up in the previous
 //            hash table and the block's per-cell mover count incremented, or,
 //            for a block without a previous slot, a slot of a second hash
@@ -93,11 +95,12 @@ __device__ int nh_lookup(const DevParams& P, uint64_t K) {
 
 constexpr int RS_BATCH = 8;  // 64-particle chunks of a segment whose keys are loaded together
 
-// count: one wave per previous block e (its segment of the previous order).
+// count: one wave per previous block e (its segment of the previous order);
+// the block's mover count goes to rs_cnt[e] (rs_cnt and rs_start serve the
+// mover list first, the entry scan later).
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_rs_count(DevParams P, const uint32_t* __restrict__ keys_prev,
-                                                 const uint32_t* __restrict__ keys_new,
-                                                 uint32_t* __restrict__ movers, int n) {
+                                                 const uint32_t* __restrict__ keys_new) {
     constexpr int CB = 2 * DIM, NC = 1 << CB;
     __shared__ unsigned cnt[WG / 64][64];
     const int lane = __lane_id(), w = threadIdx.x >> 6;
@@ -107,6 +110,7 @@ __global__ __launch_bounds__(WG) void k_rs_count(DevParams P, const uint32_t* __
         const int s = P.b_start[e], c = P.b_count[e];
         cnt[w][lane] = 0u;
         uint32_t owner = ~0u;
+        unsigned n_mov = 0u;
         if (c > 0) {
             owner = keys_prev[s] >> CB;
             const int end = s + c;
@@ -126,19 +130,50 @@ __global__ __launch_bounds__(WG) void k_rs_count(DevParams P, const uint32_t* __
                     const uint32_t cell = k[r] & (NC - 1);
                     const unsigned long long m = match_bits<CB>(cell, stay);
                     if (stay && (m & lt) == 0ull) cnt[w][cell] += (unsigned)__popcll(m);  // one leader per cell
-                    const unsigned long long mv = __ballot(valid && !stay);
-                    if (mv) {  // uniform
-                        unsigned base = 0u;
-                        if (lane == 0) base = (unsigned)atomicAdd(&P.ctr->rs_n_mov, (int)__popcll(mv));
-                        base = (unsigned)__shfl((int)base, 0);
-                        const unsigned slot = base + (unsigned)__popcll(mv & lt);
-                        if (valid && !stay && slot < (unsigned)n) movers[slot] = (uint32_t)i;
-                    }
+                    n_mov += (unsigned)__popcll(__ballot(valid && !stay));
                 }
             }
         }
         if (lane < NC) P.rs_stay[(size_t)e * NC + lane] = cnt[w][lane];
-        if (lane == 0) P.rs_oldblk[e] = owner;
+        if (lane == 0) {
+            P.rs_oldblk[e] = owner;
+            P.rs_cnt[e] = n_mov;
+        }
+    }
+}
+
+// list: one wave per previous block with movers; rs_start[e] is its offset in
+// the mover list (exclusive scan of the counts, total in rs_n_mov).
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_rs_list(DevParams P, const uint32_t* __restrict__ keys_new,
+                                                uint32_t* __restrict__ movers, int n) {
+    constexpr int CB = 2 * DIM;
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    const int nb = min(P.ctr->nb, P.block_cap);
+    for (int e = blockIdx.x * (WG / 64) + w; e < nb; e += gridDim.x * (WG / 64)) {
+        if (P.rs_cnt[e] == 0u) continue;
+        const int s = P.b_start[e], end = s + P.b_count[e];
+        const uint32_t owner = P.rs_oldblk[e];
+        unsigned slot0 = P.rs_start[e];
+        for (int i0 = s; i0 < end; i0 += 64 * RS_BATCH) {
+            uint32_t k[RS_BATCH];
+#pragma unroll
+            for (int r = 0; r < RS_BATCH; ++r) {
+                const int i = i0 + r * 64 + lane;
+                k[r] = i < end ? keys_new[i] : 0u;
+            }
+#pragma unroll
+            for (int r = 0; r < RS_BATCH; ++r) {
+                if (i0 + r * 64 >= end) break;  // uniform
+                const int i = i0 + r * 64 + lane;
+                const bool mover = i < end && (k[r] >> CB) != owner;
+                const unsigned long long mv = __ballot(mover);
+                const unsigned slot = slot0 + (unsigned)__popcll(mv & lt);
+                if (mover && slot < (unsigned)n) movers[slot] = (uint32_t)i;
+                slot0 += (unsigned)__popcll(mv);
+            }
+        }
     }
 }
 
@@ -398,15 +433,22 @@ hipError_t launch_resort(const DevParams& P, uint32_t* keys_prev, const uint32_t
     const int ge = grid_for_waves(2ll * P.block_cap);
     const int gm = (int)std::min<long long>(((long long)n + WG - 1) / WG, 2048);  // grid-stride over the movers
     const int htiles = (int)((H + SCAN_TILE - 1) / SCAN_TILE);
+    if (P.dim == 3)
+        k_rs_count<3><<<gw, WG, 0, s>>>(P, keys_prev, keys_new);
+    else
+        k_rs_count<2><<<gw, WG, 0, s>>>(P, keys_prev, keys_new);
+    hipError_t e = scan_exclusive(P.rs_cnt, P.rs_start, P.block_cap, &P.ctr->nb, partials,
+                                  (unsigned*)&P.ctr->rs_n_mov, s);
+    if (e != hipSuccess) return e;
     if (P.dim == 3) {
-        k_rs_count<3><<<gw, WG, 0, s>>>(P, keys_prev, keys_new, movers, n);
+        k_rs_list<3><<<gw, WG, 0, s>>>(P, keys_new, movers, n);
         k_rs_route<3><<<gm, WG, 0, s>>>(P, keys_new, movers, n);
     } else {
-        k_rs_count<2><<<gw, WG, 0, s>>>(P, keys_prev, keys_new, movers, n);
+        k_rs_list<2><<<gw, WG, 0, s>>>(P, keys_new, movers, n);
         k_rs_route<2><<<gm, WG, 0, s>>>(P, keys_new, movers, n);
     }
     k_rs_new_count<<<htiles, WG, 0, s>>>(P, (int)H, partials);
-    hipError_t e = scan_partials(partials, htiles, (unsigned*)&P.ctr->rs_n_new, s);
+    e = scan_partials(partials, htiles, (unsigned*)&P.ctr->rs_n_new, s);
     if (e != hipSuccess) return e;
     if (P.dim == 3) {
         k_rs_new_write<3><<<htiles, WG, 0, s>>>(P, (int)H, partials);
