@@ -134,23 +134,71 @@ struct Interleave {
     int st;                              // first sorted position of the block
 };
 
+constexpr int IL_BATCH = 8;  // 64-key chunks of a segment whose loads are issued together
+
+// Lanes whose value v (its low BITS bits) equals this lane's, among lanes with
+// `valid` set.  Every lane of the wave must call it.
+template <int BITS>
+__device__ __forceinline__ unsigned long long lanes_matching(unsigned v, bool valid) {
+    unsigned long long m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+        const bool bit = (v >> b) & 1u;
+        const unsigned long long bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
 // Workgroup-cooperative set-up for the owner segment [st, en) (every thread
-// calls it; blockDim.x >= 64; ends with a barrier).
+// calls it; blockDim.x is a multiple of 64; ends with a barrier).  The keys of
+// the segment are sorted by base cell, so a cell's range starts after the
+// particles of all lower cells: the cells are counted (keys loaded in batches,
+// one wave-wide match per 64 keys, one LDS add per distinct cell) and the
+// ranges follow from an exclusive scan of the counts.  Optionally the first
+// `stage_max` entries of another per-particle array (`stage_src[st ..]`) are
+// copied to LDS (`stage_dst`) by the same batched loads.
 template <int DIM>
-__device__ void interleave_setup(Interleave<DIM>& L, const uint32_t* __restrict__ skeys, int st, int en) {
+__device__ void interleave_setup(Interleave<DIM>& L, const uint32_t* __restrict__ skeys, int st, int en,
+                                 const uint32_t* __restrict__ stage_src = nullptr, uint32_t* stage_dst = nullptr,
+                                 int stage_max = 0) {
     constexpr int NC = Interleave<DIM>::NC;
-    for (int c = threadIdx.x; c < NC; c += blockDim.x) L.cs[c] = L.ce[c] = 0;
+    for (int c = threadIdx.x; c < NC; c += blockDim.x) L.ce[c] = 0;  // per-cell counts first
     if (threadIdx.x == 0) L.st = st;
     __syncthreads();
-    for (int i = st + (int)threadIdx.x; i < en; i += blockDim.x) {
-        const uint32_t c = skeys[i] & (NC - 1);
-        if (i == st || (skeys[i - 1] & (NC - 1)) != c) L.cs[c] = i;
-        if (i == en - 1 || (skeys[i + 1] & (NC - 1)) != c) L.ce[c] = i + 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    const int stage_end = stage_dst ? min(en, st + stage_max) : st;
+    for (int i0 = st + wave * 64 * IL_BATCH; i0 < en; i0 += n_waves * 64 * IL_BATCH) {
+        uint32_t k[IL_BATCH], v[IL_BATCH];
+#pragma unroll
+        for (int r = 0; r < IL_BATCH; ++r) {
+            const int i = i0 + r * 64 + lane;
+            k[r] = i < en ? skeys[i] : 0u;
+            v[r] = i < stage_end ? stage_src[i] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < IL_BATCH; ++r) {
+            const int i = i0 + r * 64 + lane;
+            if (i < stage_end) stage_dst[i - st] = v[r];
+        }
+#pragma unroll
+        for (int r = 0; r < IL_BATCH; ++r) {
+            if (i0 + r * 64 >= en) break;  // uniform
+            const bool valid = i0 + r * 64 + lane < en;
+            const uint32_t c = k[r] & (NC - 1);
+            const unsigned long long m = lanes_matching<2 * DIM>(c, valid);
+            if (valid && (m & lt) == 0ull) atomicAdd(&L.ce[c], __popcll(m));
+        }
     }
     __syncthreads();
     if (threadIdx.x < 64) {
-        const int lane = threadIdx.x;
-        const int cnt = lane < NC ? L.ce[lane] - L.cs[lane] : 0;
+        const int cnt = lane < NC ? L.ce[lane] : 0;
+        const int first = st + (int)wave_incl_scan((unsigned)cnt) - cnt;
+        if (lane < NC) {
+            L.cs[lane] = first;
+            L.ce[lane] = first + cnt;
+        }
         const int ovf = max(cnt - IL_ROUNDS, 0);
         const int inc = (int)wave_incl_scan((unsigned)ovf);
         if (lane < NC) L.op[lane] = inc - ovf;

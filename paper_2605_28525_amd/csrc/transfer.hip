@@ -51,23 +51,45 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
     const int lane = threadIdx.x;
     const int nb = min(P.ctr->nb, P.block_cap);
     const float dx = P.dxf, inv_dx = P.inv_dxf;
+    // The count, first sorted position and key of the next block are loaded
+    // while the current one is processed (a dense grid has no key table: its
+    // key is the linear block index).
+    int cnt_n = 0, st_n = 0;
+    uint64_t key_n = 0;
+    auto fetch_meta = [&](int bb) {
+        if (bb < nb) {
+            // the same in every lane; hidden so that the values stay in vector
+            // registers and nothing waits for them before they are used
+            asm volatile("" : "+v"(bb));
+            cnt_n = P.b_count[bb];
+            st_n = P.b_start[bb];
+            key_n = P.dense ? (uint64_t)bb : P.b_keys[bb];
+        }
+    };
+    fetch_meta(blockIdx.x);
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
-        const int cnt = P.b_count[b];
+        const int cnt = cnt_n, st = st_n;
+        const uint64_t key = key_n;
+        fetch_meta(b + gridDim.x);
         if (cnt <= 0) continue;
-        const int st = P.b_start[b], en = st + cnt;
+        const int en = st + cnt;
+        const int nbv = lane < T::NB ? P.b_nbr[(size_t)b * T::NB + lane] : -1;
         for (int t = lane; t < 4 * T::NP; t += 64) (&tile[0][0])[t] = 0.f;
-        int bc[3], inst;
-        block_coords<DIM>(P, b, bc, &inst);
+        int bc[3], inst = 0;
+        if (P.dense)
+            linear_to_block<DIM>(P, (uint32_t)key, bc);
+        else
+            unblock_key<DIM>(P, key, bc, &inst);
         const InstMat mat = material(P, inst);
         const float mp = mat.p_mass;
         const float dtv = mat.dt * mat.p_vol0;
         const int org[3] = {bc[0] * BLK, bc[1] * BLK, bc[2] * BLK};
-        for (int i = st + lane; i < min(en, st + P2G_ORDER_STAGE); i += 64) ord[i - st] = order[i];
-        if (lane < T::NB) nbr[lane] = P.b_nbr[(size_t)b * T::NB + lane];
         // cell ranges of the block and its G2P output layout (rank-major over
-        // the base cells); each lane records where G2P will store its cell's
+        // the base cells), with the block's permutation staged in LDS by the
+        // same loads; each lane records where G2P will store its cell's
         // particles as it visits them (osrc)
-        interleave_setup<DIM>(il, skeys, st, en);
+        interleave_setup<DIM>(il, skeys, st, en, order, ord, P2G_ORDER_STAGE);
+        if (lane < T::NB) nbr[lane] = nbv;
         float acc[NK][4];
 #pragma unroll
         for (int k = 0; k < NK; ++k) acc[k][0] = acc[k][1] = acc[k][2] = acc[k][3] = 0.f;
