@@ -67,6 +67,7 @@ struct mpm_ctx {
     uint64_t* nh_keys = nullptr;
     uint32_t* nh_cnt = nullptr;
     int* nh_idx = nullptr;
+    uint32_t* nh_owner = nullptr;
     uint32_t* order = nullptr;
     uint32_t* skeys = nullptr;
     uint32_t* osrc = nullptr;  // G2P output position -> input index (the spare sort value buffer)
@@ -122,6 +123,7 @@ void free_capacity_buffers(mpm_ctx* c) {
     dfree(c->nh_keys);
     dfree(c->nh_cnt);
     dfree(c->nh_idx);
+    dfree(c->nh_owner);
     c->seg_valid = false;
 }
 
@@ -239,6 +241,7 @@ void fill_params(mpm_ctx* c) {
     P.nh_keys = c->nh_keys;
     P.nh_cnt = c->nh_cnt;
     P.nh_idx = c->nh_idx;
+    P.nh_owner = c->nh_owner;
     fill_material(c);
 }
 
@@ -280,12 +283,13 @@ int alloc_capacity_buffers(mpm_ctx* c) {
         e = e ? e : dalloc(&c->rs_stay, cap * NPB);
         e = e ? e : dalloc(&c->rs_in, 2 * cap * NPB);
         e = e ? e : dalloc(&c->rs_off, 2 * cap * NPB);
-        e = e ? e : dalloc(&c->rs_oldblk, cap);
+        e = e ? e : dalloc(&c->rs_oldblk, 2 * cap);
         e = e ? e : dalloc(&c->rs_cnt, 2 * cap);
         e = e ? e : dalloc(&c->rs_start, 2 * cap);
         e = e ? e : dalloc(&c->nh_keys, H);
         e = e ? e : dalloc(&c->nh_cnt, H * NPB);
         e = e ? e : dalloc(&c->nh_idx, H);
+        e = e ? e : dalloc(&c->nh_owner, H);
     }
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -346,7 +350,7 @@ int build_once(mpm_ctx* c, const mpm_particles* p, hipStream_t s, bool reuse) {
     if (c->dense)
         e = launch_build_dense(c->P, ko, n, (int)c->n_blocks_total, c->partials, s);
     else
-        e = launch_build_sparse(c->P, ko, n, 1u << c->H_log2, c->partials, s);
+        e = launch_build_sparse(c->P, ko, n, 1u << c->H_log2, c->partials, s, reuse && n > 0);
     return hip_status(e);
 }
 

@@ -235,6 +235,46 @@ __global__ __launch_bounds__(WG) void k_hash_insert(DevParams P, const uint32_t*
     if (have) flush();
 }
 
+// Insertion after an incremental re-sort: one wave per entry (a previous block
+// or a new one) of the re-sort, whose per-cell first positions and particle
+// count are known, so the base-cell occupancy of the owner block is a ballot
+// over its cells; node masks, inserts and owner segment as in k_hash_insert.
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_hash_insert_entries(DevParams P) {
+    constexpr int NB = 1 << DIM;
+    constexpr int NC = 1 << (2 * DIM);
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
+    const int ne = P.ctr->rs_n_ent;
+    for (int e = blockIdx.x * (WG / 64) + w; e < ne; e += gridDim.x * (WG / 64)) {
+        const unsigned tot = P.rs_cnt[e];
+        if (tot == 0u) continue;
+        const unsigned first = P.rs_start[e], end = first + tot;
+        const unsigned off = lane < NC ? P.rs_off[(size_t)e * NC + lane] : end;
+        const unsigned next = __shfl_down(off, 1);
+        const bool occupied = lane < NC && (lane == NC - 1 ? end : next) > off;
+        const uint64_t occ = (uint64_t)__ballot(occupied);
+        const uint32_t owner = P.rs_oldblk[e];
+        const uint32_t bl = owner & ((1u << P.blk_bits) - 1u);
+        const int inst = (int)(owner >> P.blk_bits);
+        int bc[3];
+        linear_to_block<DIM>(P, bl, bc);
+        int slot = -1;
+        if (lane < NB) {
+            const uint64_t mymask = neighbour_mask<DIM>(occ, lane);
+            if (mymask != 0ull) {
+                const uint64_t Kd =
+                    block_key<DIM>(P, bc[0] + (lane & 1), bc[1] + ((lane >> 1) & 1), bc[2] + ((lane >> 2) & 1), inst);
+                slot = hash_insert(P, Kd);
+                if (slot >= 0) atomicOr((unsigned long long*)&P.h_mask[slot], (unsigned long long)mymask);
+            }
+        }
+        if (lane == 0 && slot >= 0) {  // lane 0 holds the owner block
+            P.h_start[slot] = (int)first;
+            P.h_end[slot] = (int)end;
+        }
+    }
+}
+
 __global__ __launch_bounds__(WG) void k_compact_count(DevParams P, int H, unsigned* __restrict__ partials) {
     __shared__ unsigned lds[WG / 64];
     const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
@@ -398,9 +438,15 @@ hipError_t launch_bin(const DevParams& P, const float* x, const uint32_t* inst, 
 }
 
 hipError_t launch_build_sparse(const DevParams& P, const uint32_t* skeys, int n, unsigned H, unsigned* partials,
-                               hipStream_t s) {
+                               hipStream_t s, bool from_resort) {
     k_hash_clear<<<grid_for(H), WG, 0, s>>>(P, H);
-    if (n > 0) {
+    if (n > 0 && from_resort) {
+        const int ge = grid_for(2ll * P.block_cap * 64, 16384);  // one wave per entry
+        if (P.dim == 3)
+            k_hash_insert_entries<3><<<ge, WG, 0, s>>>(P);
+        else
+            k_hash_insert_entries<2><<<ge, WG, 0, s>>>(P);
+    } else if (n > 0) {
         const int per_wg = WG * HI_ROUNDS;
         if (P.dim == 3)
             k_hash_insert<3><<<(n + per_wg - 1) / per_wg, WG, 0, s>>>(P, skeys, n);

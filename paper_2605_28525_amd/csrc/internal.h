@@ -113,10 +113,11 @@ struct DevParams {
     uint32_t* rs_off;     // first sorted position per entry and cell
     unsigned* rs_cnt;     // particles per entry
     unsigned* rs_start;   // first sorted position per entry
-    uint32_t* rs_oldblk;  // owner-block part of the sort key of each previous block
+    uint32_t* rs_oldblk;  // owner-block part of the sort key of each entry (~0: empty previous block)
     uint64_t* nh_keys;    // second hash table (same size as the block table): blocks
     uint32_t* nh_cnt;     //   with no previous slot, their movers per cell,
-    int* nh_idx;          //   and their entry index
+    int* nh_idx;          //   their entry index
+    uint32_t* nh_owner;   //   and the owner-block part of their sort key
     // ensembles
     int n_inst;          // 1 = single simulation
     int blk_bits;        // bits of the linear block id inside the sort key
@@ -315,7 +316,7 @@ hipError_t launch_resort(const DevParams& P, uint32_t* keys_prev, const uint32_t
                          uint32_t* vals_out, uint32_t* movers, int n, unsigned H, unsigned* partials, hipStream_t s);
 hipError_t launch_resort_init(const DevParams& P, unsigned H, hipStream_t s);
 hipError_t launch_build_sparse(const DevParams& P, const uint32_t* skeys, int n, unsigned H, unsigned* partials,
-                               hipStream_t s);
+                               hipStream_t s, bool from_resort = false);
 hipError_t launch_build_dense(const DevParams& P, const uint32_t* skeys, int n, int n_blocks, unsigned* partials,
                               hipStream_t s);
 hipError_t launch_p2g(const DevParams& P, const float* x, const float* v, const float* C, const float* tau, int n,

@@ -111,7 +111,21 @@ __global__ __launch_bounds__(WG) void k_rs_count(DevParams P, const uint32_t* __
         cnt[w][lane] = 0u;
         uint32_t owner = ~0u;
         unsigned n_mov = 0u;
-        if (c > 0) {
+        if (c <= 0) {
+            // a block that only held stencil nodes may still receive movers: its
+            // owner part from the block key (none if outside the binning range)
+            int bc[3], inst = 0;
+            unblock_key<DIM>(P, P.b_keys[e], bc, &inst);
+            bool in_range = true;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) in_range = in_range && bc[a] >= 0 && bc[a] < P.nblk[a];
+            if (in_range) {
+                const uint32_t bl = DIM == 3 ? ((uint32_t)bc[2] * (uint32_t)P.nblk[1] + (uint32_t)bc[1]) *
+                                                       (uint32_t)P.nblk[0] + (uint32_t)bc[0]
+                                             : (uint32_t)bc[1] * (uint32_t)P.nblk[0] + (uint32_t)bc[0];
+                owner = ((uint32_t)inst << P.blk_bits) | bl;
+            }
+        } else {
             owner = keys_prev[s] >> CB;
             const int end = s + c;
             for (int i0 = s; i0 < end; i0 += 64 * RS_BATCH) {
@@ -192,10 +206,12 @@ __global__ __launch_bounds__(WG) void k_rs_route(DevParams P, const uint32_t* __
             atomicAdd(&P.rs_in[(size_t)phi * NC + cell], 1u);
         } else {
             const int slot = nh_insert(P, K);
-            if (slot >= 0)
+            if (slot >= 0) {
                 atomicAdd(&P.nh_cnt[(size_t)slot * NC + cell], 1u);
-            else
+                P.nh_owner[slot] = k >> CB;  // the same value from every mover of the block
+            } else {
                 raise_flag(P.ctr, MPM_FLAG_OVERFLOW);
+            }
         }
     }
 }
@@ -243,6 +259,7 @@ __global__ __launch_bounds__(WG) void k_rs_new_write(DevParams P, int H, const u
         uint32_t* src = &P.nh_cnt[(size_t)slot * NC];
         if (e < max_ent) {
             P.nh_idx[slot] = e;
+            P.rs_oldblk[e] = P.nh_owner[slot];
             uint32_t* dst = &P.rs_in[(size_t)e * NC];
             for (int c = 0; c < NC; ++c) dst[c] = src[c];
         } else {
