@@ -106,8 +106,20 @@ __global__ __launch_bounds__(WG) void k_rs_count(DevParams P, const uint32_t* __
     const int lane = __lane_id(), w = threadIdx.x >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
     const int nb = min(P.ctr->nb, P.block_cap);
-    for (int e = blockIdx.x * (WG / 64) + w; e < nb; e += gridDim.x * (WG / 64)) {
-        const int s = P.b_start[e], c = P.b_count[e];
+    const int stride = gridDim.x * (WG / 64);
+    int s_n = 0, c_n = 0;
+    auto fetch = [&](int e) {  // the wave's next block, loaded while the current one is counted
+        c_n = 0;
+        if (e < nb) {
+            asm volatile("" : "+v"(e));  // same in every lane; keeps the values in vector registers
+            s_n = P.b_start[e];
+            c_n = P.b_count[e];
+        }
+    };
+    fetch(blockIdx.x * (WG / 64) + w);
+    for (int e = blockIdx.x * (WG / 64) + w; e < nb; e += stride) {
+        const int s = s_n, c = c_n;
+        fetch(e + stride);
         cnt[w][lane] = 0u;
         uint32_t owner = ~0u;
         unsigned n_mov = 0u;
@@ -312,22 +324,51 @@ __global__ __launch_bounds__(WG) void k_rs_offsets(DevParams P) {
     }
 }
 
+constexpr int RS_STAGE = 1024;  // particles of a block whose output is staged in LDS (larger: direct stores)
+constexpr uint32_t RS_EMPTY = 0xFFFFFFFFu;  // staging slot left to a mover (indices are < 2^30)
+
 // place, stayers: one wave per previous block, segment in the previous order.
+// The block's output range (stayers and the movers that join it) is staged in
+// LDS and written out contiguously; the metadata of the wave's next block is
+// loaded while the current one is placed.
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_rs_place(DevParams P, const uint32_t* __restrict__ keys_new,
                                                  uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
                                                  int n) {
     constexpr int CB = 2 * DIM, NC = 1 << CB;
     __shared__ unsigned run[WG / 64][64];
+    __shared__ uint32_t sk[WG / 64][RS_STAGE], sv[WG / 64][RS_STAGE];
     const int lane = __lane_id(), w = threadIdx.x >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
     const int nb = min(P.ctr->nb, P.block_cap);
+    const int stride = gridDim.x * (WG / 64);
+    int s_n = 0, c_n = 0;
+    unsigned base_n = 0u, tot_n = 0u, off_n = 0u;
+    uint32_t owner_n = 0u;
+    auto fetch = [&](int e) {
+        c_n = 0;
+        if (e < nb) {
+            asm volatile("" : "+v"(e));  // same in every lane; keeps the values in vector registers
+            s_n = P.b_start[e];
+            c_n = P.b_count[e];
+            owner_n = P.rs_oldblk[e];
+            base_n = P.rs_start[e];
+            tot_n = P.rs_cnt[e];
+            off_n = lane < NC ? P.rs_off[(size_t)e * NC + lane] : 0u;
+        }
+    };
     bool bad = false;
-    for (int e = blockIdx.x * (WG / 64) + w; e < nb; e += gridDim.x * (WG / 64)) {
-        const int s = P.b_start[e], c = P.b_count[e];
+    fetch(blockIdx.x * (WG / 64) + w);
+    for (int e = blockIdx.x * (WG / 64) + w; e < nb; e += stride) {
+        const int s = s_n, c = c_n;
+        const uint32_t owner = owner_n;
+        const unsigned base = base_n, tot = tot_n, off = off_n;
+        fetch(e + stride);
         if (c <= 0) continue;
-        const uint32_t owner = P.rs_oldblk[e];
-        run[w][lane] = lane < NC ? P.rs_off[(size_t)e * NC + lane] : 0u;
+        const bool staged = tot <= (unsigned)RS_STAGE;
+        if (staged)
+            for (unsigned j = lane; j < tot; j += 64) sv[w][j] = RS_EMPTY;
+        run[w][lane] = off;
         const int end = s + c;
         for (int i0 = s; i0 < end; i0 += 64 * RS_BATCH) {
             uint32_t k[RS_BATCH];
@@ -347,12 +388,24 @@ __global__ __launch_bounds__(WG) void k_rs_place(DevParams P, const uint32_t* __
                     const unsigned b0 = run[w][cell];
                     const unsigned pos = b0 + (unsigned)__popcll(m & lt);
                     if ((m & lt) == 0ull) run[w][cell] = b0 + (unsigned)__popcll(m);
-                    if (pos < (unsigned)n) {
+                    if (staged && pos - base < tot) {
+                        sk[w][pos - base] = k[r];
+                        sv[w][pos - base] = (uint32_t)i;
+                    } else if (!staged && pos < (unsigned)n) {
                         keys_out[pos] = k[r];
                         vals_out[pos] = (uint32_t)i;
                     } else {
                         bad = true;
                     }
+                }
+            }
+        }
+        if (staged) {
+            for (unsigned j = lane; j < tot; j += 64) {
+                const uint32_t v = sv[w][j];
+                if (v != RS_EMPTY && base + j < (unsigned)n) {
+                    keys_out[base + j] = sk[w][j];
+                    vals_out[base + j] = v;
                 }
             }
         }
