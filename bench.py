@@ -220,6 +220,27 @@ def ensemble_leg(steps, stream):
             "speedup": t_seq / t_batch, "unit": "particle-steps/s"}
 
 
+def time_graph(sim, steps, stream):
+    """The same step replayed from a HIP graph of two captured steps
+    (`mpm_graph_capture`), timed with events around `steps` // 2 replays;
+    the state returns to sim.a after every replay.  Returns seconds per step."""
+    import torch
+    from paper_2605_28525_amd import mpm as M
+    reps = max(1, steps // 2)
+    M.mpm_graph_capture(sim.ctx, sim.a.view(), sim.b.view(), 2, stream)
+    try:
+        M.mpm_graph_launch(sim.ctx, 1, stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        M.mpm_graph_launch(sim.ctx, reps, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+    finally:
+        M.mpm_graph_release(sim.ctx)
+    return e0.elapsed_time(e1) / 1e3 / (2 * reps)
+
+
 def measured_copy_gbs(mib=2048, reps=5):
     """Device-to-device copy bandwidth of this GPU (read + write bytes / time),
     the measured counterpart of the 8 TB/s spec peak."""
@@ -332,6 +353,11 @@ def main():
     rc, flags = sim.status()
     if rc != 0:
         raise SystemExit(f"device status after timing: {rc} flags={flags}")
+    t_graph = time_graph(sim, args.steps, stream)
+    rc, flags = sim.status()
+    if rc != 0:
+        raise SystemExit(f"device status after graph replays: {rc} flags={flags}")
+    log(f"bench: eager {1e3 * t / args.steps:.3f} ms/step, graph replay {1e3 * t_graph:.3f} ms/step")
     value = n * args.steps / t
     ms_per_step = 1e3 * t / args.steps
     nb, nt = M.mpm_active_count(sim.ctx)
@@ -367,6 +393,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "phases_ms": ph,
+        "graph": {"ms_per_step": 1e3 * t_graph, "value": n / t_graph},
         "tuning": tuning,
         "build_ms_per_step": ph["build"],
         "build_roofline_frac": build_bytes / (ph["build"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
