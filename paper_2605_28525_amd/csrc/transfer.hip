@@ -174,65 +174,78 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
                 for (int a = 0; a < DIM; ++a)
 #pragma unroll
                     for (int k = 0; k < 3; ++k) dxn[a][k] = ((float)k - 0.5f - t[a]) * dx;
-                // Tensor-product factorisation along x: with a = w_y w_z, the
-                // contribution to node k is w_x b + (w_x dx_x) (a A_0) - dw_x (a G_0)
-                // where b = a (m v + A_1 dx_y + A_2 dx_z) - G_1 dw_y w_z - G_2 w_y dw_z
-                // (A = m_p C_p, G = dt V0 tau_p, columns A_j, G_j): three fused
-                // multiply-adds per node and momentum component, one for the mass.
+                // Tensor-product factorisation.  The momentum contribution of the
+                // particle to node (kx, ky, kz) is
+                //   w_x w_y w_z (m v + A dx) - G grad w,   A = m_p C_p, G = dt V0 tau_p,
+                // which regroups as w_x b + w_z h with
+                //   b(ky, kz) = w_z Y(ky) + w_y Z(kz),
+                //   Y(ky) = w_y (m v + A_1 dx_y) - G_1 dw_y,  Z(kz) = w_z dx_z A_2 - G_2 dw_z,
+                //   h(kx, ky) = (w_x dx_x) w_y A_0 - dw_x w_y G_0
+                // (columns A_j, G_j): two fused multiply-adds per node and momentum
+                // component, one for the mass w_x (w_z w_y m_p).
                 if (DIM == 3) {
+                    float Z[3][3], wd[3];
 #pragma unroll
-                    for (int kz = 0; kz < 3; ++kz)
+                    for (int kz = 0; kz < 3; ++kz) {
+                        const float wzd = wt[2][kz] * dxn[2][kz];
 #pragma unroll
-                        for (int ky = 0; ky < 3; ++ky) {
-                            const float al = wt[1][ky] * wt[2][kz];
-                            const float gy = dw[1][ky] * wt[2][kz], gz = wt[1][ky] * dw[2][kz];
-                            const float dy = dxn[1][ky], dz = dxn[2][kz];
+                        for (int q = 0; q < 3; ++q) Z[kz][q] = wzd * A[q][2] - G[q][2] * dw[2][kz];
+                    }
+#pragma unroll
+                    for (int kx = 0; kx < 3; ++kx) wd[kx] = wt[0][kx] * dxn[0][kx];
+#pragma unroll
+                    for (int ky = 0; ky < 3; ++ky) {
+                        const float wy = wt[1][ky];
+                        float Y[3], H[3][3];
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) {
+                            Y[q] = wy * (mv[q] + A[q][1] * dxn[1][ky]) - G[q][1] * dw[1][ky];
+                            const float ya = wy * A[q][0], yg = wy * G[q][0];
+#pragma unroll
+                            for (int kx = 0; kx < 3; ++kx) H[kx][q] = wd[kx] * ya - dw[0][kx] * yg;
+                        }
+                        const float wym = wy * mp;
+#pragma unroll
+                        for (int kz = 0; kz < 3; ++kz) {
+                            const float wz = wt[2][kz];
                             float be[3];
 #pragma unroll
-                            for (int a = 0; a < 3; ++a)
-                                be[a] = al * (mv[a] + A[a][1] * dy + A[a][2] * dz) - G[a][1] * gy - G[a][2] * gz;
-                            float ca[3], cg[3];
-#pragma unroll
-                            for (int a = 0; a < 3; ++a) {
-                                ca[a] = al * A[a][0];
-                                cg[a] = al * G[a][0];
-                            }
-                            const float alm = al * mp;
+                            for (int q = 0; q < 3; ++q) be[q] = wz * Y[q] + wy * Z[kz][q];
+                            const float wzm = wz * wym;
 #pragma unroll
                             for (int kx = 0; kx < 3; ++kx) {
                                 const int k = kx + 3 * (ky + 3 * kz);
-                                const float wx = wt[0][kx], wd = wt[0][kx] * dxn[0][kx], dwx = dw[0][kx];
+                                const float wx = wt[0][kx];
 #pragma unroll
-                                for (int a = 0; a < 3; ++a) {
-                                    float r = fmaf(wx, be[a], acc[k][a]);
-                                    r = fmaf(wd, ca[a], r);
-                                    acc[k][a] = fmaf(-dwx, cg[a], r);
-                                }
-                                acc[k][3] = fmaf(wx, alm, acc[k][3]);
+                                for (int q = 0; q < 3; ++q) acc[k][q] = fmaf(wx, be[q], fmaf(wz, H[kx][q], acc[k][q]));
+                                acc[k][3] = fmaf(wx, wzm, acc[k][3]);
                             }
                         }
+                    }
                 } else {
+                    // 2D: the same with no z axis (w_z = 1, Z = 0)
+                    float wd[3];
+#pragma unroll
+                    for (int kx = 0; kx < 3; ++kx) wd[kx] = wt[0][kx] * dxn[0][kx];
 #pragma unroll
                     for (int ky = 0; ky < 3; ++ky) {
-                        const float al = wt[1][ky];
-                        const float gy = dw[1][ky];
-                        const float dy = dxn[1][ky];
-                        float be[2];
+                        const float wy = wt[1][ky];
+                        float Y[2], H[3][2];
 #pragma unroll
-                        for (int a = 0; a < 2; ++a) be[a] = al * (mv[a] + A[a][1] * dy) - G[a][1] * gy;
-                        const float ca[2] = {al * A[0][0], al * A[1][0]}, cg[2] = {al * G[0][0], al * G[1][0]};
-                        const float alm = al * mp;
+                        for (int q = 0; q < 2; ++q) {
+                            Y[q] = wy * (mv[q] + A[q][1] * dxn[1][ky]) - G[q][1] * dw[1][ky];
+                            const float ya = wy * A[q][0], yg = wy * G[q][0];
+#pragma unroll
+                            for (int kx = 0; kx < 3; ++kx) H[kx][q] = wd[kx] * ya - dw[0][kx] * yg;
+                        }
+                        const float wym = wy * mp;
 #pragma unroll
                         for (int kx = 0; kx < 3; ++kx) {
                             const int k = kx + 3 * ky;
-                            const float wx = wt[0][kx], wd = wt[0][kx] * dxn[0][kx], dwx = dw[0][kx];
+                            const float wx = wt[0][kx];
 #pragma unroll
-                            for (int a = 0; a < 2; ++a) {
-                                float r = fmaf(wx, be[a], acc[k][a]);
-                                r = fmaf(wd, ca[a], r);
-                                acc[k][a] = fmaf(-dwx, cg[a], r);
-                            }
-                            acc[k][3] = fmaf(wx, alm, acc[k][3]);
+                            for (int q = 0; q < 2; ++q) acc[k][q] = fmaf(wx, Y[q], acc[k][q] + H[kx][q]);
+                            acc[k][3] = fmaf(wx, wym, acc[k][3]);
                         }
                     }
                 }
