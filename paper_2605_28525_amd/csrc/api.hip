@@ -49,6 +49,8 @@ struct mpm_ctx {
     // work
     int *w_block = nullptr, *w_start = nullptr, *w_end = nullptr;
     float4* grid = nullptr;
+    float4* tiles = nullptr;
+    int* b_lo = nullptr;
     float4* grid_u = nullptr;
     float4* grid_bar = nullptr;
     float* adj_scratch = nullptr;
@@ -111,6 +113,8 @@ void free_capacity_buffers(mpm_ctx* c) {
     dfree(c->w_start);
     dfree(c->w_end);
     dfree(c->grid);
+    dfree(c->tiles);
+    dfree(c->b_lo);
     dfree(c->grid_u);
     dfree(c->grid_bar);
     dfree(c->partials);
@@ -224,6 +228,8 @@ void fill_params(mpm_ctx* c) {
     P.work_cap = c->work_cap;
     P.chunk = c->chunk;
     P.grid = c->grid;
+    P.tiles = c->tiles;
+    P.b_lo = c->b_lo;
     P.ctr = c->ctr;
     P.grid_u = c->grid_u;
     P.grid_bar = c->grid_bar;
@@ -274,6 +280,11 @@ int alloc_capacity_buffers(mpm_ctx* c) {
     e = e ? e : dalloc(&c->w_start, (size_t)c->work_cap);
     e = e ? e : dalloc(&c->w_end, (size_t)c->work_cap);
     e = e ? e : dalloc(&c->grid, cap * NPB);
+    if (!c->dense) {
+        const size_t tile_nodes = c->dim == 3 ? 216 : 36;
+        e = e ? e : dalloc(&c->tiles, cap * tile_nodes);
+        e = e ? e : dalloc(&c->b_lo, cap * NB);
+    }
     if (c->adjoint) {
         e = e ? e : dalloc(&c->grid_u, cap * NPB);
         e = e ? e : dalloc(&c->grid_bar, cap * NPB);

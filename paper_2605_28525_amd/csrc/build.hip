@@ -336,6 +336,13 @@ __global__ __launch_bounds__(WG) void k_block_setup(DevParams P) {
         for (int d = 1; d < NB; ++d)
             P.b_nbr[b * NB + d] = hash_lookup(P, block_key<DIM>(P, bc[0] + (d & 1), bc[1] + ((d >> 1) & 1),
                                                                  bc[2] + ((d >> 2) & 1), inst));
+        if (P.b_lo) {
+            P.b_lo[b * NB] = b;
+#pragma unroll
+            for (int d = 1; d < NB; ++d)
+                P.b_lo[b * NB + d] = hash_lookup(P, block_key<DIM>(P, bc[0] - (d & 1), bc[1] - ((d >> 1) & 1),
+                                                                    bc[2] - ((d >> 2) & 1), inst));
+        }
         P.b_chunks[b] = (unsigned)((P.b_count[b] + P.chunk - 1) / P.chunk);
     }
 }
@@ -362,9 +369,7 @@ __global__ __launch_bounds__(WG) void k_work_write(DevParams P) {
 }
 
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_grid_clear(DevParams P, long long n_nodes_host) {
-    constexpr int NPB = 1 << (2 * DIM);
-    const long long n_nodes = n_nodes_host >= 0 ? n_nodes_host : (long long)P.ctr->nb * NPB;
+__global__ __launch_bounds__(WG) void k_grid_clear(DevParams P, long long n_nodes) {
     const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
     for (long long s = (long long)blockIdx.x * WG + threadIdx.x; s < n_nodes; s += (long long)gridDim.x * WG)
         P.grid[s] = z;
@@ -466,11 +471,7 @@ hipError_t launch_build_sparse(const DevParams& P, const uint32_t* skeys, int n,
                                   (unsigned*)&P.ctr->n_work, s);
     if (e != hipSuccess) return e;
     k_work_write<<<gb, WG, 0, s>>>(P);
-    const int NPB = P.dim == 3 ? 64 : 16;
-    if (P.dim == 3)
-        k_grid_clear<3><<<grid_for((long long)P.block_cap * NPB), WG, 0, s>>>(P, -1);
-    else
-        k_grid_clear<2><<<grid_for((long long)P.block_cap * NPB), WG, 0, s>>>(P, -1);
+    // no grid clear: the second P2G pass writes every node of every active block
     return hipGetLastError();
 }
 

@@ -7,9 +7,11 @@
 // which spans the block and its upper neighbours (2^d blocks).
 //
 //   P2G: one wave per owner block accumulates the mass and momentum of the
-//        block's particles into an LDS tile, then flushes non-zero tile nodes to
-//        HBM with one global float atomic per channel, so global atomics fall
-//        from 27 x 4 per particle to at most 4 per tile node.
+//        block's particles into an LDS tile and stores the tile to its own slot
+//        in HBM; a second pass gives each node the sum of the (at most 2^d)
+//        tiles that cover it.  No global atomics, and node sums do not depend
+//        on scheduling.  (The dense baseline flushes its tiles with global
+//        float atomics instead, at most 4 per non-zero tile node.)
 //   G2P: a workgroup stages the tile's updated nodal velocities in LDS, then each
 //        thread gathers its 3^d nodes, updates the particle and writes it to its
 //        sorted position (structure-of-arrays, coalesced).
@@ -19,6 +21,7 @@
 //   w = (u^2/2, 1/2 + t u, t^2/2),  dw/dxi = (-u, u - t, t).
 #include <stdlib.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.h"
@@ -33,7 +36,7 @@ namespace mpmx {
 // base node (the low 2d bits of the sort key), and every particle with the same
 // base node scatters to the same 3^d nodes.  A lane therefore sums its cell's
 // particles into 27 x 4 registers and adds them to the LDS tile once per cell,
-// not once per particle; the tile is then flushed to HBM as above.
+// not once per particle; the tile then goes to HBM as above.
 template <int DIM>
 __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __restrict__ x,
                                                  const float* __restrict__ v, const float* __restrict__ C,
@@ -274,6 +277,26 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
             __syncthreads();
         }
         __syncthreads();
+        if (!P.dense) {
+            // sparse grid: the whole tile goes to the block's slot of the tile
+            // store (coalesced plain stores); k_p2g_gather sums the tiles that
+            // cover each node.  A fixed number of stores per lane (the last
+            // node repeated by the lanes past the end) keeps the count of
+            // memory operations in flight static, so the wait for the next
+            // block's metadata does not also wait for these stores.
+#pragma unroll
+            for (int r = 0; r < (T::N + 63) / 64; ++r) {
+                const int t = min(lane + 64 * r, T::N - 1);
+                const int I = t % T::E;
+                const int J = (t / T::E) % T::E;
+                const int K = DIM == 3 ? t / (T::E * T::E) : 0;
+                const int tp = T::pad(I, J, K);
+                P.tiles[(size_t)b * T::N + t] =
+                    make_float4(tile[0][tp], tile[1][tp], DIM == 3 ? tile[2][tp] : 0.f, tile[3][tp]);
+            }
+            __syncthreads();
+            continue;
+        }
         for (int t = lane; t < T::N; t += 64) {
             const int I = t % T::E;
             const int J = (t / T::E) % T::E;
@@ -294,6 +317,42 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
             }
         }
         __syncthreads();
+    }
+}
+
+// P2G, second pass on a sparse grid: node n of block b receives the tile
+// entries that cover it, from b's own tile and from the tiles of the lower
+// neighbours b - d (d in {0,1}^d) whose 6-node tiles reach n (local index < 2
+// on every axis where d is set).  One wave per block, one lane per node; each
+// tile node is read once in total, and the sum is written (no atomics).
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_p2g_gather(DevParams P) {
+    using T = Tile<DIM>;
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
+    const int nb = min(P.ctr->nb, P.block_cap);
+    const int I = lane & 3, J = (lane >> 2) & 3, K = DIM == 3 ? (lane >> 4) & 3 : 0;
+    for (int b = blockIdx.x * (WG / 64) + w; b < nb; b += gridDim.x * (WG / 64)) {
+        int src[T::NB];
+#pragma unroll
+        for (int d = 0; d < T::NB; ++d) {
+            const int a = d == 0 ? b : P.b_lo[(size_t)b * T::NB + d];
+            src[d] = (a >= 0 && P.b_count[a] > 0) ? a : -1;
+        }
+        float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int d = 0; d < T::NB; ++d) {
+            const int dx = d & 1, dy = (d >> 1) & 1, dz = (d >> 2) & 1;
+            const bool reach = (!dx || I < 2) && (!dy || J < 2) && (DIM == 2 || !dz || K < 2);
+            if (src[d] >= 0 && reach && lane < T::NPB) {
+                const int t = (I + 4 * dx) + T::E * ((J + 4 * dy) + (DIM == 3 ? T::E * (K + 4 * dz) : 0));
+                const float4 g = P.tiles[(size_t)src[d] * T::N + t];
+                sum.x += g.x;
+                sum.y += g.y;
+                sum.z += g.z;
+                sum.w += g.w;
+            }
+        }
+        if (lane < T::NPB) P.grid[(size_t)b * T::NPB + lane] = sum;
     }
 }
 
@@ -911,6 +970,13 @@ hipError_t launch_p2g(const DevParams& P, const float* x, const float* v, const 
         k_p2g_cell<3><<<g, 64, 0, s>>>(P, x, v, C, tau, n, order, skeys, osrc);
     else
         k_p2g_cell<2><<<g, 64, 0, s>>>(P, x, v, C, tau, n, order, skeys, osrc);
+    if (!P.dense) {
+        const int gg = (int)std::min<long long>(((long long)P.block_cap + 3) / 4, 16384);  // one wave per block
+        if (P.dim == 3)
+            k_p2g_gather<3><<<gg, WG, 0, s>>>(P);
+        else
+            k_p2g_gather<2><<<gg, WG, 0, s>>>(P);
+    }
     return hipGetLastError();
 }
 
