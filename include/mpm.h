@@ -269,6 +269,34 @@ int mpm_p2g_adj(mpm_ctx* ctx, const mpm_particles* in, const mpm_particles* in_b
 int mpm_step_adj(mpm_ctx* ctx, const mpm_particles* in, const mpm_particles* out_bar, const mpm_particles* in_bar,
                  float* param_bar, void* stream);
 
+/* Tape for checkpointed reverse mode (sparse contexts with MPM_FLAG_ADJOINT,
+ * without MPM_FLAG_SYNC_REBUILD).  The adjoint of a step reads what the step's
+ * own build, P2G and grid update produced (block and work tables, nodal
+ * velocities before and after the boundary conditions, sorted keys and
+ * order).  mpm_step_adj recomputes them; a tape keeps them instead, one slot
+ * per step of a segment, so that the reverse sweep runs only the three
+ * adjoint transfers per step.  A slot holds 2 x 4^d x 16 B of grid plus about
+ * 80 B of tables per block of capacity and 8 B per particle of capacity
+ * (about 28 MB for 262,144 particles at the default block capacity).
+ *
+ * mpm_tape_reserve: allocates n_slots slots (0 frees them; synchronises the
+ *   device).  A capacity change (the overflow rebuild) frees them.
+ * mpm_tape_forward: states[0 .. n_steps] are n_steps + 1 caller-owned sets of
+ *   one size, consecutive ones distinct; runs n_steps steps, step j from
+ *   states[j] to states[j+1] (as mpm_step on that pair), keeping slot j.
+ *   n_steps <= n_slots.  Afterwards no build is current (mpm_p2g etc. need a
+ *   new mpm_sparse_build).
+ * mpm_tape_adjoint: the reverse sweep over the same steps and the same sets,
+ *   unchanged since mpm_tape_forward: on entry `bar` holds dL/d(states[n_steps])
+ *   (in that set's order), on return dL/d(states[0]) (in states[0]'s order);
+ *   `spare` is scratch of the same layout; param_bar accumulates as for
+ *   mpm_step_adj.  Status flags raised in the slots are merged into the
+ *   context's own (mpm_get_status). */
+int mpm_tape_reserve(mpm_ctx* ctx, int n_slots);
+int mpm_tape_forward(mpm_ctx* ctx, const mpm_particles* states, int n_steps, void* stream);
+int mpm_tape_adjoint(mpm_ctx* ctx, const mpm_particles* states, int n_steps, const mpm_particles* bar,
+                     const mpm_particles* spare, float* param_bar, void* stream);
+
 /* ---- graphs and tuning -------------------------------------------------------
  * mpm_graph_capture records n_steps (even, >= 2) of mpm_step(a, b) into a HIP
  * graph held by the context (replacing any previous one).  It first waits for

@@ -3,14 +3,16 @@
 Forward: `steps` explicit steps from an initial state whose velocity is v0,
 with Young's modulus E and friction angle phi, keeping a copy of the state
 every `checkpoint` steps.  Backward: for each checkpoint segment, last first,
-the segment is recomputed from its checkpoint (storing every step's input
-state), then the hand-written adjoint kernels run step by step in reverse
-(mpm_step_adj).  Gradients: dL/dE, dL/dphi (per degree) and dL/dv0 (in the
-initial particle order).
+the segment is recomputed from its checkpoint on the library's tape (every
+step's input state, and its build and grids in one tape slot per step), then
+the hand-written adjoint transfers run step by step in reverse over the tape.
+Gradients: dL/dE, dL/dphi (per degree) and dL/dv0 (in the initial particle
+order).
 
-The library reorders particles every step and the forward uses float atomics,
-so a recomputed state may order particles slightly differently from the first
-pass; adjoints are carried across segment boundaries by particle id.
+The library reorders particles every step, and a recomputed segment need not
+repeat the first pass's order exactly (particles that tie in the sort may be
+placed differently); adjoints are carried across segment boundaries by
+particle id.
 """
 from __future__ import annotations
 
@@ -28,6 +30,7 @@ class Rollout:
         self.K = int(checkpoint)
         self.params = M.params_from_workload(w, block_capacity=block_capacity, flags=M.MPM_FLAG_ADJOINT)
         self.ctx = M.mpm_create(self.params)
+        M.mpm_tape_reserve(self.ctx, self.K)
         self.init = M.ParticleSet.from_arrays(w.state(), device=device)
         self.dim, self.n = w.dim, w.n
         self.device = device
@@ -81,8 +84,8 @@ class Rollout:
             k = min(self.K, self.steps - s0)
             states = self._pool[:k + 1]
             states[0].copy_(self.checkpoints[si])
-            for j in range(k):
-                M.mpm_step(self.ctx, states[j].view(), states[j + 1].view(), 1)
+            views = [st.view() for st in states]
+            M.mpm_tape_forward(self.ctx, views)
             # align the incoming adjoint with the recomputed end state by id
             end_ids = states[-1].id
             if not torch.equal(end_ids, bar_ids):
@@ -91,10 +94,8 @@ class Rollout:
                 perm = inv[end_ids.long()]
                 for key in ("x", "v", "C", "F", "tau"):
                     getattr(bar, key).copy_(getattr(bar, key)[:, perm])
-            # every field of the input adjoint is overwritten by mpm_step_adj
-            for j in range(k - 1, -1, -1):
-                M.mpm_step_adj(self.ctx, states[j].view(), bar.view(), spare.view(), self.param_bar)
-                bar, spare = spare, bar
+            # every field of the input adjoint is overwritten; the result is in bar
+            M.mpm_tape_adjoint(self.ctx, views, bar.view(), spare.view(), self.param_bar)
             bar_ids = states[0].id.clone()
         # the initial state is in the caller's order (ids 0..n-1)
         inv = torch.empty_like(bar_ids, dtype=torch.long)

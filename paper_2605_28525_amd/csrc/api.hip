@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <new>
+#include <vector>
 
 #include "internal.h"
 
@@ -73,6 +74,18 @@ struct mpm_ctx {
     uint32_t* order = nullptr;
     uint32_t* skeys = nullptr;
     uint32_t* osrc = nullptr;  // G2P output position -> input index (the spare sort value buffer)
+    // Reverse-mode tape: for each step of a recorded segment, what its adjoint
+    // reads from the step's build and transfers (block and work tables, both
+    // grids, counters, sorted keys and order).
+    struct TapeSlot {
+        uint64_t* b_keys = nullptr;
+        int *b_nbr = nullptr, *b_start = nullptr, *b_count = nullptr;
+        int *w_block = nullptr, *w_start = nullptr, *w_end = nullptr;
+        float4 *grid = nullptr, *grid_u = nullptr;
+        uint32_t *order = nullptr, *skeys = nullptr;
+    };
+    std::vector<TapeSlot> tape;
+    DevCounters* tape_ctr = nullptr;  // one per slot
 };
 
 namespace {
@@ -131,7 +144,26 @@ void free_capacity_buffers(mpm_ctx* c) {
     c->seg_valid = false;
 }
 
+void free_tape(mpm_ctx* c) {
+    for (auto& t : c->tape) {
+        dfree(t.b_keys);
+        dfree(t.b_nbr);
+        dfree(t.b_start);
+        dfree(t.b_count);
+        dfree(t.w_block);
+        dfree(t.w_start);
+        dfree(t.w_end);
+        dfree(t.grid);
+        dfree(t.grid_u);
+        dfree(t.order);
+        dfree(t.skeys);
+    }
+    c->tape.clear();
+    dfree(c->tape_ctr);
+}
+
 void free_all(mpm_ctx* c) {
+    free_tape(c);
     free_capacity_buffers(c);
     dfree(c->k0);
     dfree(c->k1);
@@ -253,6 +285,7 @@ void fill_params(mpm_ctx* c) {
 
 // (Re)allocate every buffer whose size depends on block_cap or H.
 int alloc_capacity_buffers(mpm_ctx* c) {
+    free_tape(c);  // sized by the capacities
     free_capacity_buffers(c);
     const int NB = 1 << c->dim, NPB = 1 << (2 * c->dim);
     const size_t H = (size_t)1 << c->H_log2;
@@ -379,6 +412,34 @@ int read_counters(mpm_ctx* c, hipStream_t s, DevCounters* out) {
     return MPM_OK;
 }
 
+// Points the context's build tables, grids and counters at tape slot j.
+void bind_slot(mpm_ctx* c, int j) {
+    const mpm_ctx::TapeSlot& t = c->tape[(size_t)j];
+    c->P.b_keys = t.b_keys;
+    c->P.b_nbr = t.b_nbr;
+    c->P.b_start = t.b_start;
+    c->P.b_count = t.b_count;
+    c->P.w_block = t.w_block;
+    c->P.w_start = t.w_start;
+    c->P.w_end = t.w_end;
+    c->P.grid = t.grid;
+    c->P.grid_u = t.grid_u;
+    c->P.ctr = c->tape_ctr + j;
+}
+
+// Checks shared by the tape calls: a sparse adjoint context with a tape of at
+// least n_steps slots, n_steps + 1 distinct sets of one size.
+int tape_args_ok(const mpm_ctx* c, const mpm_particles* states, int n_steps) {
+    if (!c || !states || n_steps < 0) return MPM_ERR_ARG;
+    if (!c->adjoint || c->dense || (c->prm.flags & MPM_FLAG_SYNC_REBUILD)) return MPM_ERR_STATE;
+    if ((size_t)n_steps > c->tape.size()) return MPM_ERR_STATE;
+    for (int j = 0; j <= n_steps; ++j) {
+        if (!particles_ok(c, &states[j], true) || states[j].n != states[0].n) return MPM_ERR_ARG;
+        if (j > 0 && (states[j].x == states[j - 1].x || states[j].F == states[j - 1].F)) return MPM_ERR_ARG;
+    }
+    return MPM_OK;
+}
+
 }  // namespace
 
 namespace mpmx {
@@ -386,6 +447,16 @@ __global__ void k_clear_flags(DevCounters* c) { c->flags = 0u; }
 hipError_t launch_clear_flags(DevCounters* c, hipStream_t s) {
     k_clear_flags<<<1, 1, 0, s>>>(c);
     return hipGetLastError();
+}
+// ORs the status flags of the tape slots [0, n) into the context's counters
+// and clears them.
+__global__ void k_merge_tape_flags(DevCounters* dst, DevCounters* slots, int n) {
+    unsigned f = 0u;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        f |= slots[i].flags;
+        slots[i].flags = 0u;
+    }
+    if (f) atomicOr(&dst->flags, f);
 }
 }  // namespace mpmx
 
@@ -681,6 +752,115 @@ int mpm_step_adj(mpm_ctx* c, const mpm_particles* in, const mpm_particles* ob, c
     if (st == MPM_OK) st = mpm_g2p_adj(c, in, ob, ib, param_bar, stream);
     if (st == MPM_OK) st = mpm_grid_update_adj(c, stream);
     if (st == MPM_OK) st = mpm_p2g_adj(c, in, ib, stream);
+    return st;
+}
+
+int mpm_tape_reserve(mpm_ctx* c, int n_slots) {
+    if (!c || n_slots < 0) return MPM_ERR_ARG;
+    if (!c->adjoint || c->dense) return MPM_ERR_STATE;
+    if (hipDeviceSynchronize() != hipSuccess) return MPM_ERR_HIP;  // no work may still use the old slots
+    free_tape(c);
+    if (n_slots == 0) return MPM_OK;
+    const size_t NB = (size_t)1 << c->dim, NPB = (size_t)1 << (2 * c->dim);
+    const size_t cap = (size_t)c->block_cap, wc = (size_t)c->work_cap, np = (size_t)c->max_particles;
+    hipError_t e = dalloc(&c->tape_ctr, (size_t)n_slots);
+    if (e == hipSuccess) e = hipMemset(c->tape_ctr, 0, (size_t)n_slots * sizeof(DevCounters));
+    c->tape.resize((size_t)n_slots);
+    for (auto& t : c->tape) {
+        e = e ? e : dalloc(&t.b_keys, cap);
+        e = e ? e : dalloc(&t.b_nbr, cap * NB);
+        e = e ? e : dalloc(&t.b_start, cap);
+        e = e ? e : dalloc(&t.b_count, cap);
+        e = e ? e : dalloc(&t.w_block, wc);
+        e = e ? e : dalloc(&t.w_start, wc);
+        e = e ? e : dalloc(&t.w_end, wc);
+        e = e ? e : dalloc(&t.grid, cap * NPB);
+        e = e ? e : dalloc(&t.grid_u, cap * NPB);
+        e = e ? e : dalloc(&t.order, np);
+        e = e ? e : dalloc(&t.skeys, np);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_tape(c);
+        return MPM_ERR_NOMEM;
+    }
+    return MPM_OK;
+}
+
+int mpm_tape_forward(mpm_ctx* c, const mpm_particles* states, int n_steps, void* stream) {
+    int st = tape_args_ok(c, states, n_steps);
+    if (st != MPM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const DevParams saved = c->P;
+    const size_t bytes = (size_t)states[0].n * sizeof(uint32_t);
+    for (int j = 0; j < n_steps && st == MPM_OK; ++j) {
+        bind_slot(c, j);
+        st = mpm_sparse_build(c, &states[j], stream);
+        if (st == MPM_OK && bytes &&
+            (hipMemcpyAsync(c->tape[(size_t)j].order, c->order, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+             hipMemcpyAsync(c->tape[(size_t)j].skeys, c->skeys, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess))
+            st = MPM_ERR_HIP;
+        if (st == MPM_OK) st = mpm_p2g(c, &states[j], stream);
+        if (st == MPM_OK) st = mpm_grid_update(c, stream);
+        if (st == MPM_OK) st = mpm_g2p(c, &states[j], &states[j + 1], stream);
+    }
+    // the context's own tables were not written: no build is current
+    c->P = saved;
+    c->built = false;
+    c->seg_valid = false;
+    if (n_steps > 0) {
+        k_merge_tape_flags<<<1, 64, 0, s>>>(c->ctr, c->tape_ctr, n_steps);
+        if (st == MPM_OK && hipGetLastError() != hipSuccess) st = MPM_ERR_HIP;
+    }
+    return st;
+}
+
+int mpm_tape_adjoint(mpm_ctx* c, const mpm_particles* states, int n_steps, const mpm_particles* bar,
+                     const mpm_particles* spare, float* param_bar, void* stream) {
+    int st = tape_args_ok(c, states, n_steps);
+    if (st != MPM_OK) return st;
+    if (!bar || !spare || !param_bar || bar->n != states[0].n || spare->n != states[0].n) return MPM_ERR_ARG;
+    const mpm_particles* sets[2] = {bar, spare};
+    for (const mpm_particles* q : sets)
+        if (!q->x || !q->v || !q->C || !q->F || !q->tau) return MPM_ERR_ARG;
+    if (bar->x == spare->x) return MPM_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const DevParams saved = c->P;
+    uint32_t* const saved_order = c->order;
+    uint32_t* const saved_skeys = c->skeys;
+    const mpm_particles* ob = bar;
+    const mpm_particles* ib = spare;
+    for (int j = n_steps - 1; j >= 0 && st == MPM_OK; --j) {
+        bind_slot(c, j);
+        c->order = c->tape[(size_t)j].order;
+        c->skeys = c->tape[(size_t)j].skeys;
+        c->built = true;
+        c->built_n = states[j].n;
+        st = mpm_g2p_adj(c, &states[j], ob, ib, param_bar, stream);
+        if (st == MPM_OK) st = mpm_grid_update_adj(c, stream);
+        if (st == MPM_OK) st = mpm_p2g_adj(c, &states[j], ib, stream);
+        std::swap(ob, ib);
+    }
+    c->P = saved;
+    c->order = saved_order;
+    c->skeys = saved_skeys;
+    c->built = false;
+    c->seg_valid = false;
+    if (st == MPM_OK && ob != bar) {
+        // an odd number of steps leaves the result in `spare`
+        const int d = c->dim, ns = d == 3 ? 6 : 3;
+        const size_t n = (size_t)states[0].n * sizeof(float);
+        const float* src[5] = {spare->x, spare->v, spare->C, spare->F, spare->tau};
+        float* dst[5] = {bar->x, bar->v, bar->C, bar->F, bar->tau};
+        const size_t planes[5] = {(size_t)d, (size_t)d, (size_t)(d * d), (size_t)(d * d), (size_t)ns};
+        for (int f = 0; f < 5 && st == MPM_OK; ++f)
+            if (n && hipMemcpyAsync(dst[f], src[f], planes[f] * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                st = MPM_ERR_HIP;
+    }
+    if (n_steps > 0) {
+        k_merge_tape_flags<<<1, 64, 0, s>>>(c->ctr, c->tape_ctr, n_steps);
+        if (st == MPM_OK && hipGetLastError() != hipSuccess) st = MPM_ERR_HIP;
+    }
     return st;
 }
 

@@ -100,6 +100,10 @@ _SIGS = {
     "mpm_p2g_adj": (c_int, [_PCTX, POINTER(mpm_particles), POINTER(mpm_particles), c_void_p]),
     "mpm_step_adj": (c_int, [_PCTX, POINTER(mpm_particles), POINTER(mpm_particles), POINTER(mpm_particles),
                              c_void_p, c_void_p]),
+    "mpm_tape_reserve": (c_int, [_PCTX, c_int]),
+    "mpm_tape_forward": (c_int, [_PCTX, POINTER(mpm_particles), c_int, c_void_p]),
+    "mpm_tape_adjoint": (c_int, [_PCTX, POINTER(mpm_particles), c_int, POINTER(mpm_particles),
+                                 POINTER(mpm_particles), c_void_p, c_void_p]),
     "mpm_graph_capture": (c_int, [_PCTX, POINTER(mpm_particles), POINTER(mpm_particles), c_int, c_void_p]),
     "mpm_graph_launch": (c_int, [_PCTX, c_int, c_void_p]),
     "mpm_graph_release": (c_int, [_PCTX]),
@@ -226,6 +230,29 @@ def mpm_p2g_adj(ctx, pin: mpm_particles, in_bar: mpm_particles, stream=None):
 def mpm_step_adj(ctx, pin: mpm_particles, out_bar: mpm_particles, in_bar: mpm_particles, param_bar, stream=None):
     _check(lib.mpm_step_adj(ctx, ctypes.byref(pin), ctypes.byref(out_bar), ctypes.byref(in_bar),
                             c_void_p(param_bar.data_ptr()), _stream(stream)), "mpm_step_adj")
+
+
+def mpm_tape_reserve(ctx, n_slots: int):
+    _check(lib.mpm_tape_reserve(ctx, int(n_slots)), "mpm_tape_reserve")
+
+
+def _particle_array(states):
+    arr = (mpm_particles * len(states))()
+    for i, st in enumerate(states):
+        arr[i] = st
+    return arr
+
+
+def mpm_tape_forward(ctx, states, stream=None):
+    """states: list of n_steps + 1 mpm_particles views; runs len(states) - 1 steps."""
+    arr = _particle_array(states)
+    _check(lib.mpm_tape_forward(ctx, arr, len(states) - 1, _stream(stream)), "mpm_tape_forward")
+
+
+def mpm_tape_adjoint(ctx, states, bar: mpm_particles, spare: mpm_particles, param_bar, stream=None):
+    arr = _particle_array(states)
+    _check(lib.mpm_tape_adjoint(ctx, arr, len(states) - 1, ctypes.byref(bar), ctypes.byref(spare),
+                                c_void_p(param_bar.data_ptr()), _stream(stream)), "mpm_tape_adjoint")
 
 
 def mpm_graph_capture(ctx, a: mpm_particles, b: mpm_particles, n_steps: int, stream=None):
