@@ -12,6 +12,10 @@ import os
 from ctypes import POINTER, c_double, c_float, c_int, c_uint32, c_uint64, c_void_p
 
 import numpy as np
+# torch is imported before the library is loaded: it ships its own HIP runtime
+# under the same soname as the system one, the first one loaded serves the
+# whole process, and torch's device memory and streams need torch's own.
+import torch  # noqa: F401
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmpm.so")
 
