@@ -124,14 +124,18 @@ def adjoint_ratio(steps, checkpoint=50):
         final = roll.run_forward(v0, w.E, w.friction_deg)
         roll.backward(final, torch.zeros_like(final.x))
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        final = roll.run_forward(v0, w.E, w.friction_deg)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        x_bar = (final.x - final.x.mean()) / n
-        gE, gphi, gv0 = roll.backward(final, x_bar)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
+        fwds, bwds = [], []
+        for _ in range(3):  # median of three rollouts
+            t0 = time.perf_counter()
+            final = roll.run_forward(v0, w.E, w.friction_deg)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            x_bar = (final.x - final.x.mean()) / n
+            gE, gphi, gv0 = roll.backward(final, x_bar)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            fwds.append(t1 - t0)
+            bwds.append(t2 - t1)
         # mpm_step reads a and writes b; mpm_step_adj reads a and the output
         # adjoint and writes the input adjoint: both leave a unchanged
         reps = 20
@@ -173,7 +177,7 @@ def adjoint_ratio(steps, checkpoint=50):
         t_tape_adj = ev[1].elapsed_time(ev[2]) / K
     finally:
         roll.close()
-    fwd, bwd = t1 - t0, t2 - t1
+    fwd, bwd = float(np.median(fwds)), float(np.median(bwds))
     return {"workload": w.name, "particles": n, "steps": steps, "checkpoint_every": checkpoint,
             "step_ms": t_step, "adjoint_step_ms": t_adj, "step_ratio": t_adj / t_step,
             "tape_forward_step_ms": t_tape_fwd, "tape_adjoint_step_ms": t_tape_adj,

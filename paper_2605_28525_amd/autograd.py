@@ -10,9 +10,9 @@ Gradients: dL/dE, dL/dphi (per degree) and dL/dv0 (in the initial particle
 order).
 
 The library reorders particles every step, and a recomputed segment need not
-repeat the first pass's order exactly (particles that tie in the sort may be
-placed differently); adjoints are carried across segment boundaries by
-particle id.
+repeat the first pass's order: the compact block order follows the hash slots
+that concurrent insertions claim, and the particles are stored block by block.
+Adjoints are carried across segment boundaries by particle id.
 """
 from __future__ import annotations
 
@@ -40,6 +40,7 @@ class Rollout:
         self._bars = [M.ParticleSet(w.dim, w.n, device, zero=False) for _ in range(2)]
         self._pool = []   # states of one recomputed segment, allocated on first use
         self.param_bar = torch.zeros(2, dtype=torch.float32, device=device)
+        self._arange = torch.arange(self.n, dtype=torch.long, device=device)
         self.checkpoints = []
 
     def close(self):
@@ -87,19 +88,18 @@ class Rollout:
             views = [st.view() for st in states]
             M.mpm_tape_forward(self.ctx, views)
             # align the incoming adjoint with the recomputed end state by id
-            end_ids = states[-1].id
-            if not torch.equal(end_ids, bar_ids):
-                inv = torch.empty_like(bar_ids, dtype=torch.long)
-                inv[bar_ids.long()] = torch.arange(self.n, device=self.device)
-                perm = inv[end_ids.long()]
-                for key in ("x", "v", "C", "F", "tau"):
-                    getattr(bar, key).copy_(getattr(bar, key)[:, perm])
+            # (always applied, so that no host sync decides whether to)
+            inv = torch.empty_like(bar_ids, dtype=torch.long)
+            inv[bar_ids.long()] = self._arange
+            perm = inv[states[-1].id.long()]
+            for key in ("x", "v", "C", "F", "tau"):
+                getattr(bar, key).copy_(getattr(bar, key)[:, perm])
             # every field of the input adjoint is overwritten; the result is in bar
             M.mpm_tape_adjoint(self.ctx, views, bar.view(), spare.view(), self.param_bar)
             bar_ids = states[0].id.clone()
         # the initial state is in the caller's order (ids 0..n-1)
         inv = torch.empty_like(bar_ids, dtype=torch.long)
-        inv[bar_ids.long()] = torch.arange(self.n, device=self.device)
+        inv[bar_ids.long()] = self._arange
         v0_bar = bar.v[:, inv].clone()
         self._bars = [bar, spare]
         pb = self.param_bar.detach().cpu()
