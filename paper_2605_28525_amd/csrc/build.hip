@@ -21,8 +21,10 @@
 //                   keys, masks and owner segments in Phi order; overflow when
 //                   more than block_capacity slots are occupied (the counter
 //                   check of Algorithm 6).
-//   block setup     upper-neighbour compact indices (so P2G/G2P never probe),
-//                   chunking of owner segments into work items, grid clear.
+//   block setup     upper- and lower-neighbour compact indices (so P2G/G2P never probe),
+//                   chunking of owner segments into work items (the dense
+//                   baseline also clears its grid; the sparse P2G writes
+//                   every node of every active block).
 #include "internal.h"
 #include "../../include/mpm.h"
 
