@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--block-capacity", type=int, default=0)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the 2D and 3D column collapse legs")
     ap.add_argument("--adjoint-steps", type=int, default=400)
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -242,6 +243,50 @@ def ensemble_leg(steps, stream):
             "batched": {"value": n * steps / t_batch, "ms_per_step": 1e3 * t_batch / steps, "graph": True},
             "sequential": {"value": n * steps / t_seq, "ms_per_step": 1e3 * t_seq / steps, "graph": False},
             "speedup": t_seq / t_batch, "unit": "particle-steps/s"}
+
+
+def config_leg(name, steps, stream, dense=False):
+    """A smaller configuration beside the headline one: the sparse step eager
+    (phase-timed) and replayed from a graph, the build time, the step's byte
+    model against the HBM peak, and with ``dense`` the dense-grid step."""
+    import torch
+    from paper_2605_28525_amd import mpm as M
+    from paper_2605_28525_amd import workloads as wl
+    w = {"collapse_2d": wl.collapse_2d, "collapse_3d": wl.collapse_3d}[name]()
+    n, d = w.n, w.dim
+    sim = M.Simulation(w)
+    try:
+        sim.step(10, stream=stream)
+        t, ph = time_steps(sim, steps, stream)
+        t_graph = time_graph(sim, steps, stream)
+        rc, flags = sim.status()
+        if rc != 0:
+            raise SystemExit(f"{name}: device status {rc} flags={flags}")
+        nb, _ = M.mpm_active_count(sim.ctx)
+    finally:
+        sim.close()
+    n_slot = nb * 4 ** d
+    step_bytes = (276 if d == 3 else 148) * n + (72 if d == 3 else 52) * n_slot
+    best = min(t / steps, t_graph)
+    out = {"workload": name, "particles": n, "cells": list(w.cells[:d]), "steps": steps,
+           "value": n * steps / t, "ms_per_step": 1e3 * t / steps, "phases_ms": ph,
+           "graph": {"value": n / t_graph, "ms_per_step": 1e3 * t_graph},
+           "build_ms_per_step": ph["build"], "active_blocks": nb,
+           "step_roofline_frac": step_bytes / best / 1e9 / HBM_PEAK_GBS}
+    if dense:
+        simd = M.Simulation(w, grid_mode=M.MPM_GRID_DENSE)
+        try:
+            simd.step(2, stream=stream)
+            td, _ = time_steps(simd, steps, stream, phases=False)
+            rc, flags = simd.status()
+            if rc != 0:
+                raise SystemExit(f"{name} dense: device status {rc} flags={flags}")
+        finally:
+            simd.close()
+        out["dense"] = {"value": n * steps / td, "ms_per_step": 1e3 * td / steps}
+        out["speedup_vs_dense"] = td / t
+    torch.cuda.empty_cache()
+    return out
 
 
 def time_graph(sim, steps, stream):
@@ -446,6 +491,10 @@ def main():
         simd.close()
         del simd
         torch.cuda.empty_cache()
+    if not args.no_configs:
+        log("bench: 2D and 3D column collapse")
+        out["configs"] = [config_leg("collapse_2d", args.steps, stream),
+                          config_leg("collapse_3d", args.steps, stream, dense=True)]
     if not args.no_adjoint:
         log("bench: adjoint/forward ratio")
         out["adjoint"] = adjoint_ratio(args.adjoint_steps)
