@@ -291,8 +291,11 @@ __global__ __launch_bounds__(WG) void k_compact_count(DevParams P, int H, unsign
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(WG) void k_compact_write(DevParams P, int H, const unsigned* __restrict__ partials) {
+__global__ __launch_bounds__(WG) void k_compact_write(DevParams P, int H, const unsigned* __restrict__ partials,
+                                                      int tiles) {
     __shared__ unsigned lds[WG / 64];
+    unsigned before, total;
+    tile_offset(partials, blockIdx.x, tiles, lds, &before, &total);
     const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
     bool occ[SCAN_ITEMS];
     unsigned s = 0;
@@ -303,7 +306,7 @@ __global__ __launch_bounds__(WG) void k_compact_write(DevParams P, int H, const 
         s += occ[j];
     }
     unsigned tot;
-    unsigned phi = wg_excl_scan(s, lds, &tot) + partials[blockIdx.x];
+    unsigned phi = wg_excl_scan(s, lds, &tot) + before;
     bool over = false;
 #pragma unroll
     for (int j = 0; j < SCAN_ITEMS; ++j) {
@@ -323,7 +326,10 @@ __global__ __launch_bounds__(WG) void k_compact_write(DevParams P, int H, const 
         ++phi;
     }
     if (over) raise_flag(P.ctr, MPM_FLAG_OVERFLOW);
-    if (blockIdx.x == 0 && threadIdx.x == 0) P.ctr->nb = min(P.ctr->n_touched, P.block_cap);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        P.ctr->n_touched = total;
+        P.ctr->nb = min((int)total, P.block_cap);
+    }
 }
 
 template <int DIM>
@@ -462,8 +468,7 @@ hipError_t launch_build_sparse(const DevParams& P, const uint32_t* skeys, int n,
     }
     const int tiles = ((int)H + SCAN_TILE - 1) / SCAN_TILE;
     k_compact_count<<<tiles, WG, 0, s>>>(P, (int)H, partials);
-    scan_partials(partials, tiles, (unsigned*)&P.ctr->n_touched, s);
-    k_compact_write<<<tiles, WG, 0, s>>>(P, (int)H, partials);
+    k_compact_write<<<tiles, WG, 0, s>>>(P, (int)H, partials, tiles);
     const int gb = grid_for(P.block_cap, 2048);
     if (P.dim == 3)
         k_block_setup<3><<<gb, WG, 0, s>>>(P);

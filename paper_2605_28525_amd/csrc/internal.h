@@ -301,12 +301,27 @@ __device__ __forceinline__ unsigned wg_excl_scan(unsigned v, unsigned* lds, unsi
     return off + inc - v;
 }
 
+// For a pass over tiles whose sums are partials[0 .. tiles): the sum of the
+// tiles before `tile` (its exclusive offset) and the sum of all of them, both
+// computed by the whole 256-thread workgroup (each workgroup reads the few
+// tile sums itself instead of waiting for a separate scan of them).
+__device__ __forceinline__ void tile_offset(const unsigned* __restrict__ partials, int tile, int tiles,
+                                            unsigned* lds, unsigned* before, unsigned* total) {
+    unsigned b = 0, t = 0;
+    for (int i = threadIdx.x; i < tiles; i += WG) {
+        const unsigned v = partials[i];
+        t += v;
+        b += i < tile ? v : 0u;
+    }
+    wg_excl_scan(b, lds, before);
+    wg_excl_scan(t, lds, total);
+}
+
 // ---------------------------------------------------------------------------
 // host-side launchers (each returns hipError_t of the launch)
 hipError_t scan_exclusive(const unsigned* in, unsigned* out, int n, const int* n_dev, unsigned* partials,
                           unsigned* total_out, hipStream_t s);
 int scan_partials_size(int n);
-hipError_t scan_partials(unsigned* partials, int tiles, unsigned* total_out, hipStream_t s);
 
 hipError_t radix_sort(const uint32_t* keys_in, uint32_t* k0, uint32_t* k1, uint32_t* v0, uint32_t* v1, int n,
                       int key_bits, unsigned* hist, unsigned* partials, uint32_t** keys_out, uint32_t** vals_out,

@@ -246,9 +246,13 @@ __global__ __launch_bounds__(WG) void k_rs_new_count(DevParams P, int H, unsigne
 // ... then numbered after the previous blocks (slot order), with their mover
 // counts moved into the entry rows.
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_rs_new_write(DevParams P, int H, const unsigned* __restrict__ partials) {
+__global__ __launch_bounds__(WG) void k_rs_new_write(DevParams P, int H, const unsigned* __restrict__ partials,
+                                                     int tiles) {
     constexpr int NC = 1 << (2 * DIM);
     __shared__ unsigned lds[WG / 64];
+    unsigned before, total;
+    tile_offset(partials, blockIdx.x, tiles, lds, &before, &total);
+    if (blockIdx.x == 0 && threadIdx.x == 0) P.ctr->rs_n_new = total;
     const int nb = min(P.ctr->nb, P.block_cap);
     const int max_ent = 2 * P.block_cap;
     const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
@@ -261,7 +265,7 @@ __global__ __launch_bounds__(WG) void k_rs_new_write(DevParams P, int H, const u
         s += occ[j];
     }
     unsigned tot;
-    unsigned j = wg_excl_scan(s, lds, &tot) + partials[blockIdx.x];
+    unsigned j = wg_excl_scan(s, lds, &tot) + before;
     bool over = false;
 #pragma unroll
     for (int q = 0; q < SCAN_ITEMS; ++q) {
@@ -518,13 +522,11 @@ hipError_t launch_resort(const DevParams& P, uint32_t* keys_prev, const uint32_t
         k_rs_route<2><<<gm, WG, 0, s>>>(P, keys_new, movers, n);
     }
     k_rs_new_count<<<htiles, WG, 0, s>>>(P, (int)H, partials);
-    e = scan_partials(partials, htiles, (unsigned*)&P.ctr->rs_n_new, s);
-    if (e != hipSuccess) return e;
     if (P.dim == 3) {
-        k_rs_new_write<3><<<htiles, WG, 0, s>>>(P, (int)H, partials);
+        k_rs_new_write<3><<<htiles, WG, 0, s>>>(P, (int)H, partials, htiles);
         k_rs_entry_count<3><<<ge, WG, 0, s>>>(P);
     } else {
-        k_rs_new_write<2><<<htiles, WG, 0, s>>>(P, (int)H, partials);
+        k_rs_new_write<2><<<htiles, WG, 0, s>>>(P, (int)H, partials, htiles);
         k_rs_entry_count<2><<<ge, WG, 0, s>>>(P);
     }
     e = scan_exclusive(P.rs_cnt, P.rs_start, 2 * P.block_cap, &P.ctr->rs_n_ent, partials, nullptr, s);
