@@ -452,7 +452,7 @@ hipError_t launch_bin(const DevParams& P, const float* x, const uint32_t* inst, 
 
 hipError_t launch_build_sparse(const DevParams& P, const uint32_t* skeys, int n, unsigned H, unsigned* partials,
                                hipStream_t s, bool from_resort) {
-    k_hash_clear<<<grid_for(H), WG, 0, s>>>(P, H);
+    if (!from_resort) k_hash_clear<<<grid_for(H), WG, 0, s>>>(P, H);  // the re-sort's last pass clears it
     if (n > 0 && from_resort) {
         const int ge = grid_for(2ll * P.block_cap * 64, 16384);  // one wave per entry
         if (P.dim == 3)

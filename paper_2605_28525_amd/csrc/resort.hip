@@ -27,7 +27,8 @@
 //            mover: movers go after the stayers of their cell, in the order
 //            their atomic slot claims land;
 //   reset    the per-entry mover counts and the second table are cleared for
-//            the next build.
+//            the next build, and the block hash for the insertion that
+//            follows.
 // Cost: two reads of the new keys and one write of keys and values, against
 // 2-4 full read/write passes of the radix sort.  The per-block kernels only
 // stream keys; the dependent lookups of the few movers run one per thread, so
@@ -467,9 +468,23 @@ __global__ __launch_bounds__(WG) void k_rs_reset(DevParams P, unsigned H) {
     const long long all = rows > (long long)H ? rows : (long long)H;
     for (long long t = (long long)blockIdx.x * WG + threadIdx.x; t < all; t += (long long)gridDim.x * WG) {
         if (t < rows) P.rs_in[t] = 0u;
-        if (t < (long long)H) P.nh_keys[t] = EMPTY_KEY;
+        if (t < (long long)H) {
+            P.nh_keys[t] = EMPTY_KEY;
+            // the block hash, which the re-sort was the last to read, is
+            // cleared here for the insertion that follows (Algorithm 5's
+            // initialisation)
+            P.h_keys[t] = EMPTY_KEY;
+            P.h_mask[t] = 0ull;
+            P.h_start[t] = -1;
+            P.h_end[t] = -1;
+        }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) P.ctr->rs_n_mov = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        P.ctr->rs_n_mov = 0;
+        P.ctr->nb = 0;
+        P.ctr->n_touched = 0;
+        P.ctr->n_work = 0;
+    }
 }
 
 // Initial state of the buffers the re-sort expects between builds.
