@@ -84,8 +84,10 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
         else
             unblock_key<DIM>(P, key, bc, &inst);
         const InstMat mat = material(P, inst);
+        // the lanes accumulate per unit particle mass (m_p is uniform in a
+        // block); the merge into the tile scales by m_p
         const float mp = mat.p_mass;
-        const float dtv = mat.dt * mat.p_vol0;
+        const float dtv = mat.dt * mat.p_vol0 / mp;
         const int org[3] = {bc[0] * BLK, bc[1] * BLK, bc[2] * BLK};
         // cell ranges of the block and its G2P output layout (rank-major over
         // the base cells), with the block's permutation staged in LDS by the
@@ -153,12 +155,13 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
                 particle_frame<DIM>(P, xp, org, lb, t, u);
                 float wt[3][3], dw[3][3];
                 bspline<DIM>(t, u, inv_dx, wt, dw);
+                // per unit mass: m v -> v, A = m C -> C, G = dt V0 tau / m
                 float mv[3], A[3][3], G[3][3];
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) {
-                    mv[a] = mp * vp[a];
+                    mv[a] = vp[a];
 #pragma unroll
-                    for (int bb = 0; bb < DIM; ++bb) A[a][bb] = mp * Cp[a * DIM + bb];
+                    for (int bb = 0; bb < DIM; ++bb) A[a][bb] = Cp[a * DIM + bb];
                 }
                 if (DIM == 3) {
                     G[0][0] = dtv * tp[0];
@@ -180,14 +183,21 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
                 // Tensor-product factorisation.  The momentum contribution of the
                 // particle to node (kx, ky, kz) is
                 //   w_x w_y w_z (m v + A dx) - G grad w,   A = m_p C_p, G = dt V0 tau_p,
-                // which regroups as w_x b + w_z h with
+                // which regroups as w_x b + (w_z w_y) h with
                 //   b(ky, kz) = w_z Y(ky) + w_y Z(kz),
                 //   Y(ky) = w_y (m v + A_1 dx_y) - G_1 dw_y,  Z(kz) = w_z dx_z A_2 - G_2 dw_z,
-                //   h(kx, ky) = (w_x dx_x) w_y A_0 - dw_x w_y G_0
+                //   h(kx) = (w_x dx_x) A_0 - dw_x G_0
                 // (columns A_j, G_j): two fused multiply-adds per node and momentum
-                // component, one for the mass w_x (w_z w_y m_p).
+                // component, one for the mass w_x (w_z w_y).
+                float h[3][3], wd[3];
+#pragma unroll
+                for (int kx = 0; kx < 3; ++kx) {
+                    wd[kx] = wt[0][kx] * dxn[0][kx];
+#pragma unroll
+                    for (int q = 0; q < DIM; ++q) h[kx][q] = wd[kx] * A[q][0] - dw[0][kx] * G[q][0];
+                }
                 if (DIM == 3) {
-                    float Z[3][3], wd[3];
+                    float Z[3][3];
 #pragma unroll
                     for (int kz = 0; kz < 3; ++kz) {
                         const float wzd = wt[2][kz] * dxn[2][kz];
@@ -195,60 +205,44 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
                         for (int q = 0; q < 3; ++q) Z[kz][q] = wzd * A[q][2] - G[q][2] * dw[2][kz];
                     }
 #pragma unroll
-                    for (int kx = 0; kx < 3; ++kx) wd[kx] = wt[0][kx] * dxn[0][kx];
-#pragma unroll
                     for (int ky = 0; ky < 3; ++ky) {
                         const float wy = wt[1][ky];
-                        float Y[3], H[3][3];
+                        float Y[3];
 #pragma unroll
-                        for (int q = 0; q < 3; ++q) {
-                            Y[q] = wy * (mv[q] + A[q][1] * dxn[1][ky]) - G[q][1] * dw[1][ky];
-                            const float ya = wy * A[q][0], yg = wy * G[q][0];
-#pragma unroll
-                            for (int kx = 0; kx < 3; ++kx) H[kx][q] = wd[kx] * ya - dw[0][kx] * yg;
-                        }
-                        const float wym = wy * mp;
+                        for (int q = 0; q < 3; ++q) Y[q] = wy * (mv[q] + A[q][1] * dxn[1][ky]) - G[q][1] * dw[1][ky];
 #pragma unroll
                         for (int kz = 0; kz < 3; ++kz) {
                             const float wz = wt[2][kz];
+                            const float wzy = wz * wy;
                             float be[3];
 #pragma unroll
                             for (int q = 0; q < 3; ++q) be[q] = wz * Y[q] + wy * Z[kz][q];
-                            const float wzm = wz * wym;
+
 #pragma unroll
                             for (int kx = 0; kx < 3; ++kx) {
                                 const int k = kx + 3 * (ky + 3 * kz);
                                 const float wx = wt[0][kx];
 #pragma unroll
-                                for (int q = 0; q < 3; ++q) acc[k][q] = fmaf(wx, be[q], fmaf(wz, H[kx][q], acc[k][q]));
-                                acc[k][3] = fmaf(wx, wzm, acc[k][3]);
+                                for (int q = 0; q < 3; ++q) acc[k][q] = fmaf(wx, be[q], fmaf(wzy, h[kx][q], acc[k][q]));
+                                acc[k][3] = fmaf(wx, wzy, acc[k][3]);
                             }
                         }
                     }
                 } else {
                     // 2D: the same with no z axis (w_z = 1, Z = 0)
-                    float wd[3];
-#pragma unroll
-                    for (int kx = 0; kx < 3; ++kx) wd[kx] = wt[0][kx] * dxn[0][kx];
 #pragma unroll
                     for (int ky = 0; ky < 3; ++ky) {
                         const float wy = wt[1][ky];
-                        float Y[2], H[3][2];
+                        float Y[2];
 #pragma unroll
-                        for (int q = 0; q < 2; ++q) {
-                            Y[q] = wy * (mv[q] + A[q][1] * dxn[1][ky]) - G[q][1] * dw[1][ky];
-                            const float ya = wy * A[q][0], yg = wy * G[q][0];
-#pragma unroll
-                            for (int kx = 0; kx < 3; ++kx) H[kx][q] = wd[kx] * ya - dw[0][kx] * yg;
-                        }
-                        const float wym = wy * mp;
+                        for (int q = 0; q < 2; ++q) Y[q] = wy * (mv[q] + A[q][1] * dxn[1][ky]) - G[q][1] * dw[1][ky];
 #pragma unroll
                         for (int kx = 0; kx < 3; ++kx) {
                             const int k = kx + 3 * ky;
                             const float wx = wt[0][kx];
 #pragma unroll
-                            for (int q = 0; q < 2; ++q) acc[k][q] = fmaf(wx, Y[q], acc[k][q] + H[kx][q]);
-                            acc[k][3] = fmaf(wx, wym, acc[k][3]);
+                            for (int q = 0; q < 2; ++q) acc[k][q] = fmaf(wx, Y[q], fmaf(wy, h[kx][q], acc[k][q]));
+                            acc[k][3] = fmaf(wx, wy, acc[k][3]);
                         }
                     }
                 }
@@ -260,7 +254,8 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
             walk(std::true_type{});
         else
             walk(std::false_type{});
-        // Merge the cell sums into the tile.  For a fixed offset k, distinct
+        // Merge the cell sums (per unit mass, scaled by m_p here) into the
+        // tile.  For a fixed offset k, distinct
         // cells address distinct nodes, so each offset is a conflict-free
         // read-add-write; the barrier orders successive offsets, which may hit
         // the same node from neighbouring cells.
@@ -269,10 +264,10 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
             const int kx = k % 3, ky = (k / 3) % 3, kz = DIM == 3 ? k / 9 : 0;
             const int idx = T::pad(lb[0] + kx, lb[1] + ky, DIM == 3 ? lb[2] + kz : 0);
             if (has) {
-                tile[0][idx] += acc[k][0];
-                tile[1][idx] += acc[k][1];
-                if (DIM == 3) tile[2][idx] += acc[k][2];
-                tile[3][idx] += acc[k][3];
+                tile[0][idx] = fmaf(mp, acc[k][0], tile[0][idx]);
+                tile[1][idx] = fmaf(mp, acc[k][1], tile[1][idx]);
+                if (DIM == 3) tile[2][idx] = fmaf(mp, acc[k][2], tile[2][idx]);
+                tile[3][idx] = fmaf(mp, acc[k][3], tile[3][idx]);
             }
             __syncthreads();
         }
