@@ -849,13 +849,16 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
             for (int a = 0; a < DIM; ++a)
 #pragma unroll
                 for (int k = 0; k < 3; ++k) dxn[a][k] = ((float)k - 0.5f - t[a]) * dx;
-            // Tensor-product factorisation along x: per (ky, kz) row sum
-            // S0 = sum w_x v, S1 = sum w_x dx_x v, S2 = sum dw_x v, then
-            // v_p += a S0, B = [a S1 | a dx_y S0 | a dx_z S0],
-            // grad v = [a S2 | dw_y w_z S0 | w_y dw_z S0] with a = w_y w_z.
+            // Tensor-product factorisation, one axis at a time.  Along x, per
+            // (ky, kz) row: S0 = sum w_x v, S1 = sum w_x dx_x v, S2 = sum dw_x v.
+            // Along y, per kz plane: U0 = sum w_y S0, U1 = sum w_y dx_y S0,
+            // U2 = sum dw_y S0, U3 = sum w_y S1, U4 = sum w_y S2.  Along z:
+            // v_p = sum w_z U0, B = sum [w_z U3 | w_z U1 | w_z dx_z U0],
+            // grad v = sum [w_z U4 | w_z U2 | dw_z U0].
             float vp[3] = {0, 0, 0}, B[3][3] = {{0}}, gv[3][3] = {{0}};
 #pragma unroll
-            for (int kz = 0; kz < (DIM == 3 ? 3 : 1); ++kz)
+            for (int kz = 0; kz < (DIM == 3 ? 3 : 1); ++kz) {
+                float U0[3] = {0, 0, 0}, U1[3] = {0, 0, 0}, U2[3] = {0, 0, 0}, U3[3] = {0, 0, 0}, U4[3] = {0, 0, 0};
 #pragma unroll
                 for (int ky = 0; ky < 3; ++ky) {
                     float S0[3] = {0, 0, 0}, S1[3] = {0, 0, 0}, S2[3] = {0, 0, 0};
@@ -872,31 +875,37 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
                             S2[a] += dwx * vn[a];
                         }
                     }
-                    const float wz = DIM == 3 ? wt[2][kz] : 1.f;
-                    const float al = wt[1][ky] * wz;
-                    const float b1 = al * dxn[1][ky];
-                    const float g1 = dw[1][ky] * wz;
+                    const float wy = wt[1][ky], wyd = wt[1][ky] * dxn[1][ky], dwy = dw[1][ky];
 #pragma unroll
                     for (int a = 0; a < DIM; ++a) {
-                        vp[a] += al * S0[a];
-                        B[a][0] += al * S1[a];
-                        B[a][1] += b1 * S0[a];
-                        gv[a][0] += al * S2[a];
-                        gv[a][1] += g1 * S0[a];
-                    }
-                    if (DIM == 3) {
-                        const float b2 = al * dxn[2][kz];
-                        const float g2 = wt[1][ky] * dw[2][kz];
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            B[a][2] += b2 * S0[a];
-                            gv[a][2] += g2 * S0[a];
-                        }
+                        U0[a] += wy * S0[a];
+                        U1[a] += wyd * S0[a];
+                        U2[a] += dwy * S0[a];
+                        U3[a] += wy * S1[a];
+                        U4[a] += wy * S2[a];
                     }
                     // keep the LDS gathers of one row in flight at a time
                     // (bounds register pressure, hence raises occupancy)
                     __builtin_amdgcn_sched_barrier(0);
                 }
+                const float wz = DIM == 3 ? wt[2][kz] : 1.f;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    vp[a] += wz * U0[a];
+                    B[a][0] += wz * U3[a];
+                    B[a][1] += wz * U1[a];
+                    gv[a][0] += wz * U4[a];
+                    gv[a][1] += wz * U2[a];
+                }
+                if (DIM == 3) {
+                    const float wzd = wz * dxn[2][kz], dwz = dw[2][kz];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        B[a][2] += wzd * U0[a];
+                        gv[a][2] += dwz * U0[a];
+                    }
+                }
+            }
             const size_t o = (size_t)(s + r);
             bool finite = true;
 #pragma unroll
