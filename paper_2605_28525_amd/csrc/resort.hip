@@ -329,7 +329,8 @@ __global__ __launch_bounds__(WG) void k_rs_offsets(DevParams P) {
     }
 }
 
-constexpr int RS_STAGE = 1024;  // particles of a block whose output is staged in LDS (larger: direct stores)
+constexpr int RS_STAGE = 768;  // particles of a block whose output is staged in LDS (larger: direct stores);
+                                // 25 KB of LDS per workgroup, six workgroups per compute unit
 constexpr uint32_t RS_EMPTY = 0xFFFFFFFFu;  // staging slot left to a mover (indices are < 2^30)
 
 // place, stayers: one wave per previous block, segment in the previous order.
