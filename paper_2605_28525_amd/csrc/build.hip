@@ -345,11 +345,16 @@ __global__ __launch_bounds__(WG) void k_block_setup(DevParams P) {
             P.b_nbr[b * NB + d] = hash_lookup(P, block_key<DIM>(P, bc[0] + (d & 1), bc[1] + ((d >> 1) & 1),
                                                                  bc[2] + ((d >> 2) & 1), inst));
         if (P.b_lo) {
-            P.b_lo[b * NB] = b;
+            // lower neighbours that own particles (the blocks whose P2G tiles
+            // reach this block), -1 for the others
+            int lo[NB];
+            lo[0] = b;
 #pragma unroll
             for (int d = 1; d < NB; ++d)
-                P.b_lo[b * NB + d] = hash_lookup(P, block_key<DIM>(P, bc[0] - (d & 1), bc[1] - ((d >> 1) & 1),
-                                                                    bc[2] - ((d >> 2) & 1), inst));
+                lo[d] = hash_lookup(P, block_key<DIM>(P, bc[0] - (d & 1), bc[1] - ((d >> 1) & 1),
+                                                      bc[2] - ((d >> 2) & 1), inst));
+#pragma unroll
+            for (int d = 0; d < NB; ++d) P.b_lo[b * NB + d] = (lo[d] >= 0 && P.b_count[lo[d]] > 0) ? lo[d] : -1;
         }
         P.b_chunks[b] = (unsigned)((P.b_count[b] + P.chunk - 1) / P.chunk);
     }

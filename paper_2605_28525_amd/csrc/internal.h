@@ -99,7 +99,7 @@ struct DevParams {
     // grid
     float4* grid;
     float4* tiles;        // sparse P2G: each block's (4+2)^d node tile, block-major
-    int* b_lo;            // sparse P2G: 2^d lower-neighbour compact indices (d = 0: the block)
+    int* b_lo;            // sparse P2G: 2^d lower neighbours (d = 0: the block) owning particles, else -1
     DevCounters* ctr;
     // reverse mode (allocated with MPM_FLAG_ADJOINT)
     float4* grid_u;      // pre-boundary nodal velocity u = p/m + dt g, and m

@@ -327,12 +327,9 @@ __global__ __launch_bounds__(WG) void k_p2g_gather(DevParams P) {
     const int nb = min(P.ctr->nb, P.block_cap);
     const int I = lane & 3, J = (lane >> 2) & 3, K = DIM == 3 ? (lane >> 4) & 3 : 0;
     for (int b = blockIdx.x * (WG / 64) + w; b < nb; b += gridDim.x * (WG / 64)) {
-        int src[T::NB];
+        int src[T::NB];  // the block and its lower neighbours that own particles, else -1
 #pragma unroll
-        for (int d = 0; d < T::NB; ++d) {
-            const int a = d == 0 ? b : P.b_lo[(size_t)b * T::NB + d];
-            src[d] = (a >= 0 && P.b_count[a] > 0) ? a : -1;
-        }
+        for (int d = 0; d < T::NB; ++d) src[d] = P.b_lo[(size_t)b * T::NB + d];
         float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
         for (int d = 0; d < T::NB; ++d) {
