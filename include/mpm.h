@@ -187,9 +187,11 @@ const char* mpm_status_string(int status);
  * domain. */
 int mpm_sparse_build(mpm_ctx* ctx, const mpm_particles* p, void* stream);
 
-/* P2G onto the compact storage (Eqs. 6, 7, 9): clears the active blocks and
- * accumulates per node m_n and p_n = sum_p N m_p [v_p + C_p (x_n - x_p)]
- * - dt sum_p V0_p tau_p grad N_n.  Requires a build of the same positions. */
+/* P2G onto the compact storage (Eqs. 6, 7, 9): sets every node of the active
+ * blocks to m_n and p_n = sum_p N m_p [v_p + C_p (x_n - x_p)]
+ * - dt sum_p V0_p tau_p grad N_n (zero where no particle reaches).  Requires a
+ * build of the same positions; one call per build (on a dense grid the sums
+ * accumulate into the grid that the build cleared). */
 int mpm_p2g(mpm_ctx* ctx, const mpm_particles* p, void* stream);
 
 /* Grid update (Eqs. 8, 10-12): v_n = p_n / m_n + dt g where m_n > 0, else 0,
