@@ -568,21 +568,24 @@ __device__ __forceinline__ unsigned constitutive(int model, const InstMat& P, co
     // 1e-7 relative at |M| = 1/8); the return map acts on dev(E) as a matrix;
     // tau = 2 mu E' + lambda tr(E') I; F_new = expm(E' - E) F with expm - I to
     // degree 5 (|E' - E| <= |E|).
-    float Q[3][3], L[3][3];
+    // log(I + M) = sum_{k=1..7} (-1)^(k+1) M^k / k, evaluated as
+    // (M - M^2/2 + M^3/3) + M^3 (-M/4 + M^2/5 - M^3/6 + M^4/7)
+    // (Paterson-Stockmeyer: four matrix products instead of six)
+    float Q[3][3], L[3][3], M2[3][3], M3[3][3], M4[3][3];
+    sym_mul<DIM>(M, M, M2);
+    sym_mul<DIM>(M2, M, M3);
+    sym_mul<DIM>(M2, M2, M4);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) Q[a][b] = (a == b ? (1.f / 6.f) : 0.f) - M[a][b] * (1.f / 7.f);
-#pragma unroll
-    for (int c = 5; c >= 1; --c) {
-        sym_mul<DIM>(M, Q, L);
-#pragma unroll
-        for (int a = 0; a < DIM; ++a)
-#pragma unroll
-            for (int b = 0; b < DIM; ++b) Q[a][b] = (a == b ? 1.f / (float)c : 0.f) - L[a][b];
-    }
+        for (int b = 0; b < 3; ++b)
+            Q[a][b] = -0.25f * M[a][b] + M2[a][b] * (1.f / 5.f) - M3[a][b] * (1.f / 6.f) + M4[a][b] * (1.f / 7.f);
     float E[3][3];
-    sym_mul<DIM>(M, Q, E);
+    sym_mul<DIM>(M3, Q, L);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) E[a][b] = M[a][b] - 0.5f * M2[a][b] + M3[a][b] * (1.f / 3.f) + L[a][b];
     float tr = 0.f;
 #pragma unroll
     for (int a = 0; a < DIM; ++a)
