@@ -42,6 +42,20 @@ __device__ __forceinline__ void particle_frame(const DevParams& P, const float* 
     }
 }
 
+// The same offsets for a particle whose base node is known (P2G's lanes own
+// one base cell each, the sort key's cell, which the binning took from the
+// same float64 floor and clamp): t = s - base without recomputing the floor.
+template <int DIM>
+__device__ __forceinline__ void particle_frame_at(const DevParams& P, const float* xp, const double* base, float* t,
+                                                  float* u) {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const double td = index_arg(xp[a], P.inv_dx) - base[a];
+        t[a] = fminf(fmaxf((float)td, 0.f), 1.f);
+        u[a] = fminf(fmaxf((float)(1.0 - td), 0.f), 1.f);
+    }
+}
+
 template <int DIM>
 __device__ __forceinline__ void bspline(const float* t, const float* u, float inv_dx, float (*w)[3], float (*dw)[3]) {
 #pragma unroll

@@ -99,6 +99,7 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
 #pragma unroll
         for (int k = 0; k < NK; ++k) acc[k][0] = acc[k][1] = acc[k][2] = acc[k][3] = 0.f;
         int lb[3] = {lane & 3, (lane >> 2) & 3, DIM == 3 ? (lane >> 4) & 3 : 0};
+        const double base[3] = {(double)(org[0] + lb[0]), (double)(org[1] + lb[1]), (double)(org[2] + lb[2])};
         const int c0 = lane < NC ? il.cs[lane] : 0, c1 = lane < NC ? il.ce[lane] : 0;
         const bool has = c1 > c0;
         // The walk over the lane's particles, with the source index read from
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
                 qn = src(min(i + 1, c1 - 1));
                 load_particle(qn);
                 float t[3] = {0, 0, 0}, u[3] = {1, 1, 1};
-                particle_frame<DIM>(P, xp, org, lb, t, u);
+                particle_frame_at<DIM>(P, xp, base, t, u);
                 float wt[3][3], dw[3][3];
                 bspline<DIM>(t, u, inv_dx, wt, dw);
                 // per unit mass: m v -> v, A = m C -> C, G = dt V0 tau / m
