@@ -30,7 +30,7 @@
 
 namespace mpmx {
 
-constexpr int BIN_PER_THREAD = 4;  // particles per thread of k_bin (loads issued together)
+constexpr int BIN_PER_THREAD = 2;  // particles per thread of k_bin (loads issued together)
 
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_bin(DevParams P, const float* __restrict__ x,
