@@ -121,37 +121,23 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
             // its own particle), so the number of loads in flight never depends
             // on the path taken and the wait for them lands after the
             // accumulation, not before it.
-            float xn[3], vn[3], Cn[9], tn[6];
-            auto load_particle = [&](size_t q) {
+            // Two register sets take turns (A holds particle i while the loads
+            // of particle i + 1 land in B, and the other way round), so no
+            // copies move a prefetched particle into place.
+            float xa[3], va[3], Ca[9], ta[6], xb[3], vb[3], Cb[9], tb[6];
+            auto load_into = [&](float* xs, float* vs, float* Cs, float* ts, uint32_t q) {
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) {
-                    xn[a] = x[(size_t)a * n + q];
-                    vn[a] = v[(size_t)a * n + q];
+                    xs[a] = x[(size_t)a * n + q];
+                    vs[a] = v[(size_t)a * n + q];
                 }
 #pragma unroll
-                for (int k = 0; k < DIM * DIM; ++k) Cn[k] = C[(size_t)k * n + q];
+                for (int k = 0; k < DIM * DIM; ++k) Cs[k] = C[(size_t)k * n + q];
 #pragma unroll
-                for (int k = 0; k < NS; ++k) tn[k] = tau[(size_t)k * n + q];
+                for (int k = 0; k < NS; ++k) ts[k] = tau[(size_t)k * n + q];
             };
-            uint32_t qn = 0;
-            if (has) {
-                qn = src(c0);
-                load_particle(qn);
-            }
-            for (int i = c0; i < c1; ++i) {
-                float xp[3] = {0, 0, 0}, vp[3] = {0, 0, 0}, Cp[9], tp[6];
-#pragma unroll
-                for (int a = 0; a < DIM; ++a) {
-                    xp[a] = xn[a];
-                    vp[a] = vn[a];
-                }
-#pragma unroll
-                for (int k = 0; k < DIM * DIM; ++k) Cp[k] = Cn[k];
-#pragma unroll
-                for (int k = 0; k < NS; ++k) tp[k] = tn[k];
-                const uint32_t qp = qn;
-                qn = src(min(i + 1, c1 - 1));
-                load_particle(qn);
+            auto process = [&](const float* xp, const float* vp, const float* Cp, const float* tp, uint32_t qp,
+                               int i) {
                 float t[3] = {0, 0, 0}, u[3] = {1, 1, 1};
                 particle_frame_at<DIM>(P, xp, base, t, u);
                 float wt[3][3], dw[3][3];
@@ -249,6 +235,19 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
                 }
                 // the G2P output position of this particle records its source
                 osrc[interleave_pos_cj<DIM>(il, lane, i - c0)] = qp;
+            };
+            uint32_t qa = 0, qb = 0;
+            if (has) {
+                qa = src(c0);
+                load_into(xa, va, Ca, ta, qa);
+            }
+            for (int i = c0; i < c1; i += 2) {
+                qb = src(min(i + 1, c1 - 1));
+                load_into(xb, vb, Cb, tb, qb);
+                process(xa, va, Ca, ta, qa, i);
+                qa = src(min(i + 2, c1 - 1));
+                load_into(xa, va, Ca, ta, qa);
+                if (i + 1 < c1) process(xb, vb, Cb, tb, qb, i + 1);
             }
         };
         if (cnt <= P2G_ORDER_STAGE)
