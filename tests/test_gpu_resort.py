@@ -151,3 +151,37 @@ def _run_pair_continue(w, inc, full, steps, label):
         compare_states(w, inc.b, full.b)
         inc.a, inc.b = inc.b, inc.a
         full.a, full.b = full.b, full.a
+
+
+def _dense_blocks():
+    """A 3D cluster at 64 particles per cell (8^3 cells, 32,768 particles):
+    4096 particles per owner block, more than the re-sort stages in LDS, and
+    64 per cell, past the rank-major layout's 32 interleaved ranks."""
+    w = wl.tiny_3d(n=48, ties=False)
+    rng = np.random.default_rng(41)
+    x = wl.stratified_cells((4, 4, 4), (12, 12, 12), w.dx, 4, rng)
+    st = wl.rest_state(x)
+    for k, a in st.items():
+        setattr(w, k, a)
+    w.ppc = 64
+    w.p_vol0 = w.dx ** 3 / 64
+    w.p_mass = 2000.0 * w.p_vol0
+    return wl.perturbed(w, seed=43, v_scale=0.05, C_scale=0.2, F_scale=1e-3, tau_scale=50.0)
+
+
+def test_incremental_dense_blocks():
+    """Blocks of 4096 particles (placement without LDS staging) and cells of
+    64 (ranks past the interleaved ones), before and after displacing every
+    particle by up to a cell."""
+    w = _dense_blocks()
+    _announce("resort dense blocks", w.n)
+    inc, full = _run_pair(w, 2, "dense_blocks")
+    rng = np.random.default_rng(47)
+    st = inc.a.to_arrays()
+    ids = inc.a.ids()
+    st["x"] = (st["x"].astype(np.float64) + rng.uniform(-1.0, 1.0, size=st["x"].shape) * w.dx).astype(np.float32)
+    inc.set_state(st, ids=ids)
+    full.set_state(st, ids=ids)
+    _run_pair_continue(w, inc, full, 2, "dense_blocks displaced")
+    inc.close()
+    full.close()
