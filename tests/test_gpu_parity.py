@@ -36,6 +36,29 @@ def test_tiny_3d_one_step(ties):
     sim.close()
 
 
+def test_dense_cells_one_step():
+    """64 particles per cell over 8^3 cells (32,768 particles): 4096 per owner
+    block, so P2G reads the permutation from HBM instead of its LDS copy, and
+    cells past the 32 interleaved ranks of the output layout; two steps (the
+    second after an incremental re-sort)."""
+    w = wl.tiny_3d(n=48, ties=False)
+    rng = np.random.default_rng(41)
+    x = wl.stratified_cells((4, 4, 4), (12, 12, 12), w.dx, 4, rng)
+    for k, a in wl.rest_state(x).items():
+        setattr(w, k, a)
+    w.ppc, w.p_vol0 = 64, w.dx ** 3 / 64
+    w.p_mass = 2000.0 * w.p_vol0
+    w = wl.perturbed(w, seed=43, v_scale=0.05, C_scale=0.2, F_scale=1e-3, tau_scale=50.0)
+    _announce("dense cells", w.n)
+    sim = _sim(w)
+    for k in range(2):
+        parts = gpu_step_parts(sim)
+        assert parts["status"][0] == 0, (k, parts["status"])
+        print(k, compare_step(w, parts))
+        sim.a, sim.b = sim.b, sim.a
+    sim.close()
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_large_and_small_elastic_strain_one_step(dim):
     """Deformation gradients R diag(exp(s)) with principal log-stretches s of
