@@ -147,7 +147,8 @@ typedef struct mpm_params {
 } mpm_params;
 
 typedef struct mpm_particles {
-    int n;                   /* number of particles (<= max_particles) */
+    int n;                   /* number of particles (<= max_particles); with n = 0 the
+                                array pointers may be NULL */
     float* x;
     float* v;
     float* C;

@@ -355,7 +355,9 @@ int alloc_capacity_buffers(mpm_ctx* c) {
 }
 
 bool particles_ok(const mpm_ctx* c, const mpm_particles* p, bool need_state) {
-    if (!p || p->n < 0 || p->n > c->max_particles || !p->x) return false;
+    if (!p || p->n < 0 || p->n > c->max_particles) return false;
+    if (p->n == 0) return true;  // an empty set needs no arrays
+    if (!p->x) return false;
     if (c->n_inst > 1 && !p->inst) return false;
     if (need_state && (!p->v || !p->C || !p->F || !p->tau)) return false;
     return true;
@@ -435,7 +437,8 @@ int tape_args_ok(const mpm_ctx* c, const mpm_particles* states, int n_steps) {
     if ((size_t)n_steps > c->tape.size()) return MPM_ERR_STATE;
     for (int j = 0; j <= n_steps; ++j) {
         if (!particles_ok(c, &states[j], true) || states[j].n != states[0].n) return MPM_ERR_ARG;
-        if (j > 0 && (states[j].x == states[j - 1].x || states[j].F == states[j - 1].F)) return MPM_ERR_ARG;
+        if (j > 0 && states[0].n > 0 && (states[j].x == states[j - 1].x || states[j].F == states[j - 1].F))
+            return MPM_ERR_ARG;
     }
     return MPM_OK;
 }
@@ -678,11 +681,12 @@ int mpm_grid_update(mpm_ctx* c, void* stream) {
 }
 
 int mpm_g2p(mpm_ctx* c, const mpm_particles* in, const mpm_particles* out, void* stream) {
-    if (!c || !particles_ok(c, in, false) || !out || !out->x || !out->v || !out->C || !out->F || !out->tau ||
-        !in->F || out->n != in->n)
-        return MPM_ERR_ARG;
-    if (in->x == out->x || in->F == out->F) return MPM_ERR_ARG;
-    if (c->n_inst > 1 && (!out->inst || out->inst == in->inst)) return MPM_ERR_ARG;
+    if (!c || !particles_ok(c, in, false) || !out || out->n != in->n) return MPM_ERR_ARG;
+    if (in->n > 0) {
+        if (!out->x || !out->v || !out->C || !out->F || !out->tau || !in->F) return MPM_ERR_ARG;
+        if (in->x == out->x || in->F == out->F) return MPM_ERR_ARG;
+        if (c->n_inst > 1 && (!out->inst || out->inst == in->inst)) return MPM_ERR_ARG;
+    }
     if (!c->built || in->n != c->built_n) return MPM_ERR_STATE;
     if (in->n == 0) return MPM_OK;
     const int wgs = std::min(c->g2p_wgs, c->work_cap);
@@ -707,8 +711,9 @@ int mpm_step(mpm_ctx* c, const mpm_particles* a, const mpm_particles* b, int n_s
 
 int mpm_g2p_adj(mpm_ctx* c, const mpm_particles* in, const mpm_particles* ob, const mpm_particles* ib,
                 float* param_bar, void* stream) {
-    if (!c || !particles_ok(c, in, false) || !in->F || !ob || !ib || !param_bar) return MPM_ERR_ARG;
-    if (!ob->x || !ob->v || !ob->C || !ob->F || !ob->tau || !ib->x || !ib->F) return MPM_ERR_ARG;
+    if (!c || !particles_ok(c, in, false) || !ob || !ib || !param_bar) return MPM_ERR_ARG;
+    if (in->n > 0 && (!in->F || !ob->x || !ob->v || !ob->C || !ob->F || !ob->tau || !ib->x || !ib->F))
+        return MPM_ERR_ARG;
     if (ob->n != in->n || ib->n != in->n) return MPM_ERR_ARG;
     if (!c->adjoint || !c->built || in->n != c->built_n) return MPM_ERR_STATE;
     if (in->n == 0) return MPM_OK;
@@ -733,7 +738,7 @@ int mpm_grid_update_adj(mpm_ctx* c, void* stream) {
 
 int mpm_p2g_adj(mpm_ctx* c, const mpm_particles* in, const mpm_particles* ib, void* stream) {
     if (!c || !particles_ok(c, in, true) || !ib || ib->n != in->n) return MPM_ERR_ARG;
-    if (!ib->x || !ib->v || !ib->C || !ib->tau) return MPM_ERR_ARG;
+    if (in->n > 0 && (!ib->x || !ib->v || !ib->C || !ib->tau)) return MPM_ERR_ARG;
     if (!c->adjoint || !c->built || in->n != c->built_n) return MPM_ERR_STATE;
     if (in->n == 0) return MPM_OK;
     const float* inp[4] = {in->x, in->v, in->C, in->tau};
@@ -821,9 +826,11 @@ int mpm_tape_adjoint(mpm_ctx* c, const mpm_particles* states, int n_steps, const
     if (st != MPM_OK) return st;
     if (!bar || !spare || !param_bar || bar->n != states[0].n || spare->n != states[0].n) return MPM_ERR_ARG;
     const mpm_particles* sets[2] = {bar, spare};
-    for (const mpm_particles* q : sets)
-        if (!q->x || !q->v || !q->C || !q->F || !q->tau) return MPM_ERR_ARG;
-    if (bar->x == spare->x) return MPM_ERR_ARG;
+    if (states[0].n > 0) {
+        for (const mpm_particles* q : sets)
+            if (!q->x || !q->v || !q->C || !q->F || !q->tau) return MPM_ERR_ARG;
+        if (bar->x == spare->x) return MPM_ERR_ARG;
+    }
     hipStream_t s = (hipStream_t)stream;
     const DevParams saved = c->P;
     uint32_t* const saved_order = c->order;
