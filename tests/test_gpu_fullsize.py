@@ -125,3 +125,52 @@ def test_landslide_full_size():
     errs["particles"] = int(len(o_sel))
     print(errs)
     assert errs["particles"] > 100000 and errs["nodes"] > 10000 and errs["blocks"] > 100
+
+
+def test_ensemble_full_size():
+    """The 64-instance ensemble (about 19.5 M particles) in its benchmarked
+    configuration (autotuned), one batched step after two: ids and instances
+    carried, and four instances (the smallest, the largest and two others)
+    against stand-alone runs from the same state (active sets bit-exact,
+    fields at the parity tolerance)."""
+    from paper_2605_28525_amd import mpm as M
+    from test_gpu_ensemble import FIELDS, _by_id, _decode_ensemble_keys, _member_index, _one_step
+    from oracle import sparse as osp
+    ens = wl.ensemble()
+    print("CASE ensemble full size", ens.n_instances, ens.n, flush=True)
+    sizes = np.array([m.n for m in ens.members])
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 17, 42})
+    midx = _member_index(ens)
+    batch = M.Simulation(ens)
+    try:
+        batch.step(2)
+        M.mpm_autotune(batch.ctx, batch.a.view(), batch.b.view())
+        st = batch.a.to_arrays()
+        ids = batch.a.ids().astype(np.int64)
+        insts = batch.a.insts().astype(np.int64)
+        bkeys, bmasks = _one_step(batch)
+        binst, bblk = _decode_ensemble_keys(bkeys)
+        out_ids = batch.b.ids()
+        assert np.array_equal(np.sort(out_ids), np.arange(ens.n)), "ids lost"
+        assert np.array_equal(np.bincount(batch.b.insts(), minlength=ens.n_instances), sizes), "instances lost"
+        for i in pick:
+            m = ens.members[i]
+            sel = np.nonzero(insts == i)[0]
+            order = np.argsort(midx[ids[sel]])
+            sim = M.Simulation(m)
+            try:
+                sim.set_state({k: st[k][:, sel[order]] for k in FIELDS})
+                skeys, smasks = _one_step(sim)
+                sblk = osp.unpack_key(skeys, 3)
+                got = {tuple(b): int(mk) for b, mk in zip(bblk[binst == i].tolist(), bmasks[binst == i])}
+                ref = {tuple(b): int(mk) for b, mk in zip(sblk.tolist(), smasks)}
+                assert got == ref, f"instance {i}: active sets differ ({len(got)} vs {len(ref)})"
+                bo = _by_id(batch.b, ens.member_positions(i))
+                so = _by_id(sim.b, np.arange(m.n))
+                for k in FIELDS:
+                    assert_field(f"inst {i} {k}", bo[k], so[k], RTOL, atol=tau_floor(m) if k == "tau" else 0.0)
+                print("instance", i, m.n, "ok", flush=True)
+            finally:
+                sim.close()
+    finally:
+        batch.close()
