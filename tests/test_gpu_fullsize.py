@@ -174,3 +174,33 @@ def test_ensemble_full_size():
                 sim.close()
     finally:
         batch.close()
+
+
+def test_collapse_3d_full_size_properties():
+    """The 3D column collapse at full size (2,097,152 particles, 512 x 128 x 128
+    cells; the 1/8-scale copy is compared with the oracle in the parity tests):
+    one step after 10 in the benchmarked configuration, checked by the
+    whole-step properties (status, permutation and ids, finite outputs, grid
+    mass and momentum)."""
+    from paper_2605_28525_amd import mpm as M
+    w = wl.collapse_3d()
+    n, d = w.n, w.dim
+    print("CASE collapse_3d full size", n, flush=True)
+    sim = M.Simulation(w)
+    try:
+        sim.step(10)
+        parts = gpu_step_parts(sim)
+    finally:
+        sim.close()
+    assert parts["status"][0] == 0, parts["status"]
+    order = parts["order"].astype(np.int64)
+    assert np.array_equal(np.sort(order), np.arange(n))
+    assert np.array_equal(parts["ids_out"], parts["ids_in"][order])
+    for f in ("x", "v", "C", "F", "tau"):
+        assert np.isfinite(parts["state_out"][f]).all(), f
+    g1 = parts["grid_p2g"].reshape(-1, 4).astype(np.float64)
+    m_tot = n * float(w.p_mass)
+    assert abs(g1[:, 3].sum() - m_tot) <= 1e-5 * m_tot
+    v_in = parts["state_in"]["v"].astype(np.float64)
+    mom = float(w.p_mass) * v_in.sum(axis=1)
+    assert np.all(np.abs(g1[:, :d].sum(axis=0) - mom) <= 1e-5 * float(w.p_mass) * np.abs(v_in).sum())
