@@ -267,6 +267,44 @@ def landslide_crop(seed_particles: int = 102) -> Workload:
                      seed_particles=seed_particles)
 
 
+SLIDE_MU = float(np.tan(np.deg2rad(15.0)))   # Coulomb coefficient of the sliding-block plane
+
+
+def sliding_block(theta_deg: float, seed: int = 21, dx: float = 0.02, block_cells=(10, 5, 5),
+                  E: float = 5.0e4, rho: float = 1000.0) -> Workload:
+    """Elastic block released at rest on a plane inclined at ``theta_deg`` about the
+    y axis: terrain z = 0.6 m - x tan(theta) over a 40x16x40-cell grid at dx = 0.02 m,
+    Coulomb friction mu = tan 15 deg.  The block, 0.2 x 0.1 x 0.1 m (10x5x5 cells
+    of dx along slope, across and normal), holds 8 particles per dx^3, stratified-
+    jittered in the slope's own frame, the lowest ones within dx/2 above the plane;
+    its upslope face starts 0.1 m downslope of x = 0 measured along the plane.
+    ``meta``: the downslope unit vector and the slope angle."""
+    th = np.deg2rad(theta_deg)
+    rng = np.random.default_rng(seed)
+    cells = (40, 16, 40)
+    z0 = 0.6
+    t_hat = np.array([np.cos(th), 0.0, -np.sin(th)])
+    n_hat = np.array([np.sin(th), 0.0, np.cos(th)])
+    local = stratified_cells((0, 0, 0), block_cells, dx, 2, rng).astype(np.float64)   # (s, w, n)
+    s0, w0 = 0.1 + 4 * dx, 0.1
+    anchor = np.array([s0 * np.cos(th), w0, z0 - s0 * np.sin(th)])
+    x = anchor[:, None] + t_hat[:, None] * local[0] + np.array([0.0, 1.0, 0.0])[:, None] * local[1] \
+        + n_hat[:, None] * local[2]
+    X = np.arange(cells[0] + 1, dtype=np.float64) * dx
+    hm = np.repeat((z0 - X * np.tan(th))[:, None], cells[1] + 1, axis=1).astype(np.float32)
+    vol = dx ** 3 / 8
+    w = Workload(name=f"sliding_block_{theta_deg:g}", dim=3, dx=dx, cells=cells, gravity=(0.0, 0.0, -9.81),
+                 dt=0.3 * dx / float(np.sqrt(E * 0.7 / (1.3 * 0.4 * rho))), steps=0, ppc=8, p_vol0=vol,
+                 p_mass=rho * vol, model="elastic", E=E, nu=0.3, rho=rho, friction_deg=0.0,
+                 bc=(("separate", "separate"), ("separate", "separate"), ("separate", "separate")),
+                 heightmap=hm, mu_terrain=SLIDE_MU)
+    w.meta["downslope"] = t_hat
+    w.meta["slope_deg"] = float(theta_deg)
+    for k, a in rest_state(x.astype(np.float32)).items():
+        setattr(w, k, a)
+    return w
+
+
 def elastic_bar_2d(length_cells: int = 128, thick_cells: int = 4, amplitude: float = 2.3e-3,
                    seed: int = 7) -> Workload:
     """Free-free elastic bar in 2D (plane strain) carrying its fundamental
