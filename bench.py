@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--block-capacity", type=int, default=0)
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--no-configs", action="store_true", help="skip the 2D and 3D column collapse legs")
+    ap.add_argument("--no-configs", action="store_true", help="skip the column collapse and sliding-block legs")
     ap.add_argument("--adjoint-steps", type=int, default=400)
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -252,7 +252,8 @@ def config_leg(name, steps, stream, dense=False):
     import torch
     from paper_2605_28525_amd import mpm as M
     from paper_2605_28525_amd import workloads as wl
-    w = {"collapse_2d": wl.collapse_2d, "collapse_3d": wl.collapse_3d}[name]()
+    w = {"collapse_2d": wl.collapse_2d, "collapse_3d": wl.collapse_3d,
+         "sliding_block_30": lambda: wl.sliding_block(30.0)}[name]()
     n, d = w.n, w.dim
     sim = M.Simulation(w)
     try:
@@ -494,7 +495,8 @@ def main():
     if not args.no_configs:
         log("bench: 2D and 3D column collapse")
         out["configs"] = [config_leg("collapse_2d", args.steps, stream),
-                          config_leg("collapse_3d", args.steps, stream, dense=True)]
+                          config_leg("collapse_3d", args.steps, stream, dense=True),
+                          config_leg("sliding_block_30", args.steps, stream, dense=True)]
     if not args.no_adjoint:
         log("bench: adjoint/forward ratio")
         out["adjoint"] = adjoint_ratio(args.adjoint_steps)
