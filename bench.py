@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--block-capacity", type=int, default=0)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-resolution", action="store_true",
+                    help="skip the landslide at dx = 4 m and 2 m (sparse and dense steps, device memory)")
     ap.add_argument("--no-configs", action="store_true", help="skip the column collapse and sliding-block legs")
     ap.add_argument("--adjoint-steps", type=int, default=400)
     ap.add_argument("--no-ensemble", action="store_true")
@@ -290,6 +292,49 @@ def config_leg(name, steps, stream, dense=False):
     return out
 
 
+def device_bytes_of(make):
+    """The object make() returns and the device memory it took (free memory
+    before minus after; torch's cache is emptied first, so the figure holds the
+    particle arrays and the context's own allocations)."""
+    import torch
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    f0 = torch.cuda.mem_get_info()[0]
+    obj = make()
+    torch.cuda.synchronize()
+    return obj, f0 - torch.cuda.mem_get_info()[0]
+
+
+def resolution_leg(h, steps, stream):
+    """The landslide coarsened to dx = h metres (same terrain and release):
+    whole sparse and dense steps (events around `steps` steps after 10) and
+    the device memory of each (particles included)."""
+    import torch
+    from paper_2605_28525_amd import mpm as M
+    from paper_2605_28525_amd import workloads as wl
+    w = wl.landslide(h=h)
+    n = w.n
+    out = {"workload": w.name, "dx_m": float(h), "particles": n, "cells": list(w.cells), "steps": steps}
+    for mode, name in ((M.MPM_GRID_SPARSE, "sparse"), (M.MPM_GRID_DENSE, "dense")):
+        sim, nbytes = device_bytes_of(lambda: M.Simulation(w, grid_mode=mode))
+        try:
+            sim.step(10, stream=stream)
+            t, _ = time_steps(sim, steps, stream, phases=False)
+            rc, flags = sim.status()
+            if rc != 0:
+                raise SystemExit(f"{w.name} {name}: device status {rc} flags={flags}")
+            if mode == M.MPM_GRID_SPARSE:
+                out["active_blocks"] = M.mpm_active_count(sim.ctx)[0]
+        finally:
+            sim.close()
+            del sim
+            torch.cuda.empty_cache()
+        out[name] = {"value": n * steps / t, "ms_per_step": 1e3 * t / steps, "device_bytes": nbytes}
+    out["speedup_vs_dense"] = out["dense"]["ms_per_step"] / out["sparse"]["ms_per_step"]
+    out["memory_reduction"] = out["dense"]["device_bytes"] / out["sparse"]["device_bytes"]
+    return out
+
+
 def time_graph(sim, steps, stream):
     """The same step replayed from a HIP graph of two captured steps
     (`mpm_graph_capture`), timed with events around `steps` // 2 replays;
@@ -405,7 +450,7 @@ def main():
     d = w.dim
     log(f"bench: {w.name} n={n} cells={w.cells}")
     cap = args.block_capacity or (1 << 18 if args.workload == "landslide" else 1 << 16)
-    sim = M.Simulation(w, block_capacity=cap)
+    sim, sparse_bytes = device_bytes_of(lambda: M.Simulation(w, block_capacity=cap))
     log("bench: warmup")
     if args.warmup:
         sim.step(args.warmup, stream=stream)
@@ -479,7 +524,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_dense:
         log("bench: dense baseline")
-        simd = M.Simulation(w, grid_mode=M.MPM_GRID_DENSE)
+        simd, dense_bytes = device_bytes_of(lambda: M.Simulation(w, grid_mode=M.MPM_GRID_DENSE))
         simd.step(2, stream=stream)
         td, _ = time_steps(simd, args.dense_steps, stream, phases=False)
         rc, flags = simd.status()
@@ -489,6 +534,9 @@ def main():
         out["dense"] = {"value": dense_value, "ms_per_step": 1e3 * td / args.dense_steps,
                         "steps": args.dense_steps}
         out["speedup_vs_dense"] = value / dense_value
+        # device memory, particle arrays included (the same in both)
+        out["memory"] = {"sparse_bytes": sparse_bytes, "dense_bytes": dense_bytes,
+                         "reduction": dense_bytes / sparse_bytes}
         simd.close()
         del simd
         torch.cuda.empty_cache()
@@ -497,6 +545,9 @@ def main():
         out["configs"] = [config_leg("collapse_2d", args.steps, stream),
                           config_leg("collapse_3d", args.steps, stream, dense=True),
                           config_leg("sliding_block_30", args.steps, stream, dense=True)]
+    if not args.no_resolution and args.workload == "landslide":
+        log("bench: landslide at dx = 4 m and 2 m")
+        out["resolution"] = [resolution_leg(h, args.steps, stream) for h in (4, 2)]
     if not args.no_adjoint:
         log("bench: adjoint/forward ratio")
         out["adjoint"] = adjoint_ratio(args.adjoint_steps)

@@ -204,3 +204,47 @@ def test_collapse_3d_full_size_properties():
     v_in = parts["state_in"]["v"].astype(np.float64)
     mom = float(w.p_mass) * v_in.sum(axis=1)
     assert np.all(np.abs(g1[:, :d].sum(axis=0) - mom) <= 1e-5 * float(w.p_mass) * np.abs(v_in).sum())
+
+
+@pytest.mark.parametrize("h", [4, 2])
+def test_landslide_coarse(h):
+    """The landslide coarsened to dx = 4 m (312,480 particles, 512 x 512 x 64
+    cells) and 2 m (2,480,000 particles, 1024 x 1024 x 128 cells), the
+    resolution sweep of the bench: whole-step properties after 10 steps, and
+    the sparse and the dense grid giving the same positions after 10 steps
+    (within 4 float32 ulps of the largest coordinate)."""
+    from paper_2605_28525_amd import mpm as M
+    w = wl.landslide(h=h)
+    n, d = w.n, w.dim
+    print("CASE landslide coarse", h, n, flush=True)
+    xs = {}
+    for mode in (M.MPM_GRID_SPARSE, M.MPM_GRID_DENSE):
+        sim = M.Simulation(w, grid_mode=mode)
+        try:
+            sim.step(10)
+            rc, flags = sim.status()
+            assert rc == 0, (mode, flags)
+            x = sim.a.to_arrays()["x"].astype(np.float64)
+            xb = np.empty_like(x)
+            xb[:, sim.a.ids().astype(np.int64)] = x
+            xs[mode] = xb
+            if mode == M.MPM_GRID_SPARSE:
+                parts = gpu_step_parts(sim)
+        finally:
+            sim.close()
+    assert parts["status"][0] == 0, parts["status"]
+    order = parts["order"].astype(np.int64)
+    assert np.array_equal(np.sort(order), np.arange(n))
+    assert np.array_equal(parts["ids_out"], parts["ids_in"][order])
+    for f in ("x", "v", "C", "F", "tau"):
+        assert np.isfinite(parts["state_out"][f]).all(), f
+    g1 = parts["grid_p2g"].reshape(-1, 4).astype(np.float64)
+    m_tot = n * float(w.p_mass)
+    assert abs(g1[:, 3].sum() - m_tot) <= 1e-5 * m_tot
+    v_in = parts["state_in"]["v"].astype(np.float64)
+    mom = float(w.p_mass) * v_in.sum(axis=1)
+    assert np.all(np.abs(g1[:, :d].sum(axis=0) - mom) <= 1e-5 * float(w.p_mass) * np.abs(v_in).sum())
+    diff = float(np.max(np.abs(xs[M.MPM_GRID_SPARSE] - xs[M.MPM_GRID_DENSE])))
+    ulp = float(np.spacing(np.float32(np.max(np.abs(xs[M.MPM_GRID_SPARSE])))))
+    print("sparse - dense max |dx|", diff, "ulp", ulp, flush=True)
+    assert diff <= 4 * ulp, (diff, ulp)
