@@ -47,7 +47,8 @@ def parse():
     ap.add_argument("--block-capacity", type=int, default=0)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-resolution", action="store_true",
-                    help="skip the landslide at dx = 4 m and 2 m (sparse and dense steps, device memory)")
+                    help="skip the landslide at dx = 4 m and 2 m (sparse and dense steps, device memory; "
+                         "--no-dense skips it too)")
     ap.add_argument("--no-configs", action="store_true", help="skip the column collapse and sliding-block legs")
     ap.add_argument("--adjoint-steps", type=int, default=400)
     ap.add_argument("--no-ensemble", action="store_true")
@@ -545,7 +546,7 @@ def main():
         out["configs"] = [config_leg("collapse_2d", args.steps, stream),
                           config_leg("collapse_3d", args.steps, stream, dense=True),
                           config_leg("sliding_block_30", args.steps, stream, dense=True)]
-    if not args.no_resolution and args.workload == "landslide":
+    if not (args.no_resolution or args.no_dense) and args.workload == "landslide":
         log("bench: landslide at dx = 4 m and 2 m")
         out["resolution"] = [resolution_leg(h, args.steps, stream) for h in (4, 2)]
     if not args.no_adjoint:
