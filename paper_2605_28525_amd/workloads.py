@@ -293,7 +293,7 @@ def sliding_block(theta_deg: float, seed: int = 21, dx: float = 0.02, block_cell
     Coulomb friction mu = tan 15 deg.  The block, 0.2 x 0.1 x 0.1 m (10x5x5 cells
     of dx along slope, across and normal), holds 8 particles per dx^3, stratified-
     jittered in the slope's own frame, the lowest ones within dx/2 above the plane;
-    its upslope face starts 0.1 m downslope of x = 0 measured along the plane.
+    its upslope face starts 0.18 m down the plane from its x = 0 edge.
     ``meta``: the downslope unit vector and the slope angle."""
     th = np.deg2rad(theta_deg)
     rng = np.random.default_rng(seed)
