@@ -236,6 +236,21 @@ int mpm_active_count(mpm_ctx* ctx, void* stream, int* n_blocks, int* n_touched);
  * ensemble packing (instance in bits 57-62, m = 19, bias 2^18). */
 int mpm_get_active(mpm_ctx* ctx, uint64_t* keys, uint64_t* masks, int capacity, void* stream);
 
+/* Scan-based construction of the same active set (Algorithms 1-4: block mask
+ * over the bounding box of the particles' owner blocks, grown by one block on
+ * each upper side, then an exclusive scan of the flags and compaction), an
+ * alternative to the hash table of Algorithms 5-6 for checking and comparing
+ * the two.  Bins p->x itself; independent of any earlier build and leaves the
+ * context's own active set untouched.  Writes the Eq. 22 keys and node masks
+ * (same formats as mpm_get_active) of the first min(*n_blocks, capacity)
+ * blocks, in x-fastest order of the box, to the caller's device arrays keys[]
+ * and masks[] (may be NULL when capacity is 0), and the number of active blocks
+ * to the host int *n_blocks.  Synchronous (reads the box back; allocates and
+ * frees its scratch, about 24 bytes per block of the box).  One simulation
+ * only: MPM_ERR_ARG for an ensemble context or bad arguments. */
+int mpm_scan_active(mpm_ctx* ctx, const mpm_particles* p, uint64_t* keys, uint64_t* masks, int capacity,
+                    int* n_blocks, void* stream);
+
 /* Copies the compact grid, 4 floats per node, blocks 0..min(n_blocks,
  * capacity)-1 in Phi order, nodes in l(n) order within a block: after mpm_p2g
  * (p_x, p_y, p_z, m); after mpm_grid_update (v_x, v_y, v_z, m) (2D: z = 0).

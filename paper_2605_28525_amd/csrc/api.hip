@@ -903,6 +903,13 @@ int mpm_get_active(mpm_ctx* c, uint64_t* keys, uint64_t* masks, int capacity, vo
     return hip_status(launch_copy_active(c->P, keys, masks, capacity, (hipStream_t)stream));
 }
 
+int mpm_scan_active(mpm_ctx* c, const mpm_particles* p, uint64_t* keys, uint64_t* masks, int capacity,
+                    int* n_blocks, void* stream) {
+    if (!c || !n_blocks || capacity < 0 || (capacity > 0 && (!keys || !masks))) return MPM_ERR_ARG;
+    if (c->P.n_inst > 1 || !particles_ok(c, p, false)) return MPM_ERR_ARG;
+    return hip_status(launch_scan_active(c->P, p->x, p->n, keys, masks, capacity, n_blocks, (hipStream_t)stream));
+}
+
 int mpm_get_grid(mpm_ctx* c, float* out, int capacity_blocks, void* stream) {
     if (!c || !out || capacity_blocks < 0) return MPM_ERR_ARG;
     if (!c->built) return MPM_ERR_STATE;

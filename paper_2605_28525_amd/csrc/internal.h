@@ -322,6 +322,8 @@ __device__ __forceinline__ void tile_offset(const unsigned* __restrict__ partial
 hipError_t scan_exclusive(const unsigned* in, unsigned* out, int n, const int* n_dev, unsigned* partials,
                           unsigned* total_out, hipStream_t s);
 int scan_partials_size(int n);
+hipError_t launch_scan_active(const DevParams& P, const float* x, int n, uint64_t* keys_out, uint64_t* masks_out,
+                              int cap, int* n_blocks, hipStream_t s);
 
 hipError_t radix_sort(const uint32_t* keys_in, uint32_t* k0, uint32_t* k1, uint32_t* v0, uint32_t* v1, int n,
                       int key_bits, unsigned* hist, unsigned* partials, uint32_t** keys_out, uint32_t** vals_out,

@@ -95,6 +95,7 @@ _SIGS = {
     "mpm_clear_status": (c_int, [_PCTX, c_void_p]),
     "mpm_active_count": (c_int, [_PCTX, c_void_p, POINTER(c_int), POINTER(c_int)]),
     "mpm_get_active": (c_int, [_PCTX, c_void_p, c_void_p, c_int, c_void_p]),
+    "mpm_scan_active": (c_int, [_PCTX, POINTER(mpm_particles), c_void_p, c_void_p, c_int, POINTER(c_int), c_void_p]),
     "mpm_get_grid": (c_int, [_PCTX, c_void_p, c_int, c_void_p]),
     "mpm_get_order": (c_int, [_PCTX, c_void_p, c_int, c_void_p]),
     "mpm_set_material": (c_int, [_PCTX, c_float, c_float, c_float, c_float]),
@@ -204,6 +205,16 @@ def mpm_active_count(ctx, stream=None):
 def mpm_get_active(ctx, keys, masks, capacity: int, stream=None):
     _check(lib.mpm_get_active(ctx, c_void_p(keys.data_ptr()), c_void_p(masks.data_ptr()), int(capacity),
                               _stream(stream)), "mpm_get_active")
+
+
+def mpm_scan_active(ctx, particles, keys, masks, capacity: int, stream=None) -> int:
+    """Scan-based active set of `particles` (keys and masks written to the first
+    min(count, capacity) entries of the device tensors); returns the count."""
+    nb = c_int(0)
+    _check(lib.mpm_scan_active(ctx, ctypes.byref(particles), c_void_p(keys.data_ptr() if capacity else 0),
+                               c_void_p(masks.data_ptr() if capacity else 0), int(capacity), ctypes.byref(nb),
+                               _stream(stream)), "mpm_scan_active")
+    return nb.value
 
 
 def mpm_get_grid(ctx, out, capacity_blocks: int, stream=None):
