@@ -336,6 +336,27 @@ def resolution_leg(h, steps, stream):
     return out
 
 
+def scan_builder_timing(sim, stream, hash_build_ms, reps=5):
+    """The scan-based active set (`mpm_scan_active`: binning, bounding box read
+    back, block mask, scan, compaction, with its own scratch allocation) on the
+    live state, host wall time per synchronous call, beside the hash build's
+    phase time (binning, re-sort, hash insertion, compaction, neighbour tables
+    and work items)."""
+    import time
+    import torch
+    from paper_2605_28525_amd import mpm as M
+    dummy = torch.empty(1, dtype=torch.int64, device="cuda")
+    n_scan = M.mpm_scan_active(sim.ctx, sim.a.view(), dummy, dummy, 0, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        M.mpm_scan_active(sim.ctx, sim.a.view(), dummy, dummy, 0, stream)
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    nb, _ = M.mpm_active_count(sim.ctx)
+    return {"ms_per_call": ms, "active_blocks": n_scan, "hash_active_blocks": nb,
+            "hash_build_ms": hash_build_ms}
+
+
 def time_graph(sim, steps, stream):
     """The same step replayed from a HIP graph of two captured steps
     (`mpm_graph_capture`), timed with events around `steps` // 2 replays;
@@ -520,6 +541,8 @@ def main():
         "active_blocks": nb,
         "active_fraction": n_slot / n_dense_nodes,
     }
+    if not args.no_dense and args.workload == "landslide":
+        out["scan_builder"] = scan_builder_timing(sim, stream, ph["build"])
     sim.close()
     del sim
     torch.cuda.empty_cache()
