@@ -11,7 +11,8 @@ Modules
                   conditions, G2P with APIC, Hencky elasticity and a
                   Drucker-Prager return map), all in float64.
 ``sparse``        the active-node set, its block-level layout, the local node
-                  index and the packed 64-bit block key.
-``hashmodel``     a sequential model of the hash-based block insertion with
-                  overflow and rebuild, used to pin the semantics of that path.
+                  index, the packed 64-bit block key and the sparsity ratio.
+``hashmodel``     the table a set of block keys occupies under linear probing,
+                  with the overflow rule and the doubling rebuild, used to pin
+                  the semantics of the hash-based construction.
 """

@@ -10,6 +10,7 @@
   (Algorithms 1 and 5, final step).
 * The packed key of Eq. 22 with m = 21 bits per coordinate and bias 2^20
   (Methods 3.3); in 2D the two coordinates fill the lower 2m bits.
+* The sparsity ratio of Eq. 1 (Results 2.2).
 """
 from __future__ import annotations
 
@@ -91,6 +92,34 @@ def active_blocks_and_masks(x: np.ndarray, p):
     return keys[order], masks[order]
 
 
-def sparsity_ratio(n_dense: int, n_active_per_step) -> float:
-    """Eq. 1: r_active = min_t n_dense / n_active(t)."""
-    return float(min(n_dense / a for a in n_active_per_step))
+def active_blocks_and_masks_by_cells(x: np.ndarray, p):
+    """The result of active_blocks_and_masks for large particle sets.  A depends
+    only on the set of distinct base nodes, so those are found first (as linear
+    node codes over the grid), then the union of their stencils."""
+    b = base_node(x, p.dx)
+    check_domain(b, p)
+    shape = tuple(p.nodes)
+    cells = np.unique(np.ravel_multi_index(tuple(b.T), shape))
+    ub = np.stack(np.unravel_index(cells, shape), axis=1)
+    offs = np.array(stencil_offsets(x.shape[1]))
+    nodes = (ub[:, None, :] + offs[None, :, :]).reshape(-1, x.shape[1])
+    codes = np.unique(np.ravel_multi_index(tuple(nodes.T), shape))
+    blocks, masks = block_masks(np.stack(np.unravel_index(codes, shape), axis=1).astype(np.int64))
+    keys = pack_key(blocks)
+    order = np.argsort(keys, kind="stable")
+    return keys[order], masks[order]
+
+
+def n_active_nodes(x: np.ndarray, p) -> int:
+    """n_active of Eq. 1 at one instant: the number of nodes in A."""
+    return int(len(active_nodes(x, p)))
+
+
+def sparsity_ratio(positions_over_time, p) -> float:
+    """Eq. 1: r_active = min over t of n_dense / n_active(t), where n_dense is
+    the number of nodes of the dense background grid (the potential domain,
+    cells + 1 nodes per axis) and n_active(t) the number of active nodes at
+    time t.  ``positions_over_time`` holds one (N, d) position array per
+    sampled instant."""
+    n_dense = int(np.prod(p.nodes))
+    return float(min(n_dense / n_active_nodes(x, p) for x in positions_over_time))

@@ -145,6 +145,19 @@ def test_block_masks_brute_force():
     assert got == ref
 
 
+@pytest.mark.parametrize("name", ["tiny_3d", "collapse_2d", "landslide_crop"])
+def test_active_set_by_cells_equals_direct(name):
+    # the large-input form (distinct base nodes first) gives the same blocks and
+    # masks as the direct union of every particle's stencil
+    w = {"tiny_3d": lambda: wl.tiny_3d(n=48, ties=True), "collapse_2d": wl.collapse_2d,
+         "landslide_crop": wl.landslide_crop}[name]()
+    x = w.x.T.astype(np.float64)
+    p = om.Params.from_workload(w)
+    k1, m1 = osp.active_blocks_and_masks(x, p)
+    k2, m2 = osp.active_blocks_and_masks_by_cells(x, p)
+    assert np.array_equal(k1, k2) and np.array_equal(m1, m2)
+
+
 def test_local_index_and_floor_for_negative_nodes():
     n = np.array([[-1, -4, -5], [0, 3, 4], [7, -8, 2]])
     assert np.array_equal(osp.block_of(n), [[-1, -1, -2], [0, 0, 1], [1, -2, 0]])
@@ -525,20 +538,111 @@ def test_elastic_bar_wave_period():
 
 
 # ---------------------------------------------------------------------------
-# sequential hash model: overflow and rebuild keep the block set
+# hash model: block set, linear probing, overflow and the doubling rebuild
 def test_hash_model_rebuild_keeps_block_set():
     w = wl.tiny_3d(n=40)
     x = w.x.T.astype(np.float64)
     p = P(3, dx=w.dx, cells=(16, 16, 16))
     keys_ref, _ = osp.active_blocks_and_masks(x, p)
+    K = len(keys_ref)
     t, rebuilds = ohm.build(x, w.dx, H=8, block_capacity=4)
-    assert rebuilds >= 2
-    assert sorted(t.active_block_keys) == sorted(int(k) for k in keys_ref)
-    assert t.count == len(keys_ref)
-    for s, k in enumerate(t.keys):
-        if k != ohm.EMPTY:
-            assert t.active_block_keys[t.vals[s]] == k
-    # a probe limit of one slot overflows on the first collision
-    t1 = ohm.BlockHash(64, 1000, n_probe=1)
-    t1.insert_particles(x, w.dx)
-    assert t1.overflow
+    # the stored keys are the active blocks computed from the node set
+    assert sorted(t.slot) == sorted(int(k) for k in keys_ref)
+    # doubling stops at the first capacity 4 * 2^r that holds every key
+    r = 0
+    while 4 << r < K:
+        r += 1
+    assert rebuilds == r >= 2
+    assert t.capacity == 4 << r and t.H == 8 << r
+    # one key per slot; Phi a bijection onto [0, K)
+    assert len(set(t.slot.values())) == K
+    assert sorted(t.compact_index().values()) == list(range(K))
+    # linear probing: every slot from a key's home slot up to its own is taken
+    taken = set(t.slot.values())
+    for k, s in t.slot.items():
+        h = ohm.home_slot(k, t.H)
+        j = h
+        while j != s:
+            assert j in taken
+            j = (j + 1) & (t.H - 1)
+        assert t.probes[k] == ((s - h) & (t.H - 1)) + 1
+
+
+def test_hash_model_slots_are_order_free_and_probe_limit_overflows():
+    rng = np.random.default_rng(3)
+    keys = {int(k) for k in rng.integers(0, 1 << 62, size=300)}
+    a = ohm.HashModel(keys, 512, 1000)
+    # the occupied slots do not depend on the insertion order: placing the
+    # keys one by one in a random order fills the same slots
+    occ = set()
+    for k in rng.permutation(sorted(keys)):
+        s = ohm.home_slot(int(k), 512)
+        while s in occ:
+            s = (s + 1) & 511
+        occ.add(s)
+    assert occ == set(a.slot.values())
+    assert not a.overflow
+    # more keys than the table, than the capacity, or a probe limit of one
+    # with a collision: overflow
+    assert ohm.HashModel(keys, 256, 1000).overflow
+    assert ohm.HashModel(keys, 512, 299).overflow
+    homes = [ohm.home_slot(k, 512) for k in keys]
+    assert len(set(homes)) < len(homes)  # the key set has collisions
+    assert ohm.HashModel(keys, 512, 1000, n_probe=1).overflow
+
+
+# ---------------------------------------------------------------------------
+# sparsity ratio (Eq. 1) and the domain check
+def test_sparsity_ratio():
+    d, dx = 3, 0.25
+    p = P(d, dx=dx, cells=(20, 16, 12))
+    n_dense = 21 * 17 * 13
+    # one particle off the half-cell ties touches its 3^3 stencil
+    one = np.array([[2.01, 2.02, 1.03]])
+    assert osp.n_active_nodes(one, p) == 27
+    # a cluster inside one cell, and the same particles split into two far
+    # clusters: 27 and 54 active nodes; the ratio takes the fuller instant
+    rng = np.random.default_rng(1)
+    c = 2.0 + rng.uniform(0.13, 0.37, (6, 3))   # base node 8 on every axis
+    split = c.copy()
+    split[3:, 0] += 2.0
+    assert osp.n_active_nodes(c, p) == 27
+    assert osp.n_active_nodes(split, p) == 54
+    r = osp.sparsity_ratio([c, split, c], p)
+    assert r == n_dense / 54
+    assert osp.sparsity_ratio([c], p) == n_dense / 27
+    # against brute-force enumeration of node/particle pairs
+    w = wl.tiny_3d(n=24)
+    x = w.x.T.astype(np.float64)
+    pt = P(3, dx=w.dx, cells=(16, 16, 16))
+    stencil, _ = _brute_active(x, w.dx, (17,) * 3)
+    assert osp.sparsity_ratio([x], pt) == 17 ** 3 / len(stencil)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_check_domain_edges(d):
+    cells = (12, 10, 8)[:d]
+    p = P(d, dx=0.5, cells=cells)
+    for a in range(d):
+        ok = np.full((1, d), 2)
+        ok[0, a] = cells[a] - 2          # stencil reaches node `cells`, the last node
+        om.check_domain(ok, p)
+        om.check_domain(np.zeros((1, d), np.int64), p)
+        bad = ok.copy()
+        bad[0, a] += 1                    # one node past the grid
+        with pytest.raises(om.DomainError):
+            om.check_domain(bad, p)
+        neg = np.full((1, d), 2)
+        neg[0, a] = -1
+        with pytest.raises(om.DomainError):
+            om.check_domain(neg, p)
+    # through positions: base node floor(x/dx - 1/2)
+    x_hi = np.full((1, d), 2.0)
+    x_hi[0, 0] = (cells[0] - 2 + 0.5) * 0.5      # base cells - 2, on the tie
+    om.p2g({"x": x_hi, "v": np.zeros((1, d)), "C": np.zeros((1, d, d)),
+            "tau": np.zeros((1, d, d))}, p)
+    x_out = x_hi.copy()
+    x_out[0, 0] = (cells[0] - 1 + 0.5) * 0.5
+    with pytest.raises(om.DomainError):
+        om.p2g({"x": x_out, "v": np.zeros((1, d)), "C": np.zeros((1, d, d)),
+                "tau": np.zeros((1, d, d))}, p)
