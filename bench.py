@@ -54,6 +54,14 @@ def parse():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=200)
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time the oracle on the whole 2D collapse (200 steps), the 1/8-volume 3D "
+                         "collapse (20 steps) and one 2D collapse per host core at once (minutes of CPU time)")
+    ap.add_argument("--no-builders", action="store_true",
+                    help="skip the hash vs scan-based build comparison")
+    ap.add_argument("--late-steps", default="1000,2500,5000",
+                    help="comma-separated steps from the release at which the landslide is timed again "
+                         "(sparse and dense); empty to skip")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of this many MiB (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -126,7 +134,7 @@ def adjoint_ratio(steps, checkpoint=50):
         v0 = torch.from_numpy(wl.calibration_target_velocity(n, seed=1003)).cuda()
         # warm-up (code objects, allocator)
         final = roll.run_forward(v0, w.E, w.friction_deg)
-        roll.backward(final, torch.zeros_like(final.x))
+        roll.backward(roll.checkpoints, final.id, torch.zeros_like(final.x), w.E, w.friction_deg)
         torch.cuda.synchronize()
         fwds, bwds = [], []
         for _ in range(3):  # median of three rollouts
@@ -135,7 +143,7 @@ def adjoint_ratio(steps, checkpoint=50):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             x_bar = (final.x - final.x.mean()) / n
-            gE, gphi, gv0 = roll.backward(final, x_bar)
+            gE, gphi, gv0 = roll.backward(roll.checkpoints, final.id, x_bar, w.E, w.friction_deg)
             torch.cuda.synchronize()
             t2 = time.perf_counter()
             fwds.append(t1 - t0)
@@ -336,25 +344,86 @@ def resolution_leg(h, steps, stream):
     return out
 
 
-def scan_builder_timing(sim, stream, hash_build_ms, reps=5):
-    """The scan-based active set (`mpm_scan_active`: binning, bounding box read
-    back, block mask, scan, compaction, with its own scratch allocation) on the
-    live state, host wall time per synchronous call, beside the hash build's
-    phase time (binning, re-sort, hash insertion, compaction, neighbour tables
-    and work items)."""
-    import time
+def copy_state(dst, src):
+    """Device copy of src's current particle state (ids included) into dst.a."""
+    dst.a.copy_(src.a)
+    dst.a.id.copy_(src.a.id)
+
+
+def builder_leg(w, src, cap, steps, stream):
+    """The active-node construction compared at equal footing on the live
+    state of `src`: the hash build (Algorithms 5-6) and the scan-based build
+    (Algorithms 1-4), both sorting from scratch every step, plus the default
+    hash build with the incremental re-sort (the headline).  Whole steps
+    through mpm_step and the build phase alone, events on the stream, median
+    of three runs of `steps` steps each; and the scan-based active-set query
+    (mpm_scan_active, synchronous) per call."""
     import torch
     from paper_2605_28525_amd import mpm as M
+    out = {"steps": steps}
     dummy = torch.empty(1, dtype=torch.int64, device="cuda")
-    n_scan = M.mpm_scan_active(sim.ctx, sim.a.view(), dummy, dummy, 0, stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        M.mpm_scan_active(sim.ctx, sim.a.view(), dummy, dummy, 0, stream)
-    ms = 1e3 * (time.perf_counter() - t0) / reps
-    nb, _ = M.mpm_active_count(sim.ctx)
-    return {"ms_per_call": ms, "active_blocks": n_scan, "hash_active_blocks": nb,
-            "hash_build_ms": hash_build_ms}
+    for name, flags in (("hash_resort", 0), ("hash_full_sort", M.MPM_FLAG_FULL_SORT),
+                        ("scan_full_sort", M.MPM_FLAG_SCAN_BUILD)):
+        sim = M.Simulation(w, block_capacity=cap, flags=flags)
+        try:
+            copy_state(sim, src)
+            sim.step(2, stream=stream)
+            whole = [time_steps(sim, steps, stream, phases=False)[0] for _ in range(3)]
+            _, ph = time_steps(sim, steps, stream)
+            rc, flags_ = sim.status()
+            if rc != 0:
+                raise SystemExit(f"builder leg {name}: device status {rc} flags={flags_}")
+            rec = {"ms_per_step": 1e3 * float(np.median(whole)) / steps, "build_ms": ph["build"],
+                   "active_blocks": M.mpm_active_count(sim.ctx)[0]}
+            if flags == M.MPM_FLAG_SCAN_BUILD:
+                M.mpm_scan_active(sim.ctx, sim.a.view(), dummy, dummy, 0, stream)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(5):
+                    M.mpm_scan_active(sim.ctx, sim.a.view(), dummy, dummy, 0, stream)
+                rec["query_ms_per_call"] = 1e3 * (time.perf_counter() - t0) / 5
+            out[name] = rec
+        finally:
+            sim.close()
+            del sim
+            torch.cuda.empty_cache()
+    out["scan_over_hash_step"] = out["scan_full_sort"]["ms_per_step"] / out["hash_full_sort"]["ms_per_step"]
+    out["scan_over_hash_build"] = out["scan_full_sort"]["build_ms"] / out["hash_full_sort"]["build_ms"]
+    return out
+
+
+def late_state_leg(sim, simd, steps_done, targets, steps, dense_steps, stream):
+    """The run continued from the headline state to each step in `targets`
+    (counted from the release): there, `steps` sparse steps timed three times
+    (median), the active blocks, and the dense step on a copy of that state.
+    Returns (records, steps_done)."""
+    from paper_2605_28525_amd import mpm as M
+    recs = []
+    for tgt in targets:
+        if tgt > steps_done:
+            sim.step(tgt - steps_done, stream=stream)
+            steps_done = tgt
+        runs = [time_steps(sim, steps, stream, phases=False)[0] for _ in range(3)]
+        steps_done += 3 * steps
+        rc, flags = sim.status()
+        if rc != 0:
+            raise SystemExit(f"late state {tgt}: device status {rc} flags={flags}")
+        nb, nt = M.mpm_active_count(sim.ctx)
+        ms = 1e3 * float(np.median(runs)) / steps
+        rec = {"step": tgt, "ms_per_step": ms, "value": sim.a.n * 1e3 / ms, "active_blocks": nb,
+               "runs_ms_per_step": [1e3 * r / steps for r in runs]}
+        if simd is not None:
+            copy_state(simd, sim)
+            td, _ = time_steps(simd, dense_steps, stream, phases=False)
+            rc, flags = simd.status()
+            if rc != 0:
+                raise SystemExit(f"late state {tgt} dense: device status {rc} flags={flags}")
+            rec["dense_ms_per_step"] = 1e3 * td / dense_steps
+            rec["speedup_vs_dense"] = rec["dense_ms_per_step"] / ms
+        log(f"bench: step {tgt}: {ms:.3f} ms/step, {nb} active blocks"
+            + (f", dense {rec['dense_ms_per_step']:.2f} ms" if simd is not None else ""))
+        recs.append(rec)
+    return recs, steps_done
 
 
 def time_graph(sim, steps, stream):
@@ -376,6 +445,11 @@ def time_graph(sim, steps, stream):
     finally:
         M.mpm_graph_release(sim.ctx)
     return e0.elapsed_time(e1) / 1e3 / (2 * reps)
+
+
+def graph_steps(steps):
+    """Steps that time_graph advances the state by."""
+    return 2 * (max(1, steps // 2) + 1)
 
 
 def measured_copy_gbs(mib=2048, reps=5):
@@ -419,33 +493,115 @@ def measured_traffic(kernel, workload, digest):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(w_name, budget_s):
-    """FP64 oracle on a bounded sample of the workload, single thread."""
+def all_src_digest():
+    names = sorted(f for f in os.listdir(os.path.join(ROOT, "paper_2605_28525_amd", "csrc"))
+                   if f.endswith((".hip", ".h")))
+    return src_digest(*names)
+
+
+def profile_counters(workload, digest_unused=None):
+    """Per-step counter figures from a committed rocprofv3 summary
+    (profiles/counters_<workload>.json: VALU busy fraction of the transfer
+    kernels, the HBM traffic of one whole step and of its sort / re-sort
+    kernels), used only if it was taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", f"counters_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("src_digest") != all_src_digest():
+        return None
+    rec = dict(rec)
+    rec.pop("src_digest", None)
+    return rec
+
+
+def host_info():
+    """CPU model, core counts and the BLAS thread pools numpy would use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    info = {"cpu_model": model, "cpu_count": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+    try:
+        from threadpoolctl import threadpool_info
+        info["blas"] = [{"api": t.get("internal_api"), "threads": t.get("num_threads")} for t in threadpool_info()]
+    except Exception:  # pragma: no cover
+        info["blas"] = None
+    return info
+
+
+def _oracle_steps(name, steps):
+    """Runs the FP64 oracle `steps` steps of a workload on one thread; returns
+    (particles, seconds).  Top-level so that spawned worker processes can run it."""
+    from threadpoolctl import threadpool_limits
     from oracle import mpm as om
     from paper_2605_28525_amd import workloads as wl
-    try:
-        from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(1)
-    except Exception:  # pragma: no cover
-        limiter = None
+    w = {"collapse_2d": wl.collapse_2d, "collapse_3d_1of8": lambda: wl.collapse_3d(scale=2),
+         "landslide_window": wl.landslide_crop}[name]()
+    with threadpool_limits(1):
+        p = om.Params.from_workload(w)
+        st = om.state_from_soa(w.state(), w.dim)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st = om.step(st, p)
+        return w.n, time.perf_counter() - t0
+
+
+def cpu_baseline(w_name, budget_s):
+    """FP64 oracle on a bounded sample of the workload, single thread."""
+    from threadpoolctl import threadpool_limits
+    from oracle import mpm as om
+    from paper_2605_28525_amd import workloads as wl
     if w_name == "landslide":
         w = wl.landslide_crop()
         sample = "landslide window 64x64x256 cells (same terrain, dx = 1 m), 16,384 particles"
     else:
         w = wl.collapse_3d(scale=2)
         sample = "3D collapse at 1/8 volume, 262,144 particles"
-    p = om.Params.from_workload(w)
-    st = om.state_from_soa(w.state(), w.dim)
-    steps = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        st = om.step(st, p)
-        steps += 1
-    dt = time.perf_counter() - t0
-    if limiter is not None:
-        limiter.unregister() if hasattr(limiter, "unregister") else None
+    with threadpool_limits(1):
+        p = om.Params.from_workload(w)
+        st = om.state_from_soa(w.state(), w.dim)
+        steps = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            st = om.step(st, p)
+            steps += 1
+        dt = time.perf_counter() - t0
+    host = host_info()
     return {"value": w.n * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sample}, {steps} steps in {dt:.1f} s, float64 numpy, 1 of {os.cpu_count()} host cores"}
+            "sample": f"{sample}, {steps} steps in {dt:.1f} s, float64 numpy, one thread "
+                      f"(1 of {host['affinity']} usable host cores)",
+            "host": host}
+
+
+def cpu_full_runs():
+    """The oracle on whole configurations: the 2D collapse over its 200 steps,
+    the 1/8-volume 3D collapse over 20 steps (one thread each), and the 2D
+    collapse run by one process per usable core at once (aggregate rate)."""
+    import multiprocessing as mp
+    out = {}
+    n, t = _oracle_steps("collapse_2d", 200)
+    out["collapse_2d_200_steps"] = {"particles": n, "seconds": t, "value": n * 200 / t}
+    log(f"bench: oracle collapse_2d 200 steps {t:.1f} s")
+    n, t = _oracle_steps("collapse_3d_1of8", 20)
+    out["collapse_3d_1of8_20_steps"] = {"particles": n, "seconds": t, "value": n * 20 / t}
+    log(f"bench: oracle collapse_3d 1/8 20 steps {t:.1f} s")
+    procs = min(16, len(os.sched_getaffinity(0)))
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(procs) as pool:
+        res = pool.starmap(_oracle_steps, [("collapse_2d", 50)] * procs)
+    wall = time.perf_counter() - t0
+    out["collapse_2d_aggregate"] = {"processes": procs, "steps_each": 50,
+                                    "value": sum(r[0] * 50 for r in res) / wall, "wall_seconds": wall}
+    out["host"] = host_info()
+    return out
 
 
 def main():
@@ -474,36 +630,53 @@ def main():
     cap = args.block_capacity or (1 << 18 if args.workload == "landslide" else 1 << 16)
     sim, sparse_bytes = device_bytes_of(lambda: M.Simulation(w, block_capacity=cap))
     log("bench: warmup")
+    steps_done = 0
     if args.warmup:
         sim.step(args.warmup, stream=stream)
+        steps_done += args.warmup
     rc, flags = sim.status()
     if rc != 0:
         raise SystemExit(f"device status after warmup: {rc} flags={flags}")
     tuning = None
     if not args.no_autotune:
+        # leaves the state unchanged
         chosen = M.mpm_autotune(sim.ctx, sim.a.view(), sim.b.view(), stream)
         tuning = dict(zip(("chunk", "g2p_block", "p2g_workgroups", "g2p_workgroups"), chosen))
         log(f"bench: autotune -> {tuning}")
     nb, nt = M.mpm_active_count(sim.ctx)
     log(f"bench: timed {args.steps} steps (active blocks {nb})")
-    t, ph = time_steps(sim, args.steps, stream)
+    # the headline: exactly K steps through mpm_step (one call), then the same
+    # twice more for the spread
+    t, _ = time_steps(sim, args.steps, stream, phases=False)
+    runs = [t] + [time_steps(sim, args.steps, stream, phases=False)[0] for _ in range(2)]
+    steps_done += 3 * args.steps
     rc, flags = sim.status()
     if rc != 0:
         raise SystemExit(f"device status after timing: {rc} flags={flags}")
+    # a separate instrumented run: events between the four calls of each step
+    _, ph = time_steps(sim, args.steps, stream)
+    steps_done += args.steps
     t_graph = time_graph(sim, args.steps, stream)
+    steps_done += graph_steps(args.steps)
     rc, flags = sim.status()
     if rc != 0:
         raise SystemExit(f"device status after graph replays: {rc} flags={flags}")
-    log(f"bench: eager {1e3 * t / args.steps:.3f} ms/step, graph replay {1e3 * t_graph:.3f} ms/step")
+    log(f"bench: {1e3 * t / args.steps:.3f} ms/step (runs "
+        f"{', '.join(f'{1e3 * r / args.steps:.3f}' for r in runs)}), graph replay {1e3 * t_graph:.3f} ms/step")
     value = n * args.steps / t
     ms_per_step = 1e3 * t / args.steps
     nb, nt = M.mpm_active_count(sim.ctx)
     npb = 4 ** d
     n_slot = nb * npb
     n_dense_nodes = int(np.prod([c + 1 for c in w.cells[:d]]))
-    # algorithmic bytes (counted once per field per kernel of the dataflow)
-    g2p_bytes = n * (4 * d + 4 * d * d + 4 + 4 * (d + d + d * d + d * d + (3 if d == 2 else 6)) + 8) + 16 * n_slot
-    p2g_bytes = n * (4 * (d + d + d * d + (3 if d == 2 else 6)) + 4) + 16 * n_slot
+    n_tau = 3 if d == 2 else 6
+    # algorithmic bytes per launch, counted once per field the method needs:
+    # G2P reads x, F and the particle's source index and the nodal velocity of
+    # each active node slot, and writes x, v, C, F, tau; P2G reads x, v, C, tau
+    # and the index and writes mass and momentum of each slot
+    g2p_bytes = n * (4 * d + 4 * d * d + 4 + 4 * (d + d + d * d + d * d + n_tau)) + 4 * d * n_slot
+    g2p_id_bytes = 8 * n   # the optional particle id read and written beside the state
+    p2g_bytes = n * (4 * (d + d + d * d + n_tau) + 4) + 16 * n_slot
     kernels = {"g2p": (g2p_bytes, ph["g2p"]), "p2g": (p2g_bytes, ph["p2g"])}
     dom = max(kernels, key=lambda k: kernels[k][1])
     dom_bytes, dom_ms = kernels[dom]
@@ -528,24 +701,33 @@ def main():
         "config": {"workload": w.name, "particles": n, "cells": list(w.cells[:d]), "dx_m": w.dx,
                    "block": "4^3", "grid": "sparse"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "bytes_per_launch": dom_bytes, "ms_per_launch": dom_ms,
+                     "time_source": "HIP events around the single-kernel mpm_g2p / mpm_p2g call"},
+        "runs_ms_per_step": [1e3 * r / args.steps for r in runs],
+        "median_ms_per_step": 1e3 * float(np.median(runs)) / args.steps,
         "phases_ms": ph,
+        "g2p_id_carry_bytes": g2p_id_bytes,
         "graph": {"ms_per_step": 1e3 * t_graph, "value": n / t_graph},
         "tuning": tuning,
         "build_ms_per_step": ph["build"],
         "build_roofline_frac": build_bytes / (ph["build"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "step_bytes_model": step_bytes,
         "step_roofline_frac": step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         # against the bytes a step with G2P and the next P2G fused would move (192 B per particle)
         "fused_bound_roofline_frac": 192.0 * n / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "measured_copy_GBps": measured_copy_gbs(),
         "active_blocks": nb,
+        "block_capacity": cap,
         "active_fraction": n_slot / n_dense_nodes,
     }
-    if not args.no_dense and args.workload == "landslide":
-        out["scan_builder"] = scan_builder_timing(sim, stream, ph["build"])
-    sim.close()
-    del sim
-    torch.cuda.empty_cache()
+    counters = profile_counters(args.workload, digest)
+    if counters:
+        out["counters"] = counters
+    if not args.no_builders and args.workload == "landslide":
+        log("bench: hash and scan-based builds")
+        out["builders"] = builder_leg(w, sim, cap, args.steps, stream)
+    simd = None
     if not args.no_dense:
         log("bench: dense baseline")
         simd, dense_bytes = device_bytes_of(lambda: M.Simulation(w, grid_mode=M.MPM_GRID_DENSE))
@@ -561,9 +743,16 @@ def main():
         # device memory, particle arrays included (the same in both)
         out["memory"] = {"sparse_bytes": sparse_bytes, "dense_bytes": dense_bytes,
                          "reduction": dense_bytes / sparse_bytes}
+    if args.late_steps and args.workload == "landslide":
+        log("bench: the run continued to later states")
+        targets = [int(v) for v in args.late_steps.split(",") if v]
+        out["late_states"], steps_done = late_state_leg(sim, simd, steps_done, targets, 20, 5, stream)
+    if simd is not None:
         simd.close()
         del simd
-        torch.cuda.empty_cache()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
     if not args.no_configs:
         log("bench: 2D and 3D column collapse")
         out["configs"] = [config_leg("collapse_2d", args.steps, stream),
@@ -583,6 +772,9 @@ def main():
     if not args.no_cpu:
         log("bench: cpu baseline")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
+    if args.cpu_full:
+        log("bench: oracle on whole configurations")
+        out["cpu_full"] = cpu_full_runs()
     print(json.dumps(out), flush=True)
 
 

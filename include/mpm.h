@@ -104,6 +104,26 @@ typedef struct mpm_ctx mpm_ctx;
                                     particles are contiguous with base cells
                                     ascending; block order and the order of movers
                                     inside a cell differ between the two. */
+#define MPM_FLAG_DETERMINISTIC_ORDER 8
+                                 /* Phi in ascending order of the Eq. 22 block key
+                                    (lexicographic (i, j, k), instance first in an
+                                    ensemble) instead of hash-slot order, and the
+                                    particle order a fixed function of the input
+                                    order (every build sorts from scratch, as with
+                                    MPM_FLAG_FULL_SORT).  Two runs from the same
+                                    input then give the same Phi and bit-identical
+                                    grids and particles.  Sparse grid only. */
+#define MPM_FLAG_SCAN_BUILD  16  /* mpm_sparse_build constructs the active set by the
+                                    scan-based method (Methods 3.2, Algorithms 1-4)
+                                    instead of the hash table: a block mask over the
+                                    bounding box of the owner blocks (grown by one
+                                    block upward), an exclusive scan of its flags
+                                    and compaction (Eq. 18), all on the device.
+                                    Every build sorts from scratch; Phi comes out in
+                                    ascending key order.  Allocates at create a mask
+                                    domain for every block of the potential grid
+                                    (24 bytes per block).  Sparse grid, one
+                                    simulation, no MPM_FLAG_ADJOINT. */
 
 /* Material and time step of one instance of an ensemble (see n_instances). */
 typedef struct mpm_instance {
@@ -212,7 +232,11 @@ int mpm_g2p(mpm_ctx* ctx, const mpm_particles* in, const mpm_particles* out, voi
 
 /* n_steps explicit steps ping-ponging between a and b: step 0 reads a and
  * writes b, step 1 reads b and writes a, ...  The final state is in a when
- * n_steps is even and in b when it is odd. */
+ * n_steps is even and in b when it is odd.  Between two steps of one call,
+ * G2P also bins the positions it writes (the float64 arithmetic of the build's
+ * binning on the same float32 values), so the next build skips its binning
+ * pass; the results are those of the four calls made one after the other
+ * (contexts with MPM_FLAG_ADJOINT bin in every build). */
 int mpm_step(mpm_ctx* ctx, const mpm_particles* a, const mpm_particles* b, int n_steps, void* stream);
 
 /* Synchronises `stream` and returns the sticky MPM_FLAG_* word in *flags;
@@ -236,18 +260,19 @@ int mpm_active_count(mpm_ctx* ctx, void* stream, int* n_blocks, int* n_touched);
  * ensemble packing (instance in bits 57-62, m = 19, bias 2^18). */
 int mpm_get_active(mpm_ctx* ctx, uint64_t* keys, uint64_t* masks, int capacity, void* stream);
 
-/* Scan-based construction of the same active set (Algorithms 1-4: block mask
- * over the bounding box of the particles' owner blocks, grown by one block on
- * each upper side, then an exclusive scan of the flags and compaction), an
- * alternative to the hash table of Algorithms 5-6 for checking and comparing
- * the two.  Bins p->x itself; independent of any earlier build and leaves the
- * context's own active set untouched.  Writes the Eq. 22 keys and node masks
- * (same formats as mpm_get_active) of the first min(*n_blocks, capacity)
- * blocks, in x-fastest order of the box, to the caller's device arrays keys[]
- * and masks[] (may be NULL when capacity is 0), and the number of active blocks
- * to the host int *n_blocks.  Synchronous (reads the box back; allocates and
- * frees its scratch, about 24 bytes per block of the box).  One simulation
- * only: MPM_ERR_ARG for an ensemble context or bad arguments. */
+/* Scan-based construction of the same active set (Methods 3.2, Algorithms
+ * 1-4: block mask over the bounding box of the particles' owner blocks, grown
+ * by one block on each upper side, then an exclusive scan of the flags and
+ * compaction), for checking the active set or comparing the two
+ * constructions.  Bins p->x itself; independent of any earlier build and
+ * leaves the context's build tables untouched.  Writes the Eq. 22 keys and
+ * node masks (same formats as mpm_get_active) of the first
+ * min(*n_blocks, capacity) blocks, in ascending key order, to the caller's
+ * device arrays keys[] and masks[] (may be NULL when capacity is 0), and the
+ * number of active blocks to the host int *n_blocks.  Synchronises `stream`.
+ * Uses the mask-domain scratch of a context created with MPM_FLAG_SCAN_BUILD
+ * (MPM_ERR_STATE otherwise; nothing is allocated).  MPM_ERR_ARG for an
+ * ensemble context or bad arguments. */
 int mpm_scan_active(mpm_ctx* ctx, const mpm_particles* p, uint64_t* keys, uint64_t* masks, int capacity,
                     int* n_blocks, void* stream);
 

@@ -69,22 +69,28 @@ class Rollout:
         self._bufs = [a, b]
         return a
 
-    def backward(self, final: "M.ParticleSet", x_bar: torch.Tensor):
-        """x_bar: dL/dx of `final` (same order).  Returns (dL/dE, dL/dphi, dL/dv0)."""
+    def backward(self, checkpoints, final_ids: torch.Tensor, x_bar: torch.Tensor, E: float, phi: float):
+        """x_bar: dL/dx of the final state of the forward pass that kept
+        `checkpoints` (same order as `final_ids`).  The material of that pass is
+        set again, so other forward passes on this Rollout in between do not
+        change the result.  Returns (dL/dE, dL/dphi, dL/dv0)."""
+        if len(checkpoints) != (self.steps + self.K - 1) // self.K:
+            raise ValueError("checkpoint list does not cover the rollout")
+        self.set_material(E, phi)
         self.param_bar.zero_()
-        bar_ids = final.id.clone()
+        bar_ids = final_ids.clone()
         bar, spare = self._bars
         for key in ("v", "C", "F", "tau"):
             getattr(bar, key).zero_()
         bar.x.copy_(x_bar)
         while len(self._pool) < self.K + 1:
             self._pool.append(M.ParticleSet(self.dim, self.n, self.device, zero=False))
-        nseg = len(self.checkpoints)
+        nseg = len(checkpoints)
         for si in range(nseg - 1, -1, -1):
             s0 = si * self.K
             k = min(self.K, self.steps - s0)
             states = self._pool[:k + 1]
-            states[0].copy_(self.checkpoints[si])
+            states[0].copy_(checkpoints[si])
             views = [st.view() for st in states]
             M.mpm_tape_forward(self.ctx, views)
             # align the incoming adjoint with the recomputed end state by id
@@ -111,7 +117,11 @@ class _RolloutFn(torch.autograd.Function):
     def forward(ctx, E, phi, v0, roll: Rollout):
         final = roll.run_forward(v0.detach(), float(E), float(phi))
         ctx.roll = roll
-        ctx.final = final
+        # run_forward allocates a fresh checkpoint list every call and the final
+        # state lives in buffers the next forward pass overwrites: keep the list,
+        # the ids and the material of this pass, not the buffers
+        ctx.checkpoints = roll.checkpoints
+        ctx.material = (float(E), float(phi))
         ctx.ids = final.id.clone()
         # positions returned in the caller's particle order
         inv = torch.empty_like(ctx.ids, dtype=torch.long)
@@ -124,7 +134,7 @@ class _RolloutFn(torch.autograd.Function):
         roll = ctx.roll
         # grad_x is in caller order; bring it to the final state's order
         x_bar = grad_x[:, ctx.ids.long()].contiguous()
-        gE, gphi, gv0 = roll.backward(ctx.final, x_bar)
+        gE, gphi, gv0 = roll.backward(ctx.checkpoints, ctx.ids, x_bar, *ctx.material)
         dev = grad_x.device
         return (torch.tensor(gE, dtype=torch.float64, device=dev), torch.tensor(gphi, dtype=torch.float64, device=dev),
                 gv0, None)

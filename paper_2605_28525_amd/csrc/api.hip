@@ -74,6 +74,15 @@ struct mpm_ctx {
     uint32_t* order = nullptr;
     uint32_t* skeys = nullptr;
     uint32_t* osrc = nullptr;  // G2P output position -> input index (the spare sort value buffer)
+    // scan-based construction (MPM_FLAG_SCAN_BUILD): mask-domain scratch for
+    // every block of the potential domain, allocated at create
+    bool scan_build = false;
+    void* sb_mem = nullptr;
+    int* sb_seg = nullptr;
+    SbScratch sb{};
+    // ascending-key Phi order (MPM_FLAG_DETERMINISTIC_ORDER, hash builds)
+    bool det_order = false;
+    DetTables det{};
     // Reverse-mode tape: for each step of a recorded segment, what its adjoint
     // reads from the step's build and transfers (block and work tables, both
     // grids, counters, sorted keys and order).
@@ -141,6 +150,16 @@ void free_capacity_buffers(mpm_ctx* c) {
     dfree(c->nh_cnt);
     dfree(c->nh_idx);
     dfree(c->nh_owner);
+    dfree(c->det.keys);
+    dfree(c->det.mask);
+    dfree(c->det.start);
+    dfree(c->det.count);
+    dfree(c->det.slot);
+    for (int j = 0; j < 2; ++j) {
+        dfree(c->det.k[j]);
+        dfree(c->det.v[j]);
+    }
+    dfree(c->det.hist);
     c->seg_valid = false;
 }
 
@@ -174,6 +193,9 @@ void free_all(mpm_ctx* c) {
     dfree(c->adj_scratch);
     dfree(c->inst);
     dfree(c->ctr);
+    if (c->sb_mem) (void)hipFree(c->sb_mem);
+    c->sb_mem = nullptr;
+    dfree(c->sb_seg);
 }
 
 void release_graph(mpm_ctx* c) {
@@ -292,17 +314,35 @@ int alloc_capacity_buffers(mpm_ctx* c) {
     const size_t cap = (size_t)c->block_cap;
     // room for the smallest work-item size mpm_set_tuning accepts
     c->work_cap = c->block_cap + c->max_particles / MIN_CHUNK + 1;
-    int scan_n = std::max({radix_hist_size(c->max_particles), (int)H, 2 * c->block_cap, 1});
-    const bool resort = !c->dense && !c->adjoint;  // the incremental re-sort serves these contexts
+    int scan_n = std::max({radix_hist_size(c->max_particles), radix_hist_size(c->block_cap), (int)H,
+                           2 * c->block_cap, 1});
+    // the incremental re-sort serves hash-built sparse contexts whose particle
+    // order may depend on earlier builds
+    const bool resort = !c->dense && !c->adjoint && !c->scan_build && !c->det_order;
+    const bool hashed = !c->dense && !c->scan_build;
     hipError_t e = hipSuccess;
-    if (!c->dense) {
+    if (hashed) {
         e = e ? e : dalloc(&c->h_keys, H);
         e = e ? e : dalloc(&c->h_mask, H);
         e = e ? e : dalloc(&c->h_vals, H);
         e = e ? e : dalloc(&c->h_start, H);
         e = e ? e : dalloc(&c->h_end, H);
+    }
+    if (!c->dense) {
         e = e ? e : dalloc(&c->b_keys, cap);
         e = e ? e : dalloc(&c->b_mask, cap);
+    }
+    if (hashed && c->det_order) {
+        e = e ? e : dalloc(&c->det.keys, cap);
+        e = e ? e : dalloc(&c->det.mask, cap);
+        e = e ? e : dalloc(&c->det.start, cap);
+        e = e ? e : dalloc(&c->det.count, cap);
+        e = e ? e : dalloc(&c->det.slot, cap);
+        for (int j = 0; j < 2; ++j) {
+            e = e ? e : dalloc(&c->det.k[j], cap);
+            e = e ? e : dalloc(&c->det.v[j], cap);
+        }
+        e = e ? e : dalloc(&c->det.hist, (size_t)radix_hist_size(c->block_cap));
     }
     e = e ? e : dalloc(&c->b_nbr, cap * NB);
     e = e ? e : dalloc(&c->b_start, cap);
@@ -365,10 +405,27 @@ bool particles_ok(const mpm_ctx* c, const mpm_particles* p, bool need_state) {
 
 int hip_status(hipError_t e) { return e == hipSuccess ? MPM_OK : MPM_ERR_HIP; }
 
+// Buffer that the binning of the next build writes (and that a G2P which
+// bins its output writes instead): the key buffer the sorted keys of the
+// current build do not occupy when the next build re-sorts incrementally, else
+// k1 (free once P2G has read the sorted keys).
+uint32_t* next_bin_buffer(const mpm_ctx* c, bool next_reuse) {
+    if (next_reuse) return c->skeys == c->k0 ? c->k1 : c->k0;
+    return c->k1;
+}
+
+// Whether a build of n particles following the last one re-sorts incrementally.
+bool would_reuse(const mpm_ctx* c, int n) {
+    return c->seg_valid && c->seg_n == n &&
+           !(c->prm.flags & (MPM_FLAG_FULL_SORT | MPM_FLAG_DETERMINISTIC_ORDER | MPM_FLAG_SCAN_BUILD));
+}
+
 // One build.  `reuse`: the previous build's segments, hash table and sorted
 // keys (same particle count) seed an incremental re-sort instead of the full
 // radix sort; the new sorted keys then take the previous ones' buffer.
-int build_once(mpm_ctx* c, const mpm_particles* p, hipStream_t s, bool reuse) {
+// `keys_ready`: the binning was already done (by the G2P that wrote these
+// positions) into next_bin_buffer(c, reuse).
+int build_once(mpm_ctx* c, const mpm_particles* p, hipStream_t s, bool reuse, bool keys_ready = false) {
     const int n = p->n;
     hipError_t e;
     uint32_t *ko = c->k1, *vo = c->v0;
@@ -376,15 +433,19 @@ int build_once(mpm_ctx* c, const mpm_particles* p, hipStream_t s, bool reuse) {
         uint32_t* prev = c->skeys;
         uint32_t* fresh = prev == c->k0 ? c->k1 : c->k0;
         vo = c->order;
-        e = launch_bin(c->P, p->x, p->inst, n, fresh, s);
-        if (e != hipSuccess) return MPM_ERR_HIP;
+        if (!keys_ready) {
+            e = launch_bin(c->P, p->x, p->inst, n, fresh, s);
+            if (e != hipSuccess) return MPM_ERR_HIP;
+        }
         uint32_t* spare = vo == c->v0 ? c->v1 : c->v0;  // the next osrc, free until P2G
         e = launch_resort(c->P, prev, fresh, prev, vo, spare, n, 1u << c->H_log2, c->partials, s);
         if (e != hipSuccess) return MPM_ERR_HIP;
         ko = prev;
     } else {
-        e = launch_bin(c->P, p->x, p->inst, n, c->k1, s);
-        if (e != hipSuccess) return MPM_ERR_HIP;
+        if (!keys_ready) {
+            e = launch_bin(c->P, p->x, p->inst, n, c->k1, s);
+            if (e != hipSuccess) return MPM_ERR_HIP;
+        }
         if (n > 0) {
             e = radix_sort(c->k1, c->k0, c->k1, c->v0, c->v1, n, c->key_bits, c->hist, c->partials, &ko, &vo, s);
             if (e != hipSuccess) return MPM_ERR_HIP;
@@ -395,8 +456,11 @@ int build_once(mpm_ctx* c, const mpm_particles* p, hipStream_t s, bool reuse) {
     c->osrc = vo == c->v0 ? c->v1 : c->v0;
     if (c->dense)
         e = launch_build_dense(c->P, ko, n, (int)c->n_blocks_total, c->partials, s);
+    else if (c->scan_build)
+        e = launch_build_scan(c->P, ko, n, c->sb, c->partials, s);
     else
-        e = launch_build_sparse(c->P, ko, n, 1u << c->H_log2, c->partials, s, reuse && n > 0);
+        e = launch_build_sparse(c->P, ko, n, 1u << c->H_log2, c->partials, s, reuse && n > 0,
+                                c->det_order ? &c->det : nullptr);
     return hip_status(e);
 }
 
@@ -443,6 +507,45 @@ int tape_args_ok(const mpm_ctx* c, const mpm_particles* states, int n_steps) {
     return MPM_OK;
 }
 
+}  // namespace
+
+namespace {
+// The build behind mpm_sparse_build; keys_ready as for build_once (a rebuild
+// after an overflow bins again).
+int sparse_build(mpm_ctx* c, const mpm_particles* p, hipStream_t s, bool keys_ready) {
+    const bool reuse = would_reuse(c, p->n);
+    c->built = false;
+    c->seg_valid = false;
+    int st = build_once(c, p, s, reuse, keys_ready);
+    if (st != MPM_OK) return st;
+    if (!c->dense && (c->prm.flags & MPM_FLAG_SYNC_REBUILD)) {
+        // Algorithm 7: on overflow, double the table (and the block capacity)
+        // and insert again until nothing overflows.
+        for (int attempt = 0; attempt < 24; ++attempt) {
+            DevCounters h;
+            st = read_counters(c, s, &h);
+            if (st != MPM_OK) return st;
+            if (!(h.flags & MPM_FLAG_OVERFLOW)) break;
+            const long long want = std::max<long long>(2ll * c->block_cap, (long long)h.n_touched);
+            c->block_cap = (int)std::min<long long>(want, c->n_blocks_total);
+            if (c->H_log2 < 30) ++c->H_log2;
+            while ((1ll << c->H_log2) < 2ll * c->block_cap && c->H_log2 < 30) ++c->H_log2;
+            st = alloc_capacity_buffers(c);
+            if (st != MPM_OK) return st;
+            unsigned keep = h.flags & ~MPM_FLAG_OVERFLOW;
+            if (hipMemcpyAsync(&c->ctr->flags, &keep, sizeof(unsigned), hipMemcpyHostToDevice, s) != hipSuccess)
+                return MPM_ERR_HIP;
+            if (hipStreamSynchronize(s) != hipSuccess) return MPM_ERR_HIP;
+            st = build_once(c, p, s, false);
+            if (st != MPM_OK) return st;
+        }
+    }
+    c->built = true;
+    c->built_n = p->n;
+    c->seg_valid = c->rs_in != nullptr;
+    c->seg_n = p->n;
+    return MPM_OK;
+}
 }  // namespace
 
 namespace mpmx {
@@ -495,6 +598,10 @@ int mpm_create(const mpm_params* q, mpm_ctx** out) {
         return MPM_ERR_ARG;
     if (q->n_instances < 0 || q->n_instances > MAX_INSTANCES) return MPM_ERR_ARG;
     const int n_inst = std::max(1, q->n_instances);
+    if ((q->flags & MPM_FLAG_DETERMINISTIC_ORDER) && q->grid_mode != MPM_GRID_SPARSE) return MPM_ERR_ARG;
+    if ((q->flags & MPM_FLAG_SCAN_BUILD) &&
+        (q->grid_mode != MPM_GRID_SPARSE || n_inst > 1 || (q->flags & MPM_FLAG_ADJOINT)))
+        return MPM_ERR_ARG;
     if (n_inst > 1) {
         if (!q->instances || q->grid_mode != MPM_GRID_SPARSE || (q->flags & MPM_FLAG_ADJOINT)) return MPM_ERR_ARG;
         for (int i = 0; i < n_inst; ++i) {
@@ -516,6 +623,8 @@ int mpm_create(const mpm_params* q, mpm_ctx** out) {
     c->dim = q->dim;
     c->dense = q->grid_mode == MPM_GRID_DENSE;
     c->adjoint = (q->flags & MPM_FLAG_ADJOINT) != 0;
+    c->scan_build = (q->flags & MPM_FLAG_SCAN_BUILD) != 0;
+    c->det_order = (q->flags & MPM_FLAG_DETERMINISTIC_ORDER) != 0;
     c->max_particles = q->max_particles;
     long long total = 1;
     for (int a = 0; a < 3; ++a) {
@@ -572,6 +681,12 @@ int mpm_create(const mpm_params* q, mpm_ctx** out) {
         if (e == hipSuccess) e = hipMemcpy(c->heightmap, q->heightmap, hn * sizeof(float), hipMemcpyHostToDevice);
     }
     if (e == hipSuccess) e = hipMemset(c->ctr, 0, sizeof(DevCounters));
+    if (e == hipSuccess && c->scan_build) {
+        const long long mm = c->n_blocks_total;
+        e = hipMalloc(&c->sb_mem, sb_scratch_bytes(mm));
+        if (e == hipSuccess) e = dalloc(&c->sb_seg, (size_t)(2 * mm));
+        if (e == hipSuccess) c->sb = sb_carve(c->sb_mem, mm, c->sb_seg, c->sb_seg + mm);
+    }
     if (e == hipSuccess && n_inst > 1) {
         InstMat host[MAX_INSTANCES];
         for (int i = 0; i < n_inst; ++i) {
@@ -624,41 +739,10 @@ int mpm_set_material(mpm_ctx* c, float E, float nu, float friction_deg, float dt
     return MPM_OK;
 }
 
+
 int mpm_sparse_build(mpm_ctx* c, const mpm_particles* p, void* stream) {
     if (!c || !particles_ok(c, p, false)) return MPM_ERR_ARG;
-    hipStream_t s = (hipStream_t)stream;
-    const bool reuse = c->seg_valid && c->seg_n == p->n && !(c->prm.flags & MPM_FLAG_FULL_SORT);
-    c->built = false;
-    c->seg_valid = false;
-    int st = build_once(c, p, s, reuse);
-    if (st != MPM_OK) return st;
-    if (!c->dense && (c->prm.flags & MPM_FLAG_SYNC_REBUILD)) {
-        // Algorithm 7: on overflow, double the table (and the block capacity)
-        // and insert again until nothing overflows.
-        for (int attempt = 0; attempt < 24; ++attempt) {
-            DevCounters h;
-            st = read_counters(c, s, &h);
-            if (st != MPM_OK) return st;
-            if (!(h.flags & MPM_FLAG_OVERFLOW)) break;
-            const long long want = std::max<long long>(2ll * c->block_cap, (long long)h.n_touched);
-            c->block_cap = (int)std::min<long long>(want, c->n_blocks_total);
-            if (c->H_log2 < 30) ++c->H_log2;
-            while ((1ll << c->H_log2) < 2ll * c->block_cap && c->H_log2 < 30) ++c->H_log2;
-            st = alloc_capacity_buffers(c);
-            if (st != MPM_OK) return st;
-            unsigned keep = h.flags & ~MPM_FLAG_OVERFLOW;
-            if (hipMemcpyAsync(&c->ctr->flags, &keep, sizeof(unsigned), hipMemcpyHostToDevice, s) != hipSuccess)
-                return MPM_ERR_HIP;
-            if (hipStreamSynchronize(s) != hipSuccess) return MPM_ERR_HIP;
-            st = build_once(c, p, s, false);
-            if (st != MPM_OK) return st;
-        }
-    }
-    c->built = true;
-    c->built_n = p->n;
-    c->seg_valid = !c->dense && !c->adjoint && c->rs_in != nullptr;
-    c->seg_n = p->n;
-    return MPM_OK;
+    return sparse_build(c, p, (hipStream_t)stream, false);
 }
 
 int mpm_p2g(mpm_ctx* c, const mpm_particles* p, void* stream) {
@@ -680,7 +764,10 @@ int mpm_grid_update(mpm_ctx* c, void* stream) {
     return hip_status(launch_grid_update(c->P, c->dense ? nodes : -1, (int)std::max(1ll, wgs), (hipStream_t)stream));
 }
 
-int mpm_g2p(mpm_ctx* c, const mpm_particles* in, const mpm_particles* out, void* stream) {
+namespace {
+// mpm_g2p; with keys_out, the kernel also bins the positions it writes (the
+// next build then skips its binning pass).
+int g2p_impl(mpm_ctx* c, const mpm_particles* in, const mpm_particles* out, hipStream_t s, uint32_t* keys_out) {
     if (!c || !particles_ok(c, in, false) || !out || out->n != in->n) return MPM_ERR_ARG;
     if (in->n > 0) {
         if (!out->x || !out->v || !out->C || !out->F || !out->tau || !in->F) return MPM_ERR_ARG;
@@ -691,18 +778,31 @@ int mpm_g2p(mpm_ctx* c, const mpm_particles* in, const mpm_particles* out, void*
     if (in->n == 0) return MPM_OK;
     const int wgs = std::min(c->g2p_wgs, c->work_cap);
     return hip_status(launch_g2p(c->P, in->x, in->F, in->id, in->inst, out->x, out->v, out->C, out->F, out->tau,
-                                 out->id, out->inst, in->n, c->osrc, c->g2p_block, wgs, (hipStream_t)stream));
+                                 out->id, out->inst, in->n, c->osrc, c->g2p_block, wgs, s, keys_out));
+}
+}  // namespace
+
+int mpm_g2p(mpm_ctx* c, const mpm_particles* in, const mpm_particles* out, void* stream) {
+    return g2p_impl(c, in, out, (hipStream_t)stream, nullptr);
 }
 
 int mpm_step(mpm_ctx* c, const mpm_particles* a, const mpm_particles* b, int n_steps, void* stream) {
     if (!c || !a || !b || n_steps < 0 || a->n != b->n) return MPM_ERR_ARG;
+    if (!particles_ok(c, a, true) || !particles_ok(c, b, true)) return MPM_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
     const mpm_particles* cur = a;
     const mpm_particles* nxt = b;
+    bool keys_ready = false;  // the previous step's G2P binned the positions it wrote
     for (int k = 0; k < n_steps; ++k) {
-        int st = mpm_sparse_build(c, cur, stream);
+        int st = sparse_build(c, cur, s, keys_ready);
         if (st == MPM_OK) st = mpm_p2g(c, cur, stream);
         if (st == MPM_OK) st = mpm_grid_update(c, stream);
-        if (st == MPM_OK) st = mpm_g2p(c, cur, nxt, stream);
+        // Between two steps of this call nothing else touches the positions,
+        // so G2P bins them as it writes them.  Not in reverse-mode contexts,
+        // whose tape records each build as mpm_sparse_build makes it.
+        keys_ready = k + 1 < n_steps && !c->adjoint && cur->n > 0;
+        uint32_t* keys_out = keys_ready ? next_bin_buffer(c, would_reuse(c, nxt->n)) : nullptr;
+        if (st == MPM_OK) st = g2p_impl(c, cur, nxt, s, keys_out);
         if (st != MPM_OK) return st;
         std::swap(cur, nxt);
     }
@@ -907,7 +1007,16 @@ int mpm_scan_active(mpm_ctx* c, const mpm_particles* p, uint64_t* keys, uint64_t
                     int* n_blocks, void* stream) {
     if (!c || !n_blocks || capacity < 0 || (capacity > 0 && (!keys || !masks))) return MPM_ERR_ARG;
     if (c->P.n_inst > 1 || !particles_ok(c, p, false)) return MPM_ERR_ARG;
-    return hip_status(launch_scan_active(c->P, p->x, p->n, keys, masks, capacity, n_blocks, (hipStream_t)stream));
+    *n_blocks = 0;
+    if (!c->sb_mem) return MPM_ERR_STATE;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_scan_active(c->P, p->x, p->n, c->sb, keys, masks, capacity, s);
+    SbBox box{};
+    if (e == hipSuccess) e = hipMemcpyAsync(&box, c->sb.box, sizeof(SbBox), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return MPM_ERR_HIP;
+    *n_blocks = (int)box.total;
+    return MPM_OK;
 }
 
 int mpm_get_grid(mpm_ctx* c, float* out, int capacity_blocks, void* stream) {

@@ -60,29 +60,7 @@ __global__ __launch_bounds__(WG) void k_bin(DevParams P, const float* __restrict
             bad |= MPM_FLAG_DOMAIN;
             in = (uint32_t)max(P.n_inst, 1) - 1;
         }
-        int b[3] = {0, 0, 0};
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            double f = floor(index_arg(xv[k][a], P.inv_dx));
-            if (!(f == f)) {
-                bad |= MPM_FLAG_NAN;
-                f = 0.0;
-            } else if (f < 0.0 || f + 2.0 > (double)P.cells[a]) {
-                bad |= MPM_FLAG_DOMAIN;
-                f = fmin(fmax(f, 0.0), (double)(P.cells[a] - 2));
-            }
-            b[a] = (int)f;
-        }
-        uint32_t bl, cell;
-        if (DIM == 3) {
-            bl = ((uint32_t)(b[2] >> 2) * (uint32_t)P.nblk[1] + (uint32_t)(b[1] >> 2)) * (uint32_t)P.nblk[0] +
-                 (uint32_t)(b[0] >> 2);
-            cell = (b[0] & 3) | ((b[1] & 3) << 2) | ((b[2] & 3) << 4);
-        } else {
-            bl = (uint32_t)(b[1] >> 2) * (uint32_t)P.nblk[0] + (uint32_t)(b[0] >> 2);
-            cell = (b[0] & 3) | ((b[1] & 3) << 2);
-        }
-        keys[i] = (in << (P.blk_bits + 2 * DIM)) | (bl << (2 * DIM)) | cell;
+        keys[i] = bin_key<DIM>(P, xv[k], in, &bad);
     }
     if (bad) raise_flag(P.ctr, bad);
 }
@@ -292,7 +270,7 @@ __global__ __launch_bounds__(WG) void k_compact_count(DevParams P, int H, unsign
 }
 
 __global__ __launch_bounds__(WG) void k_compact_write(DevParams P, int H, const unsigned* __restrict__ partials,
-                                                      int tiles) {
+                                                      int tiles, int* __restrict__ slot_of) {
     __shared__ unsigned lds[WG / 64];
     unsigned before, total;
     tile_offset(partials, blockIdx.x, tiles, lds, &before, &total);
@@ -319,6 +297,7 @@ __global__ __launch_bounds__(WG) void k_compact_write(DevParams P, int H, const 
             P.b_start[phi] = st;
             P.b_count[phi] = st >= 0 ? P.h_end[idx] - st : 0;
             P.h_vals[idx] = (int)phi;
+            if (slot_of) slot_of[phi] = idx;
         } else {
             P.h_vals[idx] = -1;
             over = true;
@@ -329,6 +308,40 @@ __global__ __launch_bounds__(WG) void k_compact_write(DevParams P, int H, const 
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         P.ctr->n_touched = total;
         P.ctr->nb = min((int)total, P.block_cap);
+    }
+}
+
+// Ascending-key order of Phi (MPM_FLAG_DETERMINISTIC_ORDER).  The compaction
+// wrote the block tables in slot order into the alternate arrays; the blocks
+// are sorted by their coordinates (instance, i, j, k), which is the order of
+// the Eq. 22 keys, and gathered into the block tables in that order.
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_det_keys(DevParams P, const uint64_t* __restrict__ alt_keys,
+                                                 uint32_t* __restrict__ rank_keys, uint32_t sentinel) {
+    const int nb = P.ctr->nb;
+    for (int b = blockIdx.x * WG + threadIdx.x; b < P.block_cap; b += gridDim.x * WG) {
+        uint32_t r = sentinel;
+        if (b < nb) {
+            int bc[3], inst;
+            unblock_key<DIM>(P, alt_keys[b], bc, &inst);
+            const uint32_t lin = DIM == 3 ? ((uint32_t)bc[0] * (uint32_t)P.nblk[1] + (uint32_t)bc[1]) *
+                                                    (uint32_t)P.nblk[2] + (uint32_t)bc[2]
+                                          : (uint32_t)bc[0] * (uint32_t)P.nblk[1] + (uint32_t)bc[1];
+            r = ((uint32_t)inst << P.blk_bits) | lin;
+        }
+        rank_keys[b] = r;
+    }
+}
+
+__global__ __launch_bounds__(WG) void k_det_apply(DevParams P, DetTables T, const uint32_t* __restrict__ sorted) {
+    const int nb = P.ctr->nb;
+    for (int r = blockIdx.x * WG + threadIdx.x; r < nb; r += gridDim.x * WG) {
+        const int b = (int)sorted[r];
+        P.b_keys[r] = T.keys[b];
+        P.b_mask[r] = T.mask[b];
+        P.b_start[r] = T.start[b];
+        P.b_count[r] = T.count[b];
+        P.h_vals[T.slot[b]] = r;
     }
 }
 
@@ -456,7 +469,7 @@ hipError_t launch_bin(const DevParams& P, const float* x, const uint32_t* inst, 
 }
 
 hipError_t launch_build_sparse(const DevParams& P, const uint32_t* skeys, int n, unsigned H, unsigned* partials,
-                               hipStream_t s, bool from_resort) {
+                               hipStream_t s, bool from_resort, const DetTables* det) {
     if (!from_resort) k_hash_clear<<<grid_for(H), WG, 0, s>>>(P, H);  // the re-sort's last pass clears it
     if (n > 0 && from_resort) {
         const int ge = grid_for(2ll * P.block_cap * 64, 16384);  // one wave per entry
@@ -472,18 +485,47 @@ hipError_t launch_build_sparse(const DevParams& P, const uint32_t* skeys, int n,
             k_hash_insert<2><<<(n + per_wg - 1) / per_wg, WG, 0, s>>>(P, skeys, n);
     }
     const int tiles = ((int)H + SCAN_TILE - 1) / SCAN_TILE;
-    k_compact_count<<<tiles, WG, 0, s>>>(P, (int)H, partials);
-    k_compact_write<<<tiles, WG, 0, s>>>(P, (int)H, partials, tiles);
     const int gb = grid_for(P.block_cap, 2048);
+    k_compact_count<<<tiles, WG, 0, s>>>(P, (int)H, partials);
+    if (det) {
+        // compaction in slot order into the alternate tables, then the blocks
+        // sorted by key and gathered into the block tables
+        DevParams Pa = P;
+        Pa.b_keys = det->keys;
+        Pa.b_mask = det->mask;
+        Pa.b_start = det->start;
+        Pa.b_count = det->count;
+        k_compact_write<<<tiles, WG, 0, s>>>(Pa, (int)H, partials, tiles, det->slot);
+        const int kb = P.blk_bits + (P.n_inst > 1 ? 6 : 0);
+        const uint32_t sentinel = kb >= 32 ? 0xFFFFFFFFu : ((1u << kb) - 1u);
+        if (P.dim == 3)
+            k_det_keys<3><<<gb, WG, 0, s>>>(P, det->keys, det->k[1], sentinel);
+        else
+            k_det_keys<2><<<gb, WG, 0, s>>>(P, det->keys, det->k[1], sentinel);
+        uint32_t *ko = nullptr, *vo = nullptr;
+        hipError_t e = radix_sort(det->k[1], det->k[0], det->k[1], det->v[0], det->v[1], P.block_cap, kb, det->hist,
+                                  partials, &ko, &vo, s);
+        if (e != hipSuccess) return e;
+        k_det_apply<<<gb, WG, 0, s>>>(P, *det, vo);
+    } else {
+        k_compact_write<<<tiles, WG, 0, s>>>(P, (int)H, partials, tiles, nullptr);
+    }
     if (P.dim == 3)
         k_block_setup<3><<<gb, WG, 0, s>>>(P);
     else
         k_block_setup<2><<<gb, WG, 0, s>>>(P);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // no grid clear: the second P2G pass writes every node of every active block
+    return launch_work_items(P, partials, s);
+}
+
+// Work items: exclusive scan of the per-block chunk counts, then the items.
+hipError_t launch_work_items(const DevParams& P, unsigned* partials, hipStream_t s) {
     hipError_t e = scan_exclusive(P.b_chunks, P.b_chunk_off, P.block_cap, &P.ctr->nb, partials,
                                   (unsigned*)&P.ctr->n_work, s);
     if (e != hipSuccess) return e;
-    k_work_write<<<gb, WG, 0, s>>>(P);
-    // no grid clear: the second P2G pass writes every node of every active block
+    k_work_write<<<grid_for(P.block_cap, 2048), WG, 0, s>>>(P);
     return hipGetLastError();
 }
 

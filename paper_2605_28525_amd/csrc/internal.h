@@ -200,6 +200,37 @@ __device__ __forceinline__ double index_arg(float x, double inv_dx) {
     return s - 0.5;
 }
 
+// Sort key of one particle (binning, a1): base node floor(x/dx - 1/2) per axis
+// in float64, clamped into the grid with MPM_FLAG_DOMAIN (MPM_FLAG_NAN for a
+// non-finite coordinate) ORed into *bad; key = instance << (block bits + 2d)
+// | linear owner block << 2d | local cell of the base node.
+template <int DIM>
+__device__ __forceinline__ uint32_t bin_key(const DevParams& P, const float* xv, uint32_t inst, unsigned* bad) {
+    int b[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        double f = floor(index_arg(xv[a], P.inv_dx));
+        if (!(f == f)) {
+            *bad |= MPM_FLAG_NAN;
+            f = 0.0;
+        } else if (f < 0.0 || f + 2.0 > (double)P.cells[a]) {
+            *bad |= MPM_FLAG_DOMAIN;
+            f = fmin(fmax(f, 0.0), (double)(P.cells[a] - 2));
+        }
+        b[a] = (int)f;
+    }
+    uint32_t bl, cell;
+    if (DIM == 3) {
+        bl = ((uint32_t)(b[2] >> 2) * (uint32_t)P.nblk[1] + (uint32_t)(b[1] >> 2)) * (uint32_t)P.nblk[0] +
+             (uint32_t)(b[0] >> 2);
+        cell = (b[0] & 3) | ((b[1] & 3) << 2) | ((b[2] & 3) << 4);
+    } else {
+        bl = (uint32_t)(b[1] >> 2) * (uint32_t)P.nblk[0] + (uint32_t)(b[0] >> 2);
+        cell = (b[0] & 3) | ((b[1] & 3) << 2);
+    }
+    return (inst << (P.blk_bits + 2 * DIM)) | (bl << (2 * DIM)) | cell;
+}
+
 template <int DIM>
 __device__ __forceinline__ void linear_to_block(const DevParams& P, uint32_t bl, int* bc) {
     bc[0] = (int)(bl % (uint32_t)P.nblk[0]);
@@ -317,13 +348,43 @@ __device__ __forceinline__ void tile_offset(const unsigned* __restrict__ partial
     wg_excl_scan(t, lds, total);
 }
 
+// Scan-based construction (scanbuild.hip): the mask domain (bounding box of the
+// owner blocks grown by one block on each upper side), written on the device.
+struct SbBox {
+    int lo[3], hi[3];  // owner-block bounds (lo = INT_MAX, hi = -1 while empty)
+    int ext[3];        // extents of the mask domain
+    int m;             // its volume in blocks (0: no particle, or above max_m)
+    int too_big;       // the volume exceeded max_m
+    unsigned total;    // active blocks (sum of the flags)
+    int pad[2];
+};
+
+// Scratch of the scan-based construction, carved from one allocation: box
+// header, occupancy (u64), flags and Phi (u32) for up to max_m blocks of the
+// domain, scan partials; owner segment bounds (step build only, may be null).
+struct SbScratch {
+    SbBox* box;
+    uint64_t* occ;
+    unsigned* flag;
+    unsigned* phi;
+    unsigned* partials;
+    int* seg_lo;
+    int* seg_hi;
+    long long max_m;
+};
+
 // ---------------------------------------------------------------------------
 // host-side launchers (each returns hipError_t of the launch)
 hipError_t scan_exclusive(const unsigned* in, unsigned* out, int n, const int* n_dev, unsigned* partials,
                           unsigned* total_out, hipStream_t s);
 int scan_partials_size(int n);
-hipError_t launch_scan_active(const DevParams& P, const float* x, int n, uint64_t* keys_out, uint64_t* masks_out,
-                              int cap, int* n_blocks, hipStream_t s);
+size_t sb_scratch_bytes(long long max_m);
+SbScratch sb_carve(void* base, long long max_m, int* seg_lo, int* seg_hi);
+hipError_t launch_scan_active(const DevParams& P, const float* x, int n, const SbScratch& S, uint64_t* keys_out,
+                              uint64_t* masks_out, int cap, hipStream_t s);
+hipError_t launch_build_scan(const DevParams& P, const uint32_t* skeys, int n, const SbScratch& S,
+                             unsigned* partials, hipStream_t s);
+hipError_t launch_work_items(const DevParams& P, unsigned* partials, hipStream_t s);
 
 hipError_t radix_sort(const uint32_t* keys_in, uint32_t* k0, uint32_t* k1, uint32_t* v0, uint32_t* v1, int n,
                       int key_bits, unsigned* hist, unsigned* partials, uint32_t** keys_out, uint32_t** vals_out,
@@ -334,8 +395,21 @@ hipError_t launch_bin(const DevParams& P, const float* x, const uint32_t* inst, 
 hipError_t launch_resort(const DevParams& P, uint32_t* keys_prev, const uint32_t* keys_new, uint32_t* keys_out,
                          uint32_t* vals_out, uint32_t* movers, int n, unsigned H, unsigned* partials, hipStream_t s);
 hipError_t launch_resort_init(const DevParams& P, unsigned H, hipStream_t s);
+// Buffers of the ascending-key Phi order (MPM_FLAG_DETERMINISTIC_ORDER): block
+// tables in slot order, the slot of each, and a radix sort of block_cap
+// entries (keys, values, histograms).
+struct DetTables {
+    uint64_t* keys;
+    uint64_t* mask;
+    int* start;
+    int* count;
+    int* slot;
+    uint32_t* k[2];
+    uint32_t* v[2];
+    unsigned* hist;
+};
 hipError_t launch_build_sparse(const DevParams& P, const uint32_t* skeys, int n, unsigned H, unsigned* partials,
-                               hipStream_t s, bool from_resort = false);
+                               hipStream_t s, bool from_resort = false, const DetTables* det = nullptr);
 hipError_t launch_build_dense(const DevParams& P, const uint32_t* skeys, int n, int n_blocks, unsigned* partials,
                               hipStream_t s);
 hipError_t launch_p2g(const DevParams& P, const float* x, const float* v, const float* C, const float* tau, int n,
@@ -344,7 +418,7 @@ hipError_t launch_grid_update(const DevParams& P, long long n_nodes_host, int gr
 hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, const uint32_t* id_in,
                       const uint32_t* inst_in, float* x_out, float* v_out, float* C_out, float* F_out, float* tau_out,
                       uint32_t* id_out, uint32_t* inst_out, int n, const uint32_t* osrc, int block_size,
-                      int grid_blocks, hipStream_t s);
+                      int grid_blocks, hipStream_t s, uint32_t* keys_out = nullptr);
 hipError_t launch_clear_flags(DevCounters* c, hipStream_t s);
 hipError_t launch_g2p_adj(const DevParams& P, const float* x, const float* F, const float* const* out_bar, float* x_bar,
                           float* F_bar, int n, const uint32_t* order, const uint32_t* skeys, int grid_blocks,

@@ -13,6 +13,9 @@ __global__ __launch_bounds__(WG) void k_scan_reduce(const unsigned* __restrict__
                                                     unsigned* __restrict__ partials) {
     __shared__ unsigned lds[WG / 64];
     const int nn = n_dev ? min(n, *n_dev) : n;
+    // tiles past the device count hold no values (k_scan_down reads only the
+    // partials of the tiles below it)
+    if (blockIdx.x > 0 && blockIdx.x * SCAN_TILE >= nn) return;
     const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
     unsigned s = 0;
 #pragma unroll
@@ -30,8 +33,13 @@ __global__ __launch_bounds__(WG) void k_scan_down(const unsigned* __restrict__ i
                                                   unsigned* total_out) {
     __shared__ unsigned lds[WG / 64];
     const int nn = n_dev ? min(n, *n_dev) : n;
+    // with a device count, only the tiles that hold values are scanned (the
+    // launch is sized for the host bound n); outputs at or past nn are not
+    // written then
+    const int live = n_dev ? max(1, min(tiles, (nn + SCAN_TILE - 1) / SCAN_TILE)) : tiles;
+    if (blockIdx.x >= live) return;
     unsigned before, total;
-    tile_offset(partials, blockIdx.x, tiles, lds, &before, &total);
+    tile_offset(partials, blockIdx.x, live, lds, &before, &total);
     if (blockIdx.x == 0 && threadIdx.x == 0 && total_out) *total_out = total;
     const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
     unsigned v[SCAN_ITEMS];
@@ -54,8 +62,10 @@ __global__ __launch_bounds__(WG) void k_scan_down(const unsigned* __restrict__ i
 
 int scan_partials_size(int n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
 
-// out[i] = sum_{j<i} in[j] for i < n (entries at or beyond the device count
-// *n_dev, if given, read as zero); *total_out (device) receives the sum.
+// out[i] = sum_{j<i} in[j] for i < n; with a device count *n_dev, for
+// i < min(n, *n_dev) (entries at or beyond it read as zero and outputs past the
+// last tile that holds values are left unwritten); *total_out (device)
+// receives the sum.
 hipError_t scan_exclusive(const unsigned* in, unsigned* out, int n, const int* n_dev, unsigned* partials,
                           unsigned* total_out, hipStream_t s) {
     if (n <= 0) return hipSuccess;

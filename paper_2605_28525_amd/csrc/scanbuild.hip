@@ -1,21 +1,34 @@
-// Scan-based active set (the paper's first construction, Algorithms 1-4, here on
-// the GPU): an alternative to the hash table of Algorithms 5-6 that yields the
-// same active blocks and node masks, used to check one against the other and
-// to compare their cost.
+// Scan-based active set (the paper's first construction, Methods 3.2 and
+// Algorithms 1-4, here on the GPU): the alternative to the hash table of
+// Algorithms 5-6.  It yields the same active blocks and node masks, with the
+// compact index Phi in ascending block-key order.
 //
+//   k_sb_reset  bounding-box accumulators <- empty;
 //   k_sb_bbox   bounding box of the owner blocks of all particles (wave min/max,
 //               one atomic per wave and axis);
-//   host        reads the box back; the mask domain is the box grown by one
-//               block on each upper side (the stencil spills only upward);
+//   k_sb_box    the mask domain: the box grown by one block on each upper side
+//               (a stencil spills only upward), its extents and volume m, all
+//               on the device (no host read-back);
+//   k_sb_zero   occupancy of the m blocks of the domain <- 0;
 //   k_sb_occ    per owner block, the 64-bit occupancy of its base cells (lanes
 //               of a wave with the same owner merged by ballot, one atomicOr);
-//   k_sb_mask   per block of the domain, its node mask: the OR over itself and
-//               its 2^d - 1 lower neighbours of the dilated occupancy (own part
-//               for itself, spill part for the neighbours), a gather with no
-//               atomics; flag = mask != 0;
+//               from sorted keys it also records each owner segment's first and
+//               one-past-last sorted position;
+//   k_sb_flag   per block of the domain: active iff the OR over itself and its
+//               2^d - 1 lower neighbours of the dilated occupancy (own part for
+//               itself, spill part for the neighbours) is non-zero, a gather
+//               with no atomics;
 //   scan        exclusive scan of the flags -> compact index (Eq. 18);
-//   k_sb_write  keys (Eq. 22) and masks of the flagged blocks, in the domain's
-//               x-fastest order.
+//   k_sb_write  keys (Eq. 22) and node masks of the flagged blocks, in the
+//               domain's order: i slowest, k fastest, which is ascending key
+//               order (Eq. 22 packs i highest);
+//   step build  (k_sb_write_blocks, k_sb_block_setup) the same into the
+//               context's block tables, owner segments, upper and lower
+//               neighbours looked up in the domain instead of the hash table.
+//
+// The scratch (accumulators, occupancy, flags, Phi, segment bounds, scan
+// partials) is passed in as an SbScratch: the context's own, allocated at
+// create for the whole potential domain, or a fixed static device array.
 #include <climits>
 
 #include "internal.h"
@@ -58,29 +71,56 @@ __device__ __forceinline__ uint64_t sb_node_mask(uint64_t occ, int d) {
     return sb_axis(o, 16, 0x000000000000FFFFull, (d >> 2) & 1);
 }
 
+// Owner block coordinates and base cell of particle i, from a sorted key or,
+// with x != nullptr, from its position (the binning arithmetic of k_bin: base
+// node floor(x/dx - 1/2) in float64, clamped into the grid).
 template <int DIM>
-__device__ __forceinline__ void sb_owner(const DevParams& P, uint32_t key, int* bc) {
-    const uint32_t bl = (key >> (2 * DIM)) & ((1u << P.blk_bits) - 1u);
-    bc[0] = (int)(bl % (uint32_t)P.nblk[0]);
-    const uint32_t r = bl / (uint32_t)P.nblk[0];
-    bc[1] = DIM == 3 ? (int)(r % (uint32_t)P.nblk[1]) : (int)r;
-    bc[2] = DIM == 3 ? (int)(r / (uint32_t)P.nblk[1]) : 0;
+__device__ __forceinline__ void sb_owner(const DevParams& P, const float* __restrict__ x,
+                                         const uint32_t* __restrict__ keys, int n, int i, int* bc, int* cell) {
+    if (x) {
+        int b[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            double f = floor(index_arg(x[(size_t)a * n + i], P.inv_dx));
+            if (!(f == f)) f = 0.0;
+            f = fmin(fmax(f, 0.0), (double)(P.cells[a] - 2));
+            b[a] = (int)f;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) bc[a] = b[a] >> 2;
+        *cell = DIM == 3 ? ((b[0] & 3) | ((b[1] & 3) << 2) | ((b[2] & 3) << 4)) : ((b[0] & 3) | ((b[1] & 3) << 2));
+        return;
+    }
+    const uint32_t k = keys[i];
+    linear_to_block<DIM>(P, (k >> (2 * DIM)) & ((1u << P.blk_bits) - 1u), bc);
+    *cell = (int)(k & ((1u << (2 * DIM)) - 1u));
 }
 
-__global__ __launch_bounds__(64) void k_sb_init(int* bb) {
+// Domain index of block coordinates c (box-relative), i slowest, k fastest.
+__device__ __forceinline__ long long sb_index(const SbBox& B, int c0, int c1, int c2) {
+    return ((long long)c0 * B.ext[1] + c1) * B.ext[2] + c2;
+}
+
+__global__ __launch_bounds__(64) void k_sb_reset(SbBox* box) {
     if (threadIdx.x < 3) {
-        bb[threadIdx.x] = INT_MAX;
-        bb[3 + threadIdx.x] = -1;
+        box->lo[threadIdx.x] = INT_MAX;
+        box->hi[threadIdx.x] = -1;
+        box->ext[threadIdx.x] = 0;
+    }
+    if (threadIdx.x == 0) {
+        box->m = 0;
+        box->too_big = 0;
+        box->total = 0u;
     }
 }
 
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_sb_bbox(DevParams P, const uint32_t* __restrict__ keys, int n,
-                                                int* __restrict__ bb) {
+__global__ __launch_bounds__(WG) void k_sb_bbox(DevParams P, const float* __restrict__ x,
+                                                const uint32_t* __restrict__ keys, int n, SbBox* box) {
     int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {-1, -1, -1};
     for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
-        int bc[3];
-        sb_owner<DIM>(P, keys[i], bc);
+        int bc[3], cell;
+        sb_owner<DIM>(P, x, keys, n, i, bc, &cell);
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
             lo[a] = min(lo[a], bc[a]);
@@ -98,184 +138,296 @@ __global__ __launch_bounds__(WG) void k_sb_bbox(DevParams P, const uint32_t* __r
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
             if (hi[a] >= 0) {
-                atomicMin(&bb[a], lo[a]);
-                atomicMax(&bb[3 + a], hi[a]);
+                atomicMin(&box->lo[a], lo[a]);
+                atomicMax(&box->hi[a], hi[a]);
             }
         }
     }
 }
 
-__global__ __launch_bounds__(WG) void k_sb_zero(uint64_t* __restrict__ a, long long m) {
-    for (long long i = (long long)blockIdx.x * WG + threadIdx.x; i < m; i += (long long)gridDim.x * WG) a[i] = 0ull;
-}
-
-struct SbBox {
-    int lo[3], ext[3];
-};
-
+// Extents of the mask domain; volume 0 when there is no particle or when it
+// exceeds max_m (then too_big is set and nothing further is done).
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_sb_occ(DevParams P, const uint32_t* __restrict__ keys, int n, SbBox B,
-                                               uint64_t* __restrict__ occ) {
-    constexpr int NC = 1 << (2 * DIM);
-    const int lane = __lane_id();
-    const int i = blockIdx.x * WG + threadIdx.x;
-    const bool valid = i < n;
-    uint32_t idx = 0xFFFFFFFFu;
-    uint64_t bit = 0ull;
-    if (valid) {
-        const uint32_t k = keys[i];
-        int bc[3];
-        sb_owner<DIM>(P, k, bc);
-        idx = (uint32_t)(bc[0] - B.lo[0]) +
-              (uint32_t)B.ext[0] * ((uint32_t)(bc[1] - B.lo[1]) + (uint32_t)B.ext[1] * (uint32_t)(bc[2] - B.lo[2]));
-        bit = 1ull << (k & (NC - 1));
-    }
-    unsigned long long pending = __ballot(valid);
-    while (pending) {  // one round per distinct owner block in the wave
-        const int leader = __ffsll((long long)pending) - 1;
-        const uint32_t own = (uint32_t)__shfl((int)idx, leader);
-        const bool mine = valid && idx == own;
-        const uint64_t m = wave_or64(mine ? bit : 0ull);
-        if (lane == leader) atomicOr((unsigned long long*)&occ[own], (unsigned long long)m);
-        pending &= ~__ballot(mine);
-    }
-}
-
-template <int DIM>
-__global__ __launch_bounds__(WG) void k_sb_mask(SbBox B, long long m, const uint64_t* __restrict__ occ,
-                                                uint64_t* __restrict__ mask, unsigned* __restrict__ flag) {
-    constexpr int NB = 1 << DIM;
-    for (long long t = (long long)blockIdx.x * WG + threadIdx.x; t < m; t += (long long)gridDim.x * WG) {
-        const int b0 = (int)(t % B.ext[0]);
-        const long long r = t / B.ext[0];
-        const int b1 = (int)(r % B.ext[1]);
-        const int b2 = (int)(r / B.ext[1]);
-        uint64_t acc = 0ull;
-#pragma unroll
-        for (int d = 0; d < NB; ++d) {
-            const int c0 = b0 - (d & 1), c1 = b1 - ((d >> 1) & 1), c2 = b2 - ((d >> 2) & 1);
-            if (c0 < 0 || c1 < 0 || c2 < 0) continue;
-            const uint64_t o = occ[(long long)c0 + (long long)B.ext[0] * (c1 + (long long)B.ext[1] * c2)];
-            if (o) acc |= sb_node_mask<DIM>(o, d);
+__global__ __launch_bounds__(64) void k_sb_box(DevParams P, SbBox* box, long long max_m) {
+    if (threadIdx.x != 0) return;
+    long long m = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (a >= DIM) {
+            box->lo[a] = 0;
+            box->ext[a] = 1;
+            continue;
         }
-        mask[t] = acc;
-        flag[t] = acc != 0ull ? 1u : 0u;
+        if (box->hi[a] < 0) {  // no particle
+            m = 0;
+            box->lo[a] = 0;
+            box->ext[a] = 0;
+            continue;
+        }
+        // owners lo..hi plus the upper neighbour, inside the potential domain
+        box->ext[a] = min(box->hi[a] + 1, P.nblk[a] - 1) - box->lo[a] + 1;
+        m *= box->ext[a];
+    }
+    if (m > max_m) {
+        box->too_big = 1;
+        m = 0;
+    }
+    box->m = (int)m;
+}
+
+__global__ __launch_bounds__(WG) void k_sb_zero(const SbBox* __restrict__ box, uint64_t* __restrict__ occ) {
+    const int m = box->m;
+    for (int t = blockIdx.x * WG + threadIdx.x; t < m; t += gridDim.x * WG) occ[t] = 0ull;
+}
+
+// Occupancy of each owner block's base cells; from sorted keys (x == nullptr)
+// also the first and one-past-last sorted position of each owner segment.
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_sb_occ(DevParams P, const float* __restrict__ x,
+                                               const uint32_t* __restrict__ keys, int n,
+                                               const SbBox* __restrict__ box, uint64_t* __restrict__ occ,
+                                               int* __restrict__ seg_lo, int* __restrict__ seg_hi) {
+    const SbBox B = *box;
+    if (B.m == 0) return;
+    const int lane = __lane_id();
+    for (int i0 = blockIdx.x * WG + (threadIdx.x & ~63); i0 < n; i0 += gridDim.x * WG) {
+        const int i = i0 + lane;
+        const bool valid = i < n;
+        long long idx = -1;
+        uint64_t bit = 0ull;
+        if (valid) {
+            int bc[3], cell;
+            sb_owner<DIM>(P, x, keys, n, i, bc, &cell);
+            idx = sb_index(B, bc[0] - B.lo[0], bc[1] - B.lo[1], bc[2] - B.lo[2]);
+            bit = 1ull << cell;
+            if (!x) {  // owner segment bounds of the sorted order
+                const uint32_t seg = keys[i] >> (2 * DIM);
+                if (i == 0 || (keys[i - 1] >> (2 * DIM)) != seg) seg_lo[idx] = i;
+                if (i == n - 1 || (keys[i + 1] >> (2 * DIM)) != seg) seg_hi[idx] = i + 1;
+            }
+        }
+        unsigned long long pending = __ballot(valid);
+        while (pending) {  // one round per distinct owner block in the wave
+            const int leader = __ffsll((long long)pending) - 1;
+            const long long own = __shfl(idx, leader);
+            const bool mine = valid && idx == own;
+            const uint64_t mk = wave_or64(mine ? bit : 0ull);
+            if (lane == leader) atomicOr((unsigned long long*)&occ[own], (unsigned long long)mk);
+            pending &= ~__ballot(mine);
+        }
     }
 }
 
+// Node mask of domain block (c0, c1, c2): its own dilated occupancy and the
+// spills of its lower neighbours.
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_sb_write(DevParams P, SbBox B, long long m, const uint64_t* __restrict__ mask,
+__device__ __forceinline__ uint64_t sb_mask_at(const SbBox& B, const uint64_t* __restrict__ occ, int c0, int c1,
+                                               int c2) {
+    constexpr int NB = 1 << DIM;
+    uint64_t acc = 0ull;
+#pragma unroll
+    for (int d = 0; d < NB; ++d) {
+        const int a0 = c0 - (d & 1), a1 = c1 - ((d >> 1) & 1), a2 = c2 - ((d >> 2) & 1);
+        if (a0 < 0 || a1 < 0 || a2 < 0) continue;
+        const uint64_t o = occ[sb_index(B, a0, a1, a2)];
+        if (o) acc |= sb_node_mask<DIM>(o, d);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ void sb_coords(const SbBox& B, int t, int* c) {
+    c[2] = t % B.ext[2];
+    const int r = t / B.ext[2];
+    c[1] = r % B.ext[1];
+    c[0] = r / B.ext[1];
+}
+
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_sb_flag(const SbBox* __restrict__ box, const uint64_t* __restrict__ occ,
+                                                unsigned* __restrict__ flag) {
+    const SbBox B = *box;
+    for (int t = blockIdx.x * WG + threadIdx.x; t < B.m; t += gridDim.x * WG) {
+        int c[3];
+        sb_coords(B, t, c);
+        flag[t] = sb_mask_at<DIM>(B, occ, c[0], c[1], c[2]) != 0ull ? 1u : 0u;
+    }
+}
+
+// Keys and masks of the flagged blocks into caller arrays (the first cap).
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_sb_write(DevParams P, const SbBox* __restrict__ box,
+                                                 const uint64_t* __restrict__ occ, const unsigned* __restrict__ flag,
                                                  const unsigned* __restrict__ phi, uint64_t* __restrict__ keys_out,
                                                  uint64_t* __restrict__ masks_out, int cap) {
-    for (long long t = (long long)blockIdx.x * WG + threadIdx.x; t < m; t += (long long)gridDim.x * WG) {
-        const uint64_t mk = mask[t];
-        if (mk == 0ull) continue;
+    const SbBox B = *box;
+    for (int t = blockIdx.x * WG + threadIdx.x; t < B.m; t += gridDim.x * WG) {
+        if (!flag[t]) continue;
         const unsigned p = phi[t];
         if (p >= (unsigned)cap) continue;
-        const int b0 = (int)(t % B.ext[0]);
-        const long long r = t / B.ext[0];
-        const int b1 = (int)(r % B.ext[1]);
-        const int b2 = (int)(r / B.ext[1]);
-        keys_out[p] = block_key<DIM>(P, B.lo[0] + b0, B.lo[1] + b1, B.lo[2] + b2, 0);
-        masks_out[p] = mk;
+        int c[3];
+        sb_coords(B, t, c);
+        keys_out[p] = block_key<DIM>(P, B.lo[0] + c[0], B.lo[1] + c[1], B.lo[2] + c[2], 0);
+        masks_out[p] = sb_mask_at<DIM>(B, occ, c[0], c[1], c[2]);
+    }
+}
+
+// Step build: the flagged blocks into the context's block tables in Phi order,
+// with their owner segments; the block count and the capacity check.
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_sb_write_blocks(DevParams P, const SbBox* __restrict__ box,
+                                                        const uint64_t* __restrict__ occ,
+                                                        const unsigned* __restrict__ flag,
+                                                        const unsigned* __restrict__ phi,
+                                                        const int* __restrict__ seg_lo,
+                                                        const int* __restrict__ seg_hi) {
+    const SbBox B = *box;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        P.ctr->n_touched = (int)B.total;
+        P.ctr->nb = min((int)B.total, P.block_cap);
+        P.ctr->n_work = 0;
+        if ((int)B.total > P.block_cap) raise_flag(P.ctr, MPM_FLAG_OVERFLOW);
+    }
+    for (int t = blockIdx.x * WG + threadIdx.x; t < B.m; t += gridDim.x * WG) {
+        if (!flag[t]) continue;
+        const unsigned p = phi[t];
+        if (p >= (unsigned)P.block_cap) continue;
+        int c[3];
+        sb_coords(B, t, c);
+        P.b_keys[p] = block_key<DIM>(P, B.lo[0] + c[0], B.lo[1] + c[1], B.lo[2] + c[2], 0);
+        P.b_mask[p] = sb_mask_at<DIM>(B, occ, c[0], c[1], c[2]);
+        const bool owns = occ[t] != 0ull;
+        const int st = owns ? seg_lo[t] : -1;
+        P.b_start[p] = st;
+        P.b_count[p] = owns ? seg_hi[t] - st : 0;
+    }
+}
+
+// Compact index of the domain block at box-relative c, -1 outside the domain
+// or inactive (or past the capacity).
+__device__ __forceinline__ int sb_phi_at(const DevParams& P, const SbBox& B, const unsigned* __restrict__ flag,
+                                         const unsigned* __restrict__ phi, int c0, int c1, int c2) {
+    if (c0 < 0 || c1 < 0 || c2 < 0 || c0 >= B.ext[0] || c1 >= B.ext[1] || c2 >= B.ext[2]) return -1;
+    const long long t = sb_index(B, c0, c1, c2);
+    if (!flag[t]) return -1;
+    const unsigned p = phi[t];
+    return p < (unsigned)P.block_cap ? (int)p : -1;
+}
+
+// Upper and lower neighbours (as k_block_setup, looked up in the domain) and
+// the chunk count of each block.
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_sb_block_setup(DevParams P, const SbBox* __restrict__ box,
+                                                       const unsigned* __restrict__ flag,
+                                                       const unsigned* __restrict__ phi) {
+    constexpr int NB = 1 << DIM;
+    const SbBox B = *box;
+    const int nb = P.ctr->nb;
+    for (int b = blockIdx.x * WG + threadIdx.x; b < nb; b += gridDim.x * WG) {
+        int bc[3], inst;
+        unblock_key<DIM>(P, P.b_keys[b], bc, &inst);
+        const int c0 = bc[0] - B.lo[0], c1 = bc[1] - B.lo[1], c2 = bc[2] - B.lo[2];
+        P.b_nbr[b * NB] = b;
+#pragma unroll
+        for (int d = 1; d < NB; ++d)
+            P.b_nbr[b * NB + d] = sb_phi_at(P, B, flag, phi, c0 + (d & 1), c1 + ((d >> 1) & 1), c2 + ((d >> 2) & 1));
+        if (P.b_lo) {
+            P.b_lo[b * NB] = P.b_count[b] > 0 ? b : -1;
+#pragma unroll
+            for (int d = 1; d < NB; ++d) {
+                const int lo = sb_phi_at(P, B, flag, phi, c0 - (d & 1), c1 - ((d >> 1) & 1), c2 - ((d >> 2) & 1));
+                P.b_lo[b * NB + d] = (lo >= 0 && P.b_count[lo] > 0) ? lo : -1;
+            }
+        }
+        P.b_chunks[b] = (unsigned)((P.b_count[b] + P.chunk - 1) / P.chunk);
     }
 }
 
 namespace {
-template <typename T>
-hipError_t sb_alloc(T** p, size_t count) {
-    *p = nullptr;
-    return hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
+int sb_grid(long long items, int cap_wgs) {
+    long long g = (items + WG - 1) / WG;
+    if (g < 1) g = 1;
+    if (g > cap_wgs) g = cap_wgs;
+    return (int)g;
 }
-template <typename T>
-void sb_free(T* p) {
-    if (p) (void)hipFree((void*)p);
+
+// Bounding box, domain, occupancy, flags and their scan: the part shared by
+// the query and the step build.  x != nullptr: bins the positions on the fly;
+// else reads sorted keys.
+hipError_t sb_mark(const DevParams& P, const float* x, const uint32_t* keys, int n, const SbScratch& S,
+                   hipStream_t s) {
+    k_sb_reset<<<1, 64, 0, s>>>(S.box);
+    const int gp = sb_grid(n, 4096);
+    const int gm = sb_grid(S.max_m, 8192);
+    if (P.dim == 3) {
+        if (n > 0) k_sb_bbox<3><<<gp, WG, 0, s>>>(P, x, keys, n, S.box);
+        k_sb_box<3><<<1, 64, 0, s>>>(P, S.box, S.max_m);
+        k_sb_zero<<<gm, WG, 0, s>>>(S.box, S.occ);
+        if (n > 0) k_sb_occ<3><<<gp, WG, 0, s>>>(P, x, keys, n, S.box, S.occ, S.seg_lo, S.seg_hi);
+        k_sb_flag<3><<<gm, WG, 0, s>>>(S.box, S.occ, S.flag);
+    } else {
+        if (n > 0) k_sb_bbox<2><<<gp, WG, 0, s>>>(P, x, keys, n, S.box);
+        k_sb_box<2><<<1, 64, 0, s>>>(P, S.box, S.max_m);
+        k_sb_zero<<<gm, WG, 0, s>>>(S.box, S.occ);
+        if (n > 0) k_sb_occ<2><<<gp, WG, 0, s>>>(P, x, keys, n, S.box, S.occ, S.seg_lo, S.seg_hi);
+        k_sb_flag<2><<<gm, WG, 0, s>>>(S.box, S.occ, S.flag);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return scan_exclusive(S.flag, S.phi, (int)S.max_m, &S.box->m, S.partials, &S.box->total, s);
 }
 }  // namespace
 
-// Synchronous: bins x into a scratch key array, reads the bounding box back,
-// allocates the mask domain, and returns the number of active blocks in
-// *n_blocks (the first min(*n_blocks, cap) are written).
-hipError_t launch_scan_active(const DevParams& P, const float* x, int n, uint64_t* keys_out, uint64_t* masks_out,
-                              int cap, int* n_blocks, hipStream_t s) {
-    *n_blocks = 0;
-    if (n == 0) return hipSuccess;
-    uint32_t* keys = nullptr;
-    int* bb = nullptr;
-    uint64_t *occ = nullptr, *mask = nullptr;
-    unsigned *flag = nullptr, *phi = nullptr, *partials = nullptr, *total = nullptr;
-    hipError_t e = sb_alloc(&keys, (size_t)n);
-    if (e == hipSuccess) e = sb_alloc(&bb, 8);
-    if (e == hipSuccess) e = launch_bin(P, x, nullptr, n, keys, s);
-    if (e == hipSuccess) {
-        k_sb_init<<<1, 64, 0, s>>>(bb);
-        const int g = std::min((n + WG - 1) / WG, 4096);
-        if (P.dim == 3)
-            k_sb_bbox<3><<<g, WG, 0, s>>>(P, keys, n, bb);
-        else
-            k_sb_bbox<2><<<g, WG, 0, s>>>(P, keys, n, bb);
-        e = hipGetLastError();
+size_t sb_scratch_bytes(long long max_m) {
+    // box header, occupancy (u64), flags and Phi (u32), scan partials; segment
+    // bounds (2 x i32) are added by the step build's owner
+    return 256 + (size_t)max_m * (8 + 4 + 4) + (size_t)scan_partials_size((int)max_m) * 4 + 256;
+}
+
+SbScratch sb_carve(void* base, long long max_m, int* seg_lo, int* seg_hi) {
+    SbScratch S{};
+    char* p = (char*)base;
+    S.box = (SbBox*)p;
+    p += 256;
+    S.occ = (uint64_t*)p;
+    p += (size_t)max_m * 8;
+    S.flag = (unsigned*)p;
+    p += (size_t)max_m * 4;
+    S.phi = (unsigned*)p;
+    p += (size_t)max_m * 4;
+    S.partials = (unsigned*)p;
+    S.max_m = max_m;
+    S.seg_lo = seg_lo;
+    S.seg_hi = seg_hi;
+    return S;
+}
+
+hipError_t launch_scan_active(const DevParams& P, const float* x, int n, const SbScratch& S, uint64_t* keys_out,
+                              uint64_t* masks_out, int cap, hipStream_t s) {
+    hipError_t e = sb_mark(P, x, nullptr, n, S, s);
+    if (e != hipSuccess || cap <= 0) return e;
+    const int gm = sb_grid(S.max_m, 8192);
+    if (P.dim == 3)
+        k_sb_write<3><<<gm, WG, 0, s>>>(P, S.box, S.occ, S.flag, S.phi, keys_out, masks_out, cap);
+    else
+        k_sb_write<2><<<gm, WG, 0, s>>>(P, S.box, S.occ, S.flag, S.phi, keys_out, masks_out, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_scan(const DevParams& P, const uint32_t* skeys, int n, const SbScratch& S,
+                             unsigned* partials, hipStream_t s) {
+    hipError_t e = sb_mark(P, nullptr, skeys, n, S, s);
+    if (e != hipSuccess) return e;
+    const int gm = sb_grid(S.max_m, 8192);
+    const int gb = sb_grid(P.block_cap, 2048);
+    if (P.dim == 3) {
+        k_sb_write_blocks<3><<<gm, WG, 0, s>>>(P, S.box, S.occ, S.flag, S.phi, S.seg_lo, S.seg_hi);
+        k_sb_block_setup<3><<<gb, WG, 0, s>>>(P, S.box, S.flag, S.phi);
+    } else {
+        k_sb_write_blocks<2><<<gm, WG, 0, s>>>(P, S.box, S.occ, S.flag, S.phi, S.seg_lo, S.seg_hi);
+        k_sb_block_setup<2><<<gb, WG, 0, s>>>(P, S.box, S.flag, S.phi);
     }
-    int hb[6] = {0, 0, 0, 0, 0, 0};
-    if (e == hipSuccess) e = hipMemcpyAsync(hb, bb, sizeof(hb), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    SbBox B{};
-    long long m = 0;
-    if (e == hipSuccess) {
-        m = 1;
-        for (int a = 0; a < 3; ++a) {
-            if (a >= P.dim) {
-                B.lo[a] = 0;
-                B.ext[a] = 1;
-                continue;
-            }
-            B.lo[a] = hb[a];
-            // owners lo..hi plus the upper neighbour, inside the potential domain
-            B.ext[a] = std::min(hb[3 + a] + 1, P.nblk[a] - 1) - hb[a] + 1;
-            m *= B.ext[a];
-        }
-        if (m <= 0 || m > (long long)INT_MAX) e = hipErrorInvalidValue;
-    }
-    if (e == hipSuccess) e = sb_alloc(&occ, (size_t)m);
-    if (e == hipSuccess) e = sb_alloc(&mask, (size_t)m);
-    if (e == hipSuccess) e = sb_alloc(&flag, (size_t)m);
-    if (e == hipSuccess) e = sb_alloc(&phi, (size_t)m);
-    if (e == hipSuccess) e = sb_alloc(&partials, (size_t)scan_partials_size((int)m));
-    if (e == hipSuccess) e = sb_alloc(&total, 1);
-    if (e == hipSuccess) {
-        const int gm = (int)std::min<long long>((m + WG - 1) / WG, 8192);
-        k_sb_zero<<<gm, WG, 0, s>>>(occ, m);
-        if (P.dim == 3) {
-            k_sb_occ<3><<<(n + WG - 1) / WG, WG, 0, s>>>(P, keys, n, B, occ);
-            k_sb_mask<3><<<gm, WG, 0, s>>>(B, m, occ, mask, flag);
-        } else {
-            k_sb_occ<2><<<(n + WG - 1) / WG, WG, 0, s>>>(P, keys, n, B, occ);
-            k_sb_mask<2><<<gm, WG, 0, s>>>(B, m, occ, mask, flag);
-        }
-        e = hipGetLastError();
-        if (e == hipSuccess) e = scan_exclusive(flag, phi, (int)m, nullptr, partials, total, s);
-        if (e == hipSuccess && cap > 0) {
-            if (P.dim == 3)
-                k_sb_write<3><<<gm, WG, 0, s>>>(P, B, m, mask, phi, keys_out, masks_out, cap);
-            else
-                k_sb_write<2><<<gm, WG, 0, s>>>(P, B, m, mask, phi, keys_out, masks_out, cap);
-            e = hipGetLastError();
-        }
-    }
-    unsigned count = 0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&count, total, sizeof(count), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e == hipSuccess) *n_blocks = (int)count;
-    (void)hipStreamSynchronize(s);
-    sb_free(keys);
-    sb_free(bb);
-    sb_free(occ);
-    sb_free(mask);
-    sb_free(flag);
-    sb_free(phi);
-    sb_free(partials);
-    sb_free(total);
-    return e;
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_work_items(P, partials, s);
 }
 
 }  // namespace mpmx

@@ -694,6 +694,7 @@ struct G2POut {
     float* tau;
     uint32_t* id;
     uint32_t* inst;
+    uint32_t* keys;  // optional: the sort key of each new position (the next step's binning)
 };
 
 // GS threads per workgroup, work items of at most 2 GS particles.
@@ -908,12 +909,21 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
             }
             const size_t o = (size_t)(s + r);
             bool finite = true;
+            float xn[3] = {0.f, 0.f, 0.f};
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
-                const float xn = xp[a] + dt * vp[a];
-                finite = finite && isfinite(xn) && isfinite(vp[a]);
-                out.x[(size_t)a * n + o] = xn;
+                xn[a] = xp[a] + dt * vp[a];
+                finite = finite && isfinite(xn[a]) && isfinite(vp[a]);
+                out.x[(size_t)a * n + o] = xn[a];
                 out.v[(size_t)a * n + o] = vp[a];
+            }
+            if (out.keys) {
+                // the next build's binning of the position just written (the
+                // same float64 arithmetic as k_bin on the stored float32 value);
+                // every particle of an item shares the owner block's instance
+                unsigned bad = 0;
+                out.keys[o] = bin_key<DIM>(P, xn, (uint32_t)inst, &bad);
+                if (bad) raise_flag(P.ctr, bad);
             }
 #pragma unroll
             for (int a = 0; a < DIM; ++a)
@@ -995,9 +1005,9 @@ hipError_t launch_grid_update(const DevParams& P, long long n_nodes_host, int gr
 hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, const uint32_t* id_in,
                       const uint32_t* inst_in, float* x_out, float* v_out, float* C_out, float* F_out, float* tau_out,
                       uint32_t* id_out, uint32_t* inst_out, int n, const uint32_t* osrc, int block_size,
-                      int grid_blocks, hipStream_t s) {
+                      int grid_blocks, hipStream_t s, uint32_t* keys_out) {
     G2PIn in{x_in, F_in, id_in, inst_in};
-    G2POut out{x_out, v_out, C_out, F_out, tau_out, id_out, inst_out};
+    G2POut out{x_out, v_out, C_out, F_out, tau_out, id_out, inst_out, keys_out};
     if (2 * block_size < P.chunk) return hipErrorInvalidValue;  // work items must fit the LDS staging
     switch (block_size * 4 + P.dim) {
         case 64 * 4 + 3: k_g2p<3, 64><<<grid_blocks, 64, 0, s>>>(P, in, out, n, osrc); break;

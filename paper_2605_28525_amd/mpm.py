@@ -28,6 +28,8 @@ MPM_GRID_SPARSE, MPM_GRID_DENSE = 0, 1
 MPM_FLAG_SYNC_REBUILD = 1
 MPM_FLAG_ADJOINT = 2
 MPM_FLAG_FULL_SORT = 4
+MPM_FLAG_DETERMINISTIC_ORDER = 8
+MPM_FLAG_SCAN_BUILD = 16
 
 
 class mpm_instance(ctypes.Structure):

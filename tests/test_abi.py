@@ -71,6 +71,25 @@ def test_constants_match_header():
         assert int(defs["MPM_BC_" + k.upper()]) == v
     assert int(defs["MPM_MODEL_DP"]) == M.MPM_MODEL["dp"]
     assert int(defs["MPM_MODEL_ELASTIC"]) == M.MPM_MODEL["elastic"]
+    for k in ("SYNC_REBUILD", "ADJOINT", "FULL_SORT", "DETERMINISTIC_ORDER", "SCAN_BUILD"):
+        assert int(defs["MPM_FLAG_" + k]) == getattr(M, "MPM_FLAG_" + k)
+
+
+def test_create_rejects_bad_flag_combinations_without_touching_the_device():
+    """The scan-based build is for one sparse simulation without reverse mode;
+    the ascending-key order needs a sparse grid."""
+    from paper_2605_28525_amd import mpm as M
+    from paper_2605_28525_amd import workloads as wl
+    ctx = ctypes.c_void_p()
+    w = wl.tiny_3d(n=48)
+    for flags, mode in ((M.MPM_FLAG_SCAN_BUILD, M.MPM_GRID_DENSE),
+                        (M.MPM_FLAG_SCAN_BUILD | M.MPM_FLAG_ADJOINT, M.MPM_GRID_SPARSE),
+                        (M.MPM_FLAG_DETERMINISTIC_ORDER, M.MPM_GRID_DENSE)):
+        p = M.params_from_workload(w, grid_mode=mode, flags=flags)
+        assert M.lib.mpm_create(ctypes.byref(p), ctypes.byref(ctx)) == M.MPM_ERR_ARG
+    p = M.params_from_ensemble(wl.ensemble_small(n_instances=3), flags=M.MPM_FLAG_SCAN_BUILD)
+    assert M.lib.mpm_create(ctypes.byref(p), ctypes.byref(ctx)) == M.MPM_ERR_ARG
+    assert not ctx.value
 
 
 def test_create_rejects_bad_arguments_without_touching_the_device():

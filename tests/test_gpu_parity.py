@@ -168,6 +168,28 @@ def test_collapse_3d_eighth_scale_steps():
     sim.close()
 
 
+def test_collapse_3d_eighth_scale_long_run():
+    """The 1/8-volume 3D collapse from rest (262,144 particles) over its whole
+    run: steps 0, 1, 100, 500, 1000 and 1999 compared with the oracle started
+    from the GPU's state of that step (the GPU runs ahead in between), so the
+    late, spread-out states with plastic flow are covered, not only the
+    release."""
+    w = wl.collapse_3d(scale=2)
+    _announce("collapse_3d_1of8 long run", w.n)
+    sim = _sim(w)
+    at = 0
+    for k in (0, 1, 100, 500, 1000, 1999):
+        if k > at:
+            sim.step(k - at)
+            at = k
+        parts = gpu_step_parts(sim)
+        assert parts["status"][0] == 0, (k, parts["status"])
+        print(k, parts["nb"], compare_step(w, parts), flush=True)
+        sim.a, sim.b = sim.b, sim.a
+        at += 1
+    sim.close()
+
+
 def test_dense_matches_sparse_and_oracle():
     """Dense-grid mode (every block of the potential domain) gives the oracle's
     step too; sparse and dense GPU particle results agree."""
