@@ -276,6 +276,20 @@ int mpm_get_active(mpm_ctx* ctx, uint64_t* keys, uint64_t* masks, int capacity, 
 int mpm_scan_active(mpm_ctx* ctx, const mpm_particles* p, uint64_t* keys, uint64_t* masks, int capacity,
                     int* n_blocks, void* stream);
 
+/* Allocation-free form of mpm_scan_active, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, outputs and synchronisation as
+ * mpm_scan_active, on any one-simulation context (MPM_FLAG_SCAN_BUILD not
+ * needed): the scratch is a static device array holding a mask domain of at
+ * most 1,048,576 blocks (16 MiB on each device the library runs on, resident
+ * until the process ends); no device memory is allocated or freed.  Returns
+ * MPM_ERR_OVERFLOW, with *n_blocks = 0 and nothing written, when the bounding
+ * box of the owner blocks grown by one block exceeds that.  Every call on a
+ * device shares that device's array: calls that overlap on one device (other
+ * streams, other host threads) race. */
+int mpm_scan_active_static(mpm_ctx* ctx, const mpm_particles* p, uint64_t* keys, uint64_t* masks, int capacity,
+                           int* n_blocks, void* stream);
+
 /* Copies the compact grid, 4 floats per node, blocks 0..min(n_blocks,
  * capacity)-1 in Phi order, nodes in l(n) order within a block: after mpm_p2g
  * (p_x, p_y, p_z, m); after mpm_grid_update (v_x, v_y, v_z, m) (2D: z = 0).

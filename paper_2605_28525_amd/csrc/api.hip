@@ -1019,6 +1019,20 @@ int mpm_scan_active(mpm_ctx* c, const mpm_particles* p, uint64_t* keys, uint64_t
     return MPM_OK;
 }
 
+int mpm_scan_active_static(mpm_ctx* c, const mpm_particles* p, uint64_t* keys, uint64_t* masks, int capacity,
+                           int* n_blocks, void* stream) {
+    if (!c || !n_blocks || capacity < 0 || (capacity > 0 && (!keys || !masks))) return MPM_ERR_ARG;
+    if (c->P.n_inst > 1 || !particles_ok(c, p, false)) return MPM_ERR_ARG;
+    *n_blocks = 0;
+    SbBox box{};
+    if (launch_scan_active_static(c->P, p->x, p->n, keys, masks, capacity, &box, (hipStream_t)stream) !=
+        hipSuccess)
+        return MPM_ERR_HIP;
+    if (box.too_big) return MPM_ERR_OVERFLOW;
+    *n_blocks = (int)box.total;
+    return MPM_OK;
+}
+
 int mpm_get_grid(mpm_ctx* c, float* out, int capacity_blocks, void* stream) {
     if (!c || !out || capacity_blocks < 0) return MPM_ERR_ARG;
     if (!c->built) return MPM_ERR_STATE;

@@ -385,6 +385,9 @@ hipError_t launch_scan_active(const DevParams& P, const float* x, int n, const S
 hipError_t launch_build_scan(const DevParams& P, const uint32_t* skeys, int n, const SbScratch& S,
                              unsigned* partials, hipStream_t s);
 hipError_t launch_work_items(const DevParams& P, unsigned* partials, hipStream_t s);
+long long scan_active_static_max_blocks();
+hipError_t launch_scan_active_static(const DevParams& P, const float* x, int n, uint64_t* keys_out,
+                                     uint64_t* masks_out, int cap, SbBox* box_host, hipStream_t s);
 
 hipError_t radix_sort(const uint32_t* keys_in, uint32_t* k0, uint32_t* k1, uint32_t* v0, uint32_t* v1, int n,
                       int key_bits, unsigned* hist, unsigned* partials, uint32_t** keys_out, uint32_t** vals_out,

@@ -98,6 +98,8 @@ _SIGS = {
     "mpm_active_count": (c_int, [_PCTX, c_void_p, POINTER(c_int), POINTER(c_int)]),
     "mpm_get_active": (c_int, [_PCTX, c_void_p, c_void_p, c_int, c_void_p]),
     "mpm_scan_active": (c_int, [_PCTX, POINTER(mpm_particles), c_void_p, c_void_p, c_int, POINTER(c_int), c_void_p]),
+    "mpm_scan_active_static": (c_int, [_PCTX, POINTER(mpm_particles), c_void_p, c_void_p, c_int, POINTER(c_int),
+                                       c_void_p]),
     "mpm_get_grid": (c_int, [_PCTX, c_void_p, c_int, c_void_p]),
     "mpm_get_order": (c_int, [_PCTX, c_void_p, c_int, c_void_p]),
     "mpm_set_material": (c_int, [_PCTX, c_float, c_float, c_float, c_float]),
@@ -216,6 +218,16 @@ def mpm_scan_active(ctx, particles, keys, masks, capacity: int, stream=None) -> 
     _check(lib.mpm_scan_active(ctx, ctypes.byref(particles), c_void_p(keys.data_ptr() if capacity else 0),
                                c_void_p(masks.data_ptr() if capacity else 0), int(capacity), ctypes.byref(nb),
                                _stream(stream)), "mpm_scan_active")
+    return nb.value
+
+
+def mpm_scan_active_static(ctx, particles, keys, masks, capacity: int, stream=None) -> int:
+    """mpm_scan_active with the library's static scratch (allocates nothing);
+    returns the count."""
+    nb = c_int(0)
+    _check(lib.mpm_scan_active_static(ctx, ctypes.byref(particles), c_void_p(keys.data_ptr() if capacity else 0),
+                                      c_void_p(masks.data_ptr() if capacity else 0), int(capacity),
+                                      ctypes.byref(nb), _stream(stream)), "mpm_scan_active_static")
     return nb.value
 
 
