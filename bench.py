@@ -97,7 +97,7 @@ def time_steps(sim, steps, stream, phases=True):
         return e0.elapsed_time(e1) / 1e3, {}
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
     for k in range(steps):
-        a, b = sim.a.view(), sim.b.view()
+        a, b = sim.a.view(sim.carry_id), sim.b.view(sim.carry_id)
         e = ev[k]
         e[0].record(stream)
         M.mpm_sparse_build(sim.ctx, a, stream)
@@ -199,8 +199,8 @@ def adjoint_ratio(steps, checkpoint=50):
 
 
 def ensemble_leg(steps, stream):
-    """64 uneven column collapses (about 19.5 M particles): autotuned, one
-    graph-captured step pair replayed, against the same instances run one after
+    """64 uneven column collapses (about 19.5 M particles): autotuned, a graph
+    of 10 captured steps replayed, against the same instances run one after
     another as 64 stand-alone simulations (eager steps)."""
     import torch
     from paper_2605_28525_amd import mpm as M
@@ -213,12 +213,15 @@ def ensemble_leg(steps, stream):
     chosen = M.mpm_autotune(sim.ctx, sim.a.view(), sim.b.view(), stream)
     log(f"bench: ensemble autotune -> chunk {chosen[0]}, g2p block {chosen[1]}, p2g wgs {chosen[2]}, "
         f"g2p wgs {chosen[3]}")
-    M.mpm_graph_capture(sim.ctx, sim.a.view(), sim.b.view(), 2, stream)
+    # a graph of 10 steps (inside one capture G2P bins for the next step)
+    cap = 10
+    steps = max(cap, steps - steps % cap)
+    M.mpm_graph_capture(sim.ctx, sim.a.view(), sim.b.view(), cap, stream)
     M.mpm_graph_launch(sim.ctx, 1, stream)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    M.mpm_graph_launch(sim.ctx, steps // 2, stream)
+    M.mpm_graph_launch(sim.ctx, steps // cap, stream)
     e1.record(stream)
     torch.cuda.synchronize()
     t_batch = e0.elapsed_time(e1) / 1e3
@@ -365,6 +368,7 @@ def builder_leg(w, src, cap, steps, stream):
     for name, flags in (("hash_resort", 0), ("hash_full_sort", M.MPM_FLAG_FULL_SORT),
                         ("scan_full_sort", M.MPM_FLAG_SCAN_BUILD)):
         sim = M.Simulation(w, block_capacity=cap, flags=flags)
+        sim.carry_id = src.carry_id
         try:
             copy_state(sim, src)
             sim.step(2, stream=stream)
@@ -426,30 +430,36 @@ def late_state_leg(sim, simd, steps_done, targets, steps, dense_steps, stream):
     return recs, steps_done
 
 
+def graph_len(steps):
+    """Steps captured in one graph: as many as one timed run (even, so that the
+    state returns to sim.a), so that its steps bin in G2P like mpm_step's."""
+    return max(2, steps - steps % 2)
+
+
 def time_graph(sim, steps, stream):
-    """The same step replayed from a HIP graph of two captured steps
-    (`mpm_graph_capture`), timed with events around `steps` // 2 replays;
-    the state returns to sim.a after every replay.  Returns seconds per step."""
+    """The same steps replayed from a HIP graph of graph_len(steps) captured
+    steps (`mpm_graph_capture`), one replay after a warm-up replay, timed with
+    events.  Returns seconds per step."""
     import torch
     from paper_2605_28525_amd import mpm as M
-    reps = max(1, steps // 2)
-    M.mpm_graph_capture(sim.ctx, sim.a.view(), sim.b.view(), 2, stream)
+    n_cap = graph_len(steps)
+    M.mpm_graph_capture(sim.ctx, sim.a.view(sim.carry_id), sim.b.view(sim.carry_id), n_cap, stream)
     try:
         M.mpm_graph_launch(sim.ctx, 1, stream)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        M.mpm_graph_launch(sim.ctx, reps, stream)
+        M.mpm_graph_launch(sim.ctx, 1, stream)
         e1.record(stream)
         torch.cuda.synchronize()
     finally:
         M.mpm_graph_release(sim.ctx)
-    return e0.elapsed_time(e1) / 1e3 / (2 * reps)
+    return e0.elapsed_time(e1) / 1e3 / n_cap
 
 
 def graph_steps(steps):
     """Steps that time_graph advances the state by."""
-    return 2 * (max(1, steps // 2) + 1)
+    return 2 * graph_len(steps)
 
 
 def measured_copy_gbs(mib=2048, reps=5):
@@ -536,7 +546,7 @@ def host_info():
     return info
 
 
-def _oracle_steps(name, steps):
+def _oracle_steps(name, steps, progress=False):
     """Runs the FP64 oracle `steps` steps of a workload on one thread; returns
     (particles, seconds).  Top-level so that spawned worker processes can run it."""
     from threadpoolctl import threadpool_limits
@@ -548,8 +558,10 @@ def _oracle_steps(name, steps):
         p = om.Params.from_workload(w)
         st = om.state_from_soa(w.state(), w.dim)
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for k in range(steps):
             st = om.step(st, p)
+            if progress and (k + 1) % 5 == 0:
+                log(f"bench: oracle {name} step {k + 1}/{steps}, {time.perf_counter() - t0:.1f} s")
         return w.n, time.perf_counter() - t0
 
 
@@ -574,9 +586,15 @@ def cpu_baseline(w_name, budget_s):
             steps += 1
         dt = time.perf_counter() - t0
     host = host_info()
+    # the oracle on the smaller configurations too: the whole 2D collapse, and
+    # three steps of the 1/8-volume 3D collapse (all 20 with --cpu-full)
+    n2, t2 = _oracle_steps("collapse_2d", 200)
+    n3, t3 = _oracle_steps("collapse_3d_1of8", 3)
     return {"value": w.n * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{sample}, {steps} steps in {dt:.1f} s, float64 numpy, one thread "
                       f"(1 of {host['affinity']} usable host cores)",
+            "configs": {"collapse_2d": {"particles": n2, "steps": 200, "seconds": t2, "value": n2 * 200 / t2},
+                        "collapse_3d_1of8": {"particles": n3, "steps": 3, "seconds": t3, "value": n3 * 3 / t3}},
             "host": host}
 
 
@@ -589,7 +607,7 @@ def cpu_full_runs():
     n, t = _oracle_steps("collapse_2d", 200)
     out["collapse_2d_200_steps"] = {"particles": n, "seconds": t, "value": n * 200 / t}
     log(f"bench: oracle collapse_2d 200 steps {t:.1f} s")
-    n, t = _oracle_steps("collapse_3d_1of8", 20)
+    n, t = _oracle_steps("collapse_3d_1of8", 20, progress=True)
     out["collapse_3d_1of8_20_steps"] = {"particles": n, "seconds": t, "value": n * 20 / t}
     log(f"bench: oracle collapse_3d 1/8 20 steps {t:.1f} s")
     procs = min(16, len(os.sched_getaffinity(0)))
@@ -629,6 +647,10 @@ def main():
     log(f"bench: {w.name} n={n} cells={w.cells}")
     cap = args.block_capacity or (1 << 18 if args.workload == "landslide" else 1 << 16)
     sim, sparse_bytes = device_bytes_of(lambda: M.Simulation(w, block_capacity=cap))
+    # The particle id that may travel with each particle is bookkeeping for the
+    # caller, not the method's work: the headline runs without it, and one run
+    # with it is timed beside.
+    sim.carry_id = False
     log("bench: warmup")
     steps_done = 0
     if args.warmup:
@@ -658,6 +680,10 @@ def main():
     steps_done += args.steps
     t_graph = time_graph(sim, args.steps, stream)
     steps_done += graph_steps(args.steps)
+    sim.carry_id = True
+    t_id, _ = time_steps(sim, args.steps, stream, phases=False)
+    steps_done += args.steps
+    sim.carry_id = False
     rc, flags = sim.status()
     if rc != 0:
         raise SystemExit(f"device status after graph replays: {rc} flags={flags}")
@@ -709,6 +735,7 @@ def main():
         "phases_ms": ph,
         "g2p_id_carry_bytes": g2p_id_bytes,
         "graph": {"ms_per_step": 1e3 * t_graph, "value": n / t_graph},
+        "with_id": {"ms_per_step": 1e3 * t_id / args.steps, "value": n * args.steps / t_id},
         "tuning": tuning,
         "build_ms_per_step": ph["build"],
         "build_roofline_frac": build_bytes / (ph["build"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -731,6 +758,7 @@ def main():
     if not args.no_dense:
         log("bench: dense baseline")
         simd, dense_bytes = device_bytes_of(lambda: M.Simulation(w, grid_mode=M.MPM_GRID_DENSE))
+        simd.carry_id = False
         simd.step(2, stream=stream)
         td, _ = time_steps(simd, args.dense_steps, stream, phases=False)
         rc, flags = simd.status()

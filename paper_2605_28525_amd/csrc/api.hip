@@ -71,9 +71,12 @@ struct mpm_ctx {
     uint32_t* nh_cnt = nullptr;
     int* nh_idx = nullptr;
     uint32_t* nh_owner = nullptr;
+    int* h_entry = nullptr;
+    int* b_entry = nullptr;
     uint32_t* order = nullptr;
     uint32_t* skeys = nullptr;
     uint32_t* osrc = nullptr;  // G2P output position -> input index (the spare sort value buffer)
+    uint32_t* movers = nullptr;  // incremental re-sort: particles that changed owner block
     // scan-based construction (MPM_FLAG_SCAN_BUILD): mask-domain scratch for
     // every block of the potential domain, allocated at create
     bool scan_build = false;
@@ -150,6 +153,8 @@ void free_capacity_buffers(mpm_ctx* c) {
     dfree(c->nh_cnt);
     dfree(c->nh_idx);
     dfree(c->nh_owner);
+    dfree(c->h_entry);
+    dfree(c->b_entry);
     dfree(c->det.keys);
     dfree(c->det.mask);
     dfree(c->det.start);
@@ -193,6 +198,7 @@ void free_all(mpm_ctx* c) {
     dfree(c->adj_scratch);
     dfree(c->inst);
     dfree(c->ctr);
+    dfree(c->movers);
     if (c->sb_mem) (void)hipFree(c->sb_mem);
     c->sb_mem = nullptr;
     dfree(c->sb_seg);
@@ -302,6 +308,8 @@ void fill_params(mpm_ctx* c) {
     P.nh_cnt = c->nh_cnt;
     P.nh_idx = c->nh_idx;
     P.nh_owner = c->nh_owner;
+    P.h_entry = c->h_entry;
+    P.b_entry = c->b_entry;
     fill_material(c);
 }
 
@@ -374,6 +382,8 @@ int alloc_capacity_buffers(mpm_ctx* c) {
         e = e ? e : dalloc(&c->nh_cnt, H * NPB);
         e = e ? e : dalloc(&c->nh_idx, H);
         e = e ? e : dalloc(&c->nh_owner, H);
+        e = e ? e : dalloc(&c->h_entry, H);
+        e = e ? e : dalloc(&c->b_entry, cap);
     }
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -437,8 +447,10 @@ int build_once(mpm_ctx* c, const mpm_particles* p, hipStream_t s, bool reuse, bo
             e = launch_bin(c->P, p->x, p->inst, n, fresh, s);
             if (e != hipSuccess) return MPM_ERR_HIP;
         }
-        uint32_t* spare = vo == c->v0 ? c->v1 : c->v0;  // the next osrc, free until P2G
-        e = launch_resort(c->P, prev, fresh, prev, vo, spare, n, 1u << c->H_log2, c->partials, s);
+        // keys_ready: the G2P that binned also counted stayers and listed movers.
+        // The sorted keys are not written: P2G reads each block's cell ranges
+        // from the re-sort's table, and the next re-sort reads no previous key.
+        e = launch_resort(c->P, fresh, nullptr, vo, c->movers, n, 1u << c->H_log2, c->partials, s, keys_ready);
         if (e != hipSuccess) return MPM_ERR_HIP;
         ko = prev;
     } else {
@@ -673,6 +685,7 @@ int mpm_create(const mpm_params* q, mpm_ctx** out) {
     e = e ? e : dalloc(&c->v0, np);
     e = e ? e : dalloc(&c->v1, np);
     e = e ? e : dalloc(&c->hist, (size_t)radix_hist_size(q->max_particles));
+    if (!c->dense && !c->adjoint && !c->scan_build && !c->det_order) e = e ? e : dalloc(&c->movers, np);
     e = e ? e : dalloc(&c->ctr, 1);
     if (c->adjoint) e = e ? e : dalloc(&c->adj_scratch, np * (size_t)(c->dim + 2 * c->dim * c->dim));
     if (e == hipSuccess && q->heightmap) {
@@ -767,7 +780,8 @@ int mpm_grid_update(mpm_ctx* c, void* stream) {
 namespace {
 // mpm_g2p; with keys_out, the kernel also bins the positions it writes (the
 // next build then skips its binning pass).
-int g2p_impl(mpm_ctx* c, const mpm_particles* in, const mpm_particles* out, hipStream_t s, uint32_t* keys_out) {
+int g2p_impl(mpm_ctx* c, const mpm_particles* in, const mpm_particles* out, hipStream_t s, uint32_t* keys_out,
+             uint32_t* movers_out) {
     if (!c || !particles_ok(c, in, false) || !out || out->n != in->n) return MPM_ERR_ARG;
     if (in->n > 0) {
         if (!out->x || !out->v || !out->C || !out->F || !out->tau || !in->F) return MPM_ERR_ARG;
@@ -778,12 +792,12 @@ int g2p_impl(mpm_ctx* c, const mpm_particles* in, const mpm_particles* out, hipS
     if (in->n == 0) return MPM_OK;
     const int wgs = std::min(c->g2p_wgs, c->work_cap);
     return hip_status(launch_g2p(c->P, in->x, in->F, in->id, in->inst, out->x, out->v, out->C, out->F, out->tau,
-                                 out->id, out->inst, in->n, c->osrc, c->g2p_block, wgs, s, keys_out));
+                                 out->id, out->inst, in->n, c->osrc, c->g2p_block, wgs, s, keys_out, movers_out));
 }
 }  // namespace
 
 int mpm_g2p(mpm_ctx* c, const mpm_particles* in, const mpm_particles* out, void* stream) {
-    return g2p_impl(c, in, out, (hipStream_t)stream, nullptr);
+    return g2p_impl(c, in, out, (hipStream_t)stream, nullptr, nullptr);
 }
 
 int mpm_step(mpm_ctx* c, const mpm_particles* a, const mpm_particles* b, int n_steps, void* stream) {
@@ -801,8 +815,11 @@ int mpm_step(mpm_ctx* c, const mpm_particles* a, const mpm_particles* b, int n_s
         // so G2P bins them as it writes them.  Not in reverse-mode contexts,
         // whose tape records each build as mpm_sparse_build makes it.
         keys_ready = k + 1 < n_steps && !c->adjoint && cur->n > 0;
-        uint32_t* keys_out = keys_ready ? next_bin_buffer(c, would_reuse(c, nxt->n)) : nullptr;
-        if (st == MPM_OK) st = g2p_impl(c, cur, nxt, s, keys_out);
+        const bool next_reuse = would_reuse(c, nxt->n);
+        uint32_t* keys_out = keys_ready ? next_bin_buffer(c, next_reuse) : nullptr;
+        // with an incremental re-sort next, G2P also does its counting
+        uint32_t* movers_out = keys_ready && next_reuse ? c->movers : nullptr;
+        if (st == MPM_OK) st = g2p_impl(c, cur, nxt, s, keys_out, movers_out);
         if (st != MPM_OK) return st;
         std::swap(cur, nxt);
     }

@@ -65,14 +65,18 @@ __global__ __launch_bounds__(WG) void k_bin(DevParams P, const float* __restrict
     if (bad) raise_flag(P.ctr, bad);
 }
 
+// Claims or finds the slot of key K (Eqs. 23-25): a probed slot is read
+// first and compare-and-swapped from EMPTY only when it is empty (most inserts
+// find their block already claimed by another wave: each block is the owner
+// or an upper neighbour of up to 2^d inserting waves).
 __device__ int hash_insert(const DevParams& P, uint64_t K) {
     unsigned s = (unsigned)mix64(K) & P.h_mask_bits;
     for (int r = 0; r < P.n_probe; ++r) {
-        uint64_t cur = __hip_atomic_load(&P.h_keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t cur = __hip_atomic_load(&P.h_keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (cur == K) return (int)s;
         if (cur == EMPTY_KEY) {
-            uint64_t old = atomicCAS((unsigned long long*)&P.h_keys[s], (unsigned long long)EMPTY_KEY,
-                                     (unsigned long long)K);
+            const uint64_t old = atomicCAS((unsigned long long*)&P.h_keys[s], (unsigned long long)EMPTY_KEY,
+                                           (unsigned long long)K);
             if (old == EMPTY_KEY || old == K) return (int)s;
         }
         s = (s + 1) & P.h_mask_bits;
@@ -87,6 +91,7 @@ __global__ __launch_bounds__(WG) void k_hash_clear(DevParams P, unsigned H) {
         P.h_mask[s] = 0ull;
         P.h_start[s] = -1;
         P.h_end[s] = -1;
+        if (P.h_entry) P.h_entry[s] = -1;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         P.ctr->nb = 0;
@@ -251,6 +256,7 @@ __global__ __launch_bounds__(WG) void k_hash_insert_entries(DevParams P) {
         if (lane == 0 && slot >= 0) {  // lane 0 holds the owner block
             P.h_start[slot] = (int)first;
             P.h_end[slot] = (int)end;
+            if (P.h_entry) P.h_entry[slot] = e;
         }
     }
 }
@@ -298,6 +304,7 @@ __global__ __launch_bounds__(WG) void k_compact_write(DevParams P, int H, const 
             P.b_count[phi] = st >= 0 ? P.h_end[idx] - st : 0;
             P.h_vals[idx] = (int)phi;
             if (slot_of) slot_of[phi] = idx;
+            if (P.b_entry) P.b_entry[phi] = P.h_entry[idx];
         } else {
             P.h_vals[idx] = -1;
             over = true;
@@ -345,32 +352,59 @@ __global__ __launch_bounds__(WG) void k_det_apply(DevParams P, DetTables T, cons
     }
 }
 
+// Neighbour tables and chunking of the compact blocks, 2^(d+1) lanes per block:
+// lane j < 2^d looks up upper neighbour j, lane 2^d + j lower neighbour j (so
+// the probe chains of a block run side by side, not one after another).
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_block_setup(DevParams P) {
     constexpr int NB = 1 << DIM;
+    constexpr int LPB = 2 * NB;
+    constexpr int NC = 1 << (2 * DIM);
     const int nb = P.ctr->nb;
-    for (int b = blockIdx.x * WG + threadIdx.x; b < nb; b += gridDim.x * WG) {
+    const long long total = (long long)nb * LPB;
+    for (long long t = (long long)blockIdx.x * WG + threadIdx.x; t < total; t += (long long)gridDim.x * WG) {
+        const int b = (int)(t / LPB), j = (int)(t % LPB);
+        const int d = j % NB;
         int bc[3], inst;
         unblock_key<DIM>(P, P.b_keys[b], bc, &inst);
-        P.b_nbr[b * NB] = b;
-#pragma unroll
-        for (int d = 1; d < NB; ++d)
-            P.b_nbr[b * NB + d] = hash_lookup(P, block_key<DIM>(P, bc[0] + (d & 1), bc[1] + ((d >> 1) & 1),
-                                                                 bc[2] + ((d >> 2) & 1), inst));
-        if (P.b_lo) {
+        if (j < NB) {
+            P.b_nbr[b * NB + d] =
+                d == 0 ? b
+                       : hash_lookup(P, block_key<DIM>(P, bc[0] + (d & 1), bc[1] + ((d >> 1) & 1),
+                                                       bc[2] + ((d >> 2) & 1), inst));
+        } else if (P.b_lo) {
             // lower neighbours that own particles (the blocks whose P2G tiles
             // reach this block), -1 for the others
-            int lo[NB];
-            lo[0] = b;
-#pragma unroll
-            for (int d = 1; d < NB; ++d)
-                lo[d] = hash_lookup(P, block_key<DIM>(P, bc[0] - (d & 1), bc[1] - ((d >> 1) & 1),
-                                                      bc[2] - ((d >> 2) & 1), inst));
-#pragma unroll
-            for (int d = 0; d < NB; ++d) P.b_lo[b * NB + d] = (lo[d] >= 0 && P.b_count[lo[d]] > 0) ? lo[d] : -1;
+            const int lo = d == 0 ? b
+                                  : hash_lookup(P, block_key<DIM>(P, bc[0] - (d & 1), bc[1] - ((d >> 1) & 1),
+                                                                  bc[2] - ((d >> 2) & 1), inst));
+            P.b_lo[b * NB + d] = (lo >= 0 && P.b_count[lo] > 0) ? lo : -1;
         }
-        P.b_chunks[b] = (unsigned)((P.b_count[b] + P.chunk - 1) / P.chunk);
+        const unsigned chunks = (unsigned)((P.b_count[b] + P.chunk - 1) / P.chunk);
+        if (j == 0) P.b_chunks[b] = chunks;
+        if (P.rs_stay) {
+            // for the next incremental re-sort, when a G2P bins its output:
+            // the owner part of the block's sort key, and cleared per-cell
+            // stayer counts where G2P will not store them whole (no particle,
+            // or several work items adding theirs)
+            if (j == 0) {
+                bool in_range = inst < max(P.n_inst, 1);
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) in_range = in_range && bc[a] >= 0 && bc[a] < P.nblk[a];
+                uint32_t owner = ~0u;
+                if (in_range) {
+                    const uint32_t bl = DIM == 3 ? ((uint32_t)bc[2] * (uint32_t)P.nblk[1] + (uint32_t)bc[1]) *
+                                                           (uint32_t)P.nblk[0] + (uint32_t)bc[0]
+                                                 : (uint32_t)bc[1] * (uint32_t)P.nblk[0] + (uint32_t)bc[0];
+                    owner = ((uint32_t)inst << P.blk_bits) | bl;
+                }
+                P.rs_oldblk[b] = owner;
+            }
+            if (chunks != 1u)
+                for (int c = j; c < NC; c += LPB) P.rs_stay[(size_t)b * NC + c] = 0u;
+        }
     }
+    if (P.rs_stay && blockIdx.x == 0 && threadIdx.x == 0) P.ctr->rs_n_mov = 0;
 }
 
 __global__ __launch_bounds__(WG) void k_work_write(DevParams P) {
@@ -486,6 +520,7 @@ hipError_t launch_build_sparse(const DevParams& P, const uint32_t* skeys, int n,
     }
     const int tiles = ((int)H + SCAN_TILE - 1) / SCAN_TILE;
     const int gb = grid_for(P.block_cap, 2048);
+    const int gs = grid_for(2ll * (1 << P.dim) * P.block_cap, 8192);  // k_block_setup: 2^(d+1) lanes per block
     k_compact_count<<<tiles, WG, 0, s>>>(P, (int)H, partials);
     if (det) {
         // compaction in slot order into the alternate tables, then the blocks
@@ -511,9 +546,9 @@ hipError_t launch_build_sparse(const DevParams& P, const uint32_t* skeys, int n,
         k_compact_write<<<tiles, WG, 0, s>>>(P, (int)H, partials, tiles, nullptr);
     }
     if (P.dim == 3)
-        k_block_setup<3><<<gb, WG, 0, s>>>(P);
+        k_block_setup<3><<<gs, WG, 0, s>>>(P);
     else
-        k_block_setup<2><<<gb, WG, 0, s>>>(P);
+        k_block_setup<2><<<gs, WG, 0, s>>>(P);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // no grid clear: the second P2G pass writes every node of every active block

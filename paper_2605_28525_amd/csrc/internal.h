@@ -120,6 +120,9 @@ struct DevParams {
     uint32_t* nh_cnt;     //   with no previous slot, their movers per cell,
     int* nh_idx;          //   their entry index
     uint32_t* nh_owner;   //   and the owner-block part of their sort key
+    int* h_entry;         // re-sort entry of each hash slot's owner block (-1: none)
+    int* b_entry;         // re-sort entry of each compact block (-1: none): its cell
+                          // ranges are the entry's row of rs_off
     // ensembles
     int n_inst;          // 1 = single simulation
     int blk_bits;        // bits of the linear block id inside the sort key
@@ -360,10 +363,17 @@ struct SbBox {
 };
 
 // Scratch of the scan-based construction, carved from one allocation: box
-// header, occupancy (u64), flags and Phi (u32) for up to max_m blocks of the
-// domain, scan partials; owner segment bounds (step build only, may be null).
+// header, the bounding-box partials of the SB_BBOX_WGS workgroups of its pass,
+// occupancy (u64), flags and Phi (u32) for up to max_m blocks of the domain,
+// scan partials; owner segment bounds (step build only, may be null).
+constexpr int SB_BBOX_WGS = 1024;
+constexpr size_t sb_scratch_size(long long max_m) {
+    return 256 + (size_t)SB_BBOX_WGS * 8 * sizeof(int) + (size_t)max_m * (8 + 4 + 4) +
+           (size_t)((max_m + SCAN_TILE - 1) / SCAN_TILE + 1) * sizeof(unsigned) + 256;
+}
 struct SbScratch {
     SbBox* box;
+    int* bbp;  // per workgroup of the bounding-box pass: lo[3], hi[3]
     uint64_t* occ;
     unsigned* flag;
     unsigned* phi;
@@ -395,8 +405,12 @@ hipError_t radix_sort(const uint32_t* keys_in, uint32_t* k0, uint32_t* k1, uint3
 int radix_hist_size(int n);
 
 hipError_t launch_bin(const DevParams& P, const float* x, const uint32_t* inst, int n, uint32_t* keys, hipStream_t s);
-hipError_t launch_resort(const DevParams& P, uint32_t* keys_prev, const uint32_t* keys_new, uint32_t* keys_out,
-                         uint32_t* vals_out, uint32_t* movers, int n, unsigned H, unsigned* partials, hipStream_t s);
+// keys_out may be null: the sorted keys are then not written (after an
+// incremental re-sort nothing reads them; P2G takes the cell ranges from the
+// re-sort's per-entry table)
+hipError_t launch_resort(const DevParams& P, const uint32_t* keys_new, uint32_t* keys_out, uint32_t* vals_out,
+                         uint32_t* movers, int n, unsigned H, unsigned* partials, hipStream_t s,
+                         bool counted = false);
 hipError_t launch_resort_init(const DevParams& P, unsigned H, hipStream_t s);
 // Buffers of the ascending-key Phi order (MPM_FLAG_DETERMINISTIC_ORDER): block
 // tables in slot order, the slot of each, and a radix sort of block_cap
@@ -421,7 +435,8 @@ hipError_t launch_grid_update(const DevParams& P, long long n_nodes_host, int gr
 hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, const uint32_t* id_in,
                       const uint32_t* inst_in, float* x_out, float* v_out, float* C_out, float* F_out, float* tau_out,
                       uint32_t* id_out, uint32_t* inst_out, int n, const uint32_t* osrc, int block_size,
-                      int grid_blocks, hipStream_t s, uint32_t* keys_out = nullptr);
+                      int grid_blocks, hipStream_t s, uint32_t* keys_out = nullptr,
+                      uint32_t* movers_out = nullptr);
 hipError_t launch_clear_flags(DevCounters* c, hipStream_t s);
 hipError_t launch_g2p_adj(const DevParams& P, const float* x, const float* F, const float* const* out_bar, float* x_bar,
                           float* F_bar, int n, const uint32_t* order, const uint32_t* skeys, int grid_blocks,

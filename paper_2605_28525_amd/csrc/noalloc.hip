@@ -15,8 +15,7 @@
 namespace mpmx {
 
 constexpr long long SB_STATIC_MAX_M = 1ll << 20;  // blocks of the mask domain
-constexpr size_t SB_STATIC_BYTES =
-    256 + (size_t)SB_STATIC_MAX_M * 16 + (size_t)((SB_STATIC_MAX_M + SCAN_TILE - 1) / SCAN_TILE + 1) * 4 + 256;
+constexpr size_t SB_STATIC_BYTES = sb_scratch_size(SB_STATIC_MAX_M);
 
 // Host code must not pass this name to a kernel (it is a host-side stand-in);
 // the device address comes from hipGetSymbolAddress below.

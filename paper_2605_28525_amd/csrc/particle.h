@@ -24,6 +24,34 @@ struct Tile {
     static constexpr int SZ = DIM == 3 ? 80 : 0;
     static constexpr int NP = DIM == 3 ? E * SZ : E * E;   // padded size
     static __device__ __forceinline__ int pad(int I, int J, int K) { return I + SY * J + SZ * K; }
+
+    // Layout of a tile in the HBM tile store, grouped by the block each node
+    // belongs to: part d (d = dx + 2 dy + 4 dz) holds the nodes of the upper
+    // neighbour d, local indices 0..3 along an axis where d's bit is clear and
+    // 4..5 (spilled) where it is set, x fastest.  The gather of a block then
+    // reads each part it needs whole and contiguous.  Part sizes are 4 or 2
+    // per axis, so the index arithmetic is shifts and masks; the part offsets
+    // are packed 8 bits each (3D: 0, 64, 96, 128, 144, 176, 192, 208; 2D: 0,
+    // 16, 24, 32).
+    static constexpr uint64_t PART_OFFS = DIM == 3 ? 0xD0C0B09080604000ull : 0x20181000ull;
+    static __device__ __forceinline__ int part_off(int d) { return (int)((PART_OFFS >> (8 * d)) & 255u); }
+    static __device__ __forceinline__ int part_lx(int d, int a) { return ((d >> a) & 1) ? 1 : 2; }  // log2 extent
+    // store position of node (I, J, K) of the 6^d tile
+    static __device__ __forceinline__ int store_index(int I, int J, int K) {
+        const int d = (I >> 2) | ((J >> 2) << 1) | (DIM == 3 ? ((K >> 2) << 2) : 0);
+        const int lx = part_lx(d, 0), ly = part_lx(d, 1);
+        return part_off(d) + (I & 3) + (((J & 3) + ((K & 3) << ly)) << lx);
+    }
+    // node (I, J, K) of the tile at store position t
+    static __device__ __forceinline__ void store_node(int t, int* I, int* J, int* K) {
+        int d = 0;
+#pragma unroll
+        for (int q = 1; q < NB; ++q) d += t >= part_off(q) ? 1 : 0;
+        const int i = t - part_off(d), lx = part_lx(d, 0), ly = part_lx(d, 1);
+        *I = (i & ((1 << lx) - 1)) + ((d & 1) << 2);
+        *J = ((i >> lx) & ((1 << ly) - 1)) + (((d >> 1) & 1) << 2);
+        *K = DIM == 3 ? (i >> (lx + ly)) + (((d >> 2) & 1) << 2) : 0;
+    }
 };
 
 // Per-axis base offset within the owner block, t and u, for one particle.
@@ -171,19 +199,46 @@ __device__ __forceinline__ unsigned long long lanes_matching(unsigned v, bool va
 // one wave-wide match per 64 keys, one LDS add per distinct cell) and the
 // ranges follow from an exclusive scan of the counts.  Optionally the first
 // `stage_max` entries of another per-particle array (`stage_src[st ..]`) are
-// copied to LDS (`stage_dst`) by the same batched loads.
+// copied to LDS (`stage_dst`) by the same batched loads.  With `cell_first`
+// (the first sorted position of each base cell, which an incremental re-sort
+// leaves per block) the counts are taken from it and no key is read.
 template <int DIM>
 __device__ void interleave_setup(Interleave<DIM>& L, const uint32_t* __restrict__ skeys, int st, int en,
                                  const uint32_t* __restrict__ stage_src = nullptr, uint32_t* stage_dst = nullptr,
-                                 int stage_max = 0) {
+                                 int stage_max = 0, const uint32_t* __restrict__ cell_first = nullptr) {
     constexpr int NC = Interleave<DIM>::NC;
-    for (int c = threadIdx.x; c < NC; c += blockDim.x) L.ce[c] = 0;  // per-cell counts first
-    if (threadIdx.x == 0) L.st = st;
-    __syncthreads();
+    const int stage_end = stage_dst ? min(en, st + stage_max) : st;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
-    const int stage_end = stage_dst ? min(en, st + stage_max) : st;
-    for (int i0 = st + wave * 64 * IL_BATCH; i0 < en; i0 += n_waves * 64 * IL_BATCH) {
+    if (cell_first) {
+        // the cell table and the first batch of the staged array are loaded
+        // together, then further batches (IL_BATCH loads in flight per lane)
+        int first = 0, next = 0;
+        if (threadIdx.x < NC) {
+            first = (int)cell_first[threadIdx.x];
+            next = threadIdx.x + 1 < NC ? (int)cell_first[threadIdx.x + 1] : en;
+        }
+        for (int i0 = st + wave * 64 * IL_BATCH; i0 < stage_end; i0 += n_waves * 64 * IL_BATCH) {
+            uint32_t v[IL_BATCH];
+#pragma unroll
+            for (int r = 0; r < IL_BATCH; ++r) {
+                const int i = i0 + r * 64 + lane;
+                v[r] = i < stage_end ? stage_src[i] : 0u;
+            }
+#pragma unroll
+            for (int r = 0; r < IL_BATCH; ++r) {
+                const int i = i0 + r * 64 + lane;
+                if (i < stage_end) stage_dst[i - st] = v[r];
+            }
+        }
+        if (threadIdx.x < NC) L.ce[threadIdx.x] = next - first;
+        if (threadIdx.x == 0) L.st = st;
+    } else {
+        for (int c = threadIdx.x; c < NC; c += blockDim.x) L.ce[c] = 0;  // per-cell counts first
+        if (threadIdx.x == 0) L.st = st;
+    }
+    __syncthreads();
+    for (int i0 = st + wave * 64 * IL_BATCH; !cell_first && i0 < en; i0 += n_waves * 64 * IL_BATCH) {
         uint32_t k[IL_BATCH], v[IL_BATCH];
 #pragma unroll
         for (int r = 0; r < IL_BATCH; ++r) {

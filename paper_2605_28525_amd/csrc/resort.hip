@@ -14,6 +14,10 @@
 //            others ("movers") per block;
 //   list     the movers of each block are written, in segment order, at the
 //            block's exclusive prefix of the mover counts;
+//            (inside mpm_step the G2P that wrote the positions does count and
+//            list itself, see k_g2p: stayer counts per block and cell, the
+//            owner part of each block from the build before, movers appended
+//            in any order; both passes are then skipped)
 //   route    one thread per mover: its new block is looked up in the previous
 //            hash table and the block's per-cell mover count incremented, or,
 //            for a block without a previous slot, a slot of a second hash
@@ -100,8 +104,7 @@ constexpr int RS_BATCH = 8;  // 64-particle chunks of a segment whose keys are l
 // the block's mover count goes to rs_cnt[e] (rs_cnt and rs_start serve the
 // mover list first, the entry scan later).
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_rs_count(DevParams P, const uint32_t* __restrict__ keys_prev,
-                                                 const uint32_t* __restrict__ keys_new) {
+__global__ __launch_bounds__(WG) void k_rs_count(DevParams P, const uint32_t* __restrict__ keys_new) {
     constexpr int CB = 2 * DIM, NC = 1 << CB;
     __shared__ unsigned cnt[WG / 64][64];
     const int lane = __lane_id(), w = threadIdx.x >> 6;
@@ -122,24 +125,11 @@ __global__ __launch_bounds__(WG) void k_rs_count(DevParams P, const uint32_t* __
         const int s = s_n, c = c_n;
         fetch(e + stride);
         cnt[w][lane] = 0u;
-        uint32_t owner = ~0u;
+        // owner part of the block's sort key, stored by the previous build (a
+        // block that only held stencil nodes may still receive movers)
+        const uint32_t owner = P.rs_oldblk[e];
         unsigned n_mov = 0u;
-        if (c <= 0) {
-            // a block that only held stencil nodes may still receive movers: its
-            // owner part from the block key (none if outside the binning range)
-            int bc[3], inst = 0;
-            unblock_key<DIM>(P, P.b_keys[e], bc, &inst);
-            bool in_range = true;
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) in_range = in_range && bc[a] >= 0 && bc[a] < P.nblk[a];
-            if (in_range) {
-                const uint32_t bl = DIM == 3 ? ((uint32_t)bc[2] * (uint32_t)P.nblk[1] + (uint32_t)bc[1]) *
-                                                       (uint32_t)P.nblk[0] + (uint32_t)bc[0]
-                                             : (uint32_t)bc[1] * (uint32_t)P.nblk[0] + (uint32_t)bc[0];
-                owner = ((uint32_t)inst << P.blk_bits) | bl;
-            }
-        } else {
-            owner = keys_prev[s] >> CB;
+        if (c > 0) {
             const int end = s + c;
             for (int i0 = s; i0 < end; i0 += 64 * RS_BATCH) {
                 uint32_t k[RS_BATCH];
@@ -162,10 +152,7 @@ __global__ __launch_bounds__(WG) void k_rs_count(DevParams P, const uint32_t* __
             }
         }
         if (lane < NC) P.rs_stay[(size_t)e * NC + lane] = cnt[w][lane];
-        if (lane == 0) {
-            P.rs_oldblk[e] = owner;
-            P.rs_cnt[e] = n_mov;
-        }
+        if (lane == 0) P.rs_cnt[e] = n_mov;
     }
 }
 
@@ -337,13 +324,15 @@ constexpr uint32_t RS_EMPTY = 0xFFFFFFFFu;  // staging slot left to a mover (ind
 // The block's output range (stayers and the movers that join it) is staged in
 // LDS and written out contiguously; the metadata of the wave's next block is
 // loaded while the current one is placed.
-template <int DIM>
+// KEYS: the sorted keys are written too (keys_out); without them the staging
+// holds values only, half the LDS.
+template <int DIM, bool KEYS>
 __global__ __launch_bounds__(WG) void k_rs_place(DevParams P, const uint32_t* __restrict__ keys_new,
                                                  uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
                                                  int n) {
     constexpr int CB = 2 * DIM, NC = 1 << CB;
     __shared__ unsigned run[WG / 64][64];
-    __shared__ uint32_t sk[WG / 64][RS_STAGE], sv[WG / 64][RS_STAGE];
+    __shared__ uint32_t sk[WG / 64][KEYS ? RS_STAGE : 1], sv[WG / 64][RS_STAGE];
     const int lane = __lane_id(), w = threadIdx.x >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
     const int nb = min(P.ctr->nb, P.block_cap);
@@ -395,10 +384,10 @@ __global__ __launch_bounds__(WG) void k_rs_place(DevParams P, const uint32_t* __
                     const unsigned pos = b0 + (unsigned)__popcll(m & lt);
                     if ((m & lt) == 0ull) run[w][cell] = b0 + (unsigned)__popcll(m);
                     if (staged && pos - base < tot) {
-                        sk[w][pos - base] = k[r];
+                        if (KEYS) sk[w][pos - base] = k[r];
                         sv[w][pos - base] = (uint32_t)i;
                     } else if (!staged && pos < (unsigned)n) {
-                        keys_out[pos] = k[r];
+                        if (KEYS) keys_out[pos] = k[r];
                         vals_out[pos] = (uint32_t)i;
                     } else {
                         bad = true;
@@ -410,7 +399,7 @@ __global__ __launch_bounds__(WG) void k_rs_place(DevParams P, const uint32_t* __
             for (unsigned j = lane; j < tot; j += 64) {
                 const uint32_t v = sv[w][j];
                 if (v != RS_EMPTY && base + j < (unsigned)n) {
-                    keys_out[base + j] = sk[w][j];
+                    if (KEYS) keys_out[base + j] = sk[w][j];
                     vals_out[base + j] = v;
                 }
             }
@@ -452,7 +441,7 @@ __global__ __launch_bounds__(WG) void k_rs_place_movers(DevParams P, const uint3
         }
         const unsigned pos = b0 + atomicAdd(&P.rs_in[(size_t)e2 * NC + cell], 1u);
         if (pos < (unsigned)n) {
-            keys_out[pos] = k;
+            if (keys_out) keys_out[pos] = k;
             vals_out[pos] = i;
         } else {
             bad = true;
@@ -478,6 +467,7 @@ __global__ __launch_bounds__(WG) void k_rs_reset(DevParams P, unsigned H) {
             P.h_mask[t] = 0ull;
             P.h_start[t] = -1;
             P.h_end[t] = -1;
+            P.h_entry[t] = -1;
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -517,26 +507,33 @@ hipError_t launch_resort_init(const DevParams& P, unsigned H, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_resort(const DevParams& P, uint32_t* keys_prev, const uint32_t* keys_new, uint32_t* keys_out,
-                         uint32_t* vals_out, uint32_t* movers, int n, unsigned H, unsigned* partials, hipStream_t s) {
+// counted: the G2P that wrote keys_new already stored the stayer counts per
+// previous block and cell, the owner part of each previous block and the
+// mover list (in any order) with its length; count and list are skipped.
+hipError_t launch_resort(const DevParams& P, const uint32_t* keys_new, uint32_t* keys_out, uint32_t* vals_out,
+                         uint32_t* movers, int n, unsigned H, unsigned* partials, hipStream_t s, bool counted) {
     const int gw = grid_for_waves(P.block_cap);
     const int ge = grid_for_waves(2ll * P.block_cap);
     const int gm = (int)std::min<long long>(((long long)n + WG - 1) / WG, 2048);  // grid-stride over the movers
     const int htiles = (int)((H + SCAN_TILE - 1) / SCAN_TILE);
-    if (P.dim == 3)
-        k_rs_count<3><<<gw, WG, 0, s>>>(P, keys_prev, keys_new);
-    else
-        k_rs_count<2><<<gw, WG, 0, s>>>(P, keys_prev, keys_new);
-    hipError_t e = scan_exclusive(P.rs_cnt, P.rs_start, P.block_cap, &P.ctr->nb, partials,
-                                  (unsigned*)&P.ctr->rs_n_mov, s);
-    if (e != hipSuccess) return e;
-    if (P.dim == 3) {
-        k_rs_list<3><<<gw, WG, 0, s>>>(P, keys_new, movers, n);
-        k_rs_route<3><<<gm, WG, 0, s>>>(P, keys_new, movers, n);
-    } else {
-        k_rs_list<2><<<gw, WG, 0, s>>>(P, keys_new, movers, n);
-        k_rs_route<2><<<gm, WG, 0, s>>>(P, keys_new, movers, n);
+    hipError_t e = hipSuccess;
+    if (!counted) {
+        if (P.dim == 3)
+            k_rs_count<3><<<gw, WG, 0, s>>>(P, keys_new);
+        else
+            k_rs_count<2><<<gw, WG, 0, s>>>(P, keys_new);
+        e = scan_exclusive(P.rs_cnt, P.rs_start, P.block_cap, &P.ctr->nb, partials, (unsigned*)&P.ctr->rs_n_mov,
+                           s);
+        if (e != hipSuccess) return e;
+        if (P.dim == 3)
+            k_rs_list<3><<<gw, WG, 0, s>>>(P, keys_new, movers, n);
+        else
+            k_rs_list<2><<<gw, WG, 0, s>>>(P, keys_new, movers, n);
     }
+    if (P.dim == 3)
+        k_rs_route<3><<<gm, WG, 0, s>>>(P, keys_new, movers, n);
+    else
+        k_rs_route<2><<<gm, WG, 0, s>>>(P, keys_new, movers, n);
     k_rs_new_count<<<htiles, WG, 0, s>>>(P, (int)H, partials);
     if (P.dim == 3) {
         k_rs_new_write<3><<<htiles, WG, 0, s>>>(P, (int)H, partials, htiles);
@@ -549,12 +546,18 @@ hipError_t launch_resort(const DevParams& P, uint32_t* keys_prev, const uint32_t
     if (e != hipSuccess) return e;
     if (P.dim == 3) {
         k_rs_offsets<3><<<ge, WG, 0, s>>>(P);
-        k_rs_place<3><<<gw, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n);
+        if (keys_out)
+            k_rs_place<3, true><<<gw, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n);
+        else
+            k_rs_place<3, false><<<gw, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n);
         k_rs_place_movers<3><<<gm, WG, 0, s>>>(P, keys_new, movers, keys_out, vals_out, n);
         k_rs_reset<3><<<4096, WG, 0, s>>>(P, H);
     } else {
         k_rs_offsets<2><<<ge, WG, 0, s>>>(P);
-        k_rs_place<2><<<gw, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n);
+        if (keys_out)
+            k_rs_place<2, true><<<gw, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n);
+        else
+            k_rs_place<2, false><<<gw, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n);
         k_rs_place_movers<2><<<gm, WG, 0, s>>>(P, keys_new, movers, keys_out, vals_out, n);
         k_rs_reset<2><<<4096, WG, 0, s>>>(P, H);
     }

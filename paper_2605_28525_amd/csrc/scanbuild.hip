@@ -3,12 +3,13 @@
 // Algorithms 5-6.  It yields the same active blocks and node masks, with the
 // compact index Phi in ascending block-key order.
 //
-//   k_sb_reset  bounding-box accumulators <- empty;
-//   k_sb_bbox   bounding box of the owner blocks of all particles (wave min/max,
-//               one atomic per wave and axis);
-//   k_sb_box    the mask domain: the box grown by one block on each upper side
-//               (a stencil spills only upward), its extents and volume m, all
-//               on the device (no host read-back);
+//   k_sb_bbox   bounding box of the owner blocks of all particles: each of a
+//               fixed number of workgroups reduces its share (wave shuffles,
+//               then LDS) and writes one partial box, no atomics;
+//   k_sb_box    one workgroup reduces the partial boxes; the mask domain is the
+//               box grown by one block on each upper side (a stencil spills
+//               only upward), its extents and volume m, all on the device (no
+//               host read-back);
 //   k_sb_zero   occupancy of the m blocks of the domain <- 0;
 //   k_sb_occ    per owner block, the 64-bit occupancy of its base cells (lanes
 //               of a wave with the same owner merged by ballot, one atomicOr);
@@ -101,22 +102,10 @@ __device__ __forceinline__ long long sb_index(const SbBox& B, int c0, int c1, in
     return ((long long)c0 * B.ext[1] + c1) * B.ext[2] + c2;
 }
 
-__global__ __launch_bounds__(64) void k_sb_reset(SbBox* box) {
-    if (threadIdx.x < 3) {
-        box->lo[threadIdx.x] = INT_MAX;
-        box->hi[threadIdx.x] = -1;
-        box->ext[threadIdx.x] = 0;
-    }
-    if (threadIdx.x == 0) {
-        box->m = 0;
-        box->too_big = 0;
-        box->total = 0u;
-    }
-}
-
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_sb_bbox(DevParams P, const float* __restrict__ x,
-                                                const uint32_t* __restrict__ keys, int n, SbBox* box) {
+                                                const uint32_t* __restrict__ keys, int n, int* __restrict__ bbp) {
+    __shared__ int red[WG / 64][6];
     int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {-1, -1, -1};
     for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
         int bc[3], cell;
@@ -128,28 +117,71 @@ __global__ __launch_bounds__(WG) void k_sb_bbox(DevParams P, const float* __rest
         }
     }
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) {
+    for (int a = 0; a < 3; ++a) {
         for (int m = 32; m >= 1; m >>= 1) {
             lo[a] = min(lo[a], __shfl_xor(lo[a], m));
             hi[a] = max(hi[a], __shfl_xor(hi[a], m));
         }
     }
+    const int w = threadIdx.x >> 6;
     if (__lane_id() == 0) {
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            if (hi[a] >= 0) {
-                atomicMin(&box->lo[a], lo[a]);
-                atomicMax(&box->hi[a], hi[a]);
-            }
+        for (int a = 0; a < 3; ++a) {
+            red[w][a] = lo[a];
+            red[w][3 + a] = hi[a];
         }
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int t = threadIdx.x;
+        int v = red[0][t];
+        for (int q = 1; q < WG / 64; ++q) v = t < 3 ? min(v, red[q][t]) : max(v, red[q][t]);
+        bbp[blockIdx.x * 8 + t] = v;
     }
 }
 
-// Extents of the mask domain; volume 0 when there is no particle or when it
-// exceeds max_m (then too_big is set and nothing further is done).
+// The bounding box from the partial boxes, and the extents of the mask domain;
+// volume 0 when there is no particle or when it exceeds max_m (then too_big is
+// set and nothing further is done).  The active-block total is set by the
+// scan that follows.
 template <int DIM>
-__global__ __launch_bounds__(64) void k_sb_box(DevParams P, SbBox* box, long long max_m) {
+__global__ __launch_bounds__(WG) void k_sb_box(DevParams P, const int* __restrict__ bbp, int parts, SbBox* box,
+                                               long long max_m) {
+    __shared__ int red[WG / 64][6];
+    int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {-1, -1, -1};
+    for (int q = threadIdx.x; q < parts; q += WG) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = min(lo[a], bbp[q * 8 + a]);
+            hi[a] = max(hi[a], bbp[q * 8 + 3 + a]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        for (int m = 32; m >= 1; m >>= 1) {
+            lo[a] = min(lo[a], __shfl_xor(lo[a], m));
+            hi[a] = max(hi[a], __shfl_xor(hi[a], m));
+        }
+    }
+    const int w = threadIdx.x >> 6;
+    if (__lane_id() == 0) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            red[w][a] = lo[a];
+            red[w][3 + a] = hi[a];
+        }
+    }
+    __syncthreads();
     if (threadIdx.x != 0) return;
+    for (int a = 0; a < 3; ++a) {
+        box->lo[a] = red[0][a];
+        box->hi[a] = red[0][3 + a];
+        for (int q = 1; q < WG / 64; ++q) {
+            box->lo[a] = min(box->lo[a], red[q][a]);
+            box->hi[a] = max(box->hi[a], red[q][3 + a]);
+        }
+    }
+    box->too_big = 0;
     long long m = 1;
     for (int a = 0; a < 3; ++a) {
         if (a >= DIM) {
@@ -354,18 +386,17 @@ int sb_grid(long long items, int cap_wgs) {
 // else reads sorted keys.
 hipError_t sb_mark(const DevParams& P, const float* x, const uint32_t* keys, int n, const SbScratch& S,
                    hipStream_t s) {
-    k_sb_reset<<<1, 64, 0, s>>>(S.box);
     const int gp = sb_grid(n, 4096);
     const int gm = sb_grid(S.max_m, 8192);
     if (P.dim == 3) {
-        if (n > 0) k_sb_bbox<3><<<gp, WG, 0, s>>>(P, x, keys, n, S.box);
-        k_sb_box<3><<<1, 64, 0, s>>>(P, S.box, S.max_m);
+        k_sb_bbox<3><<<SB_BBOX_WGS, WG, 0, s>>>(P, x, keys, n, S.bbp);
+        k_sb_box<3><<<1, WG, 0, s>>>(P, S.bbp, SB_BBOX_WGS, S.box, S.max_m);
         k_sb_zero<<<gm, WG, 0, s>>>(S.box, S.occ);
         if (n > 0) k_sb_occ<3><<<gp, WG, 0, s>>>(P, x, keys, n, S.box, S.occ, S.seg_lo, S.seg_hi);
         k_sb_flag<3><<<gm, WG, 0, s>>>(S.box, S.occ, S.flag);
     } else {
-        if (n > 0) k_sb_bbox<2><<<gp, WG, 0, s>>>(P, x, keys, n, S.box);
-        k_sb_box<2><<<1, 64, 0, s>>>(P, S.box, S.max_m);
+        k_sb_bbox<2><<<SB_BBOX_WGS, WG, 0, s>>>(P, x, keys, n, S.bbp);
+        k_sb_box<2><<<1, WG, 0, s>>>(P, S.bbp, SB_BBOX_WGS, S.box, S.max_m);
         k_sb_zero<<<gm, WG, 0, s>>>(S.box, S.occ);
         if (n > 0) k_sb_occ<2><<<gp, WG, 0, s>>>(P, x, keys, n, S.box, S.occ, S.seg_lo, S.seg_hi);
         k_sb_flag<2><<<gm, WG, 0, s>>>(S.box, S.occ, S.flag);
@@ -377,9 +408,8 @@ hipError_t sb_mark(const DevParams& P, const float* x, const uint32_t* keys, int
 }  // namespace
 
 size_t sb_scratch_bytes(long long max_m) {
-    // box header, occupancy (u64), flags and Phi (u32), scan partials; segment
-    // bounds (2 x i32) are added by the step build's owner
-    return 256 + (size_t)max_m * (8 + 4 + 4) + (size_t)scan_partials_size((int)max_m) * 4 + 256;
+    // segment bounds (2 x i32 per block) are allocated by the step build's owner
+    return sb_scratch_size(max_m);
 }
 
 SbScratch sb_carve(void* base, long long max_m, int* seg_lo, int* seg_hi) {
@@ -387,6 +417,8 @@ SbScratch sb_carve(void* base, long long max_m, int* seg_lo, int* seg_hi) {
     char* p = (char*)base;
     S.box = (SbBox*)p;
     p += 256;
+    S.bbp = (int*)p;
+    p += (size_t)SB_BBOX_WGS * 8 * sizeof(int);
     S.occ = (uint64_t*)p;
     p += (size_t)max_m * 8;
     S.flag = (unsigned*)p;

@@ -57,7 +57,7 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
     // The count, first sorted position and key of the next block are loaded
     // while the current one is processed (a dense grid has no key table: its
     // key is the linear block index).
-    int cnt_n = 0, st_n = 0;
+    int cnt_n = 0, st_n = 0, ent_n = -1;
     uint64_t key_n = 0;
     auto fetch_meta = [&](int bb) {
         if (bb < nb) {
@@ -67,11 +67,12 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
             cnt_n = P.b_count[bb];
             st_n = P.b_start[bb];
             key_n = P.dense ? (uint64_t)bb : P.b_keys[bb];
+            ent_n = P.b_entry ? P.b_entry[bb] : -1;
         }
     };
     fetch_meta(blockIdx.x);
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
-        const int cnt = cnt_n, st = st_n;
+        const int cnt = cnt_n, st = st_n, ent = ent_n;
         const uint64_t key = key_n;
         fetch_meta(b + gridDim.x);
         if (cnt <= 0) continue;
@@ -93,7 +94,10 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
         // the base cells), with the block's permutation staged in LDS by the
         // same loads; each lane records where G2P will store its cell's
         // particles as it visits them (osrc)
-        interleave_setup<DIM>(il, skeys, st, en, order, ord, P2G_ORDER_STAGE);
+        // after an incremental re-sort the block's cell ranges are its entry's
+        // row of first positions; otherwise they are counted from the keys
+        interleave_setup<DIM>(il, skeys, st, en, order, ord, P2G_ORDER_STAGE,
+                              ent >= 0 ? P.rs_off + (size_t)ent * NC : nullptr);
         if (lane < T::NB) nbr[lane] = nbv;
         float acc[NK][4];
 #pragma unroll
@@ -282,9 +286,8 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
 #pragma unroll
             for (int r = 0; r < (T::N + 63) / 64; ++r) {
                 const int t = min(lane + 64 * r, T::N - 1);
-                const int I = t % T::E;
-                const int J = (t / T::E) % T::E;
-                const int K = DIM == 3 ? t / (T::E * T::E) : 0;
+                int I, J, K;
+                T::store_node(t, &I, &J, &K);
                 const int tp = T::pad(I, J, K);
                 P.tiles[(size_t)b * T::N + t] =
                     make_float4(tile[0][tp], tile[1][tp], DIM == 3 ? tile[2][tp] : 0.f, tile[3][tp]);
@@ -336,7 +339,7 @@ __global__ __launch_bounds__(WG) void k_p2g_gather(DevParams P) {
             const int dx = d & 1, dy = (d >> 1) & 1, dz = (d >> 2) & 1;
             const bool reach = (!dx || I < 2) && (!dy || J < 2) && (DIM == 2 || !dz || K < 2);
             if (src[d] >= 0 && reach && lane < T::NPB) {
-                const int t = (I + 4 * dx) + T::E * ((J + 4 * dy) + (DIM == 3 ? T::E * (K + 4 * dz) : 0));
+                const int t = T::store_index(I + 4 * dx, J + 4 * dy, K + 4 * dz);
                 const float4 g = P.tiles[(size_t)src[d] * T::N + t];
                 sum.x += g.x;
                 sum.y += g.y;
@@ -694,10 +697,20 @@ struct G2POut {
     float* tau;
     uint32_t* id;
     uint32_t* inst;
-    uint32_t* keys;  // optional: the sort key of each new position (the next step's binning)
+    uint32_t* keys;    // optional: the sort key of each new position (the next step's binning)
+    uint32_t* movers;  // optional (with keys): the next incremental re-sort's counting, see k_g2p
 };
 
 // GS threads per workgroup, work items of at most 2 GS particles.
+//
+// With out.keys the kernel also bins each new position (the next build's
+// sort key).  With out.movers as well it does the counting of the next
+// incremental re-sort for the block of each item: the particles whose new key
+// keeps the block's owner ("stayers") are counted per base cell in LDS and
+// the counts stored to the block's row of rs_stay (added, for blocks split
+// over several items, to the row the build cleared); the others ("movers")
+// are appended to out.movers at a position claimed once per wave from the
+// counter rs_n_mov.
 template <int DIM, int GS>
 __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, int n,
                                             const uint32_t* __restrict__ osrc) {
@@ -709,6 +722,9 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
     constexpr int MAXI = 2 * GS;
     __shared__ float xs[DIM][MAXI];
     __shared__ float fs[DD][MAXI];
+    constexpr int NC = 1 << (2 * DIM);
+    __shared__ unsigned scnt[NC];  // stayers per base cell of the current item's block
+    if (threadIdx.x < NC) scnt[threadIdx.x] = 0u;
     const int n_work = min(P.ctr->n_work, P.work_cap);
     const float dx = P.dxf, inv_dx = P.inv_dxf;
     const float cscale = 4.f * inv_dx * inv_dx;  // D_p^{-1} = (4/dx^2) I for quadratic B-splines
@@ -732,6 +748,7 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
     uint32_t pq[PER];
     int pphi[TPER];
     uint64_t pkey = 0;
+    unsigned pch = 0;
     float px[PER][DIM], pF[PER][DD];
     uint32_t pid[PER], pin[PER];
     float4 pt[TPER];
@@ -765,6 +782,7 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
         const uint64_t* kp = P.dense ? reinterpret_cast<const uint64_t*>(P.b_nbr + (size_t)R.blk * T::NB)
                                      : P.b_keys + R.blk;
         pkey = *kp;
+        pch = P.b_chunks[R.blk];  // work items of the block
     };
     auto fetch_data = [&]() {
 #pragma unroll
@@ -798,6 +816,7 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
     while (w < n_work) {
         const int s = cur.s, L = min(cur.e - cur.s, MAXI);
         const uint64_t key = P.dense ? (uint64_t)cur.blk : pkey;
+        const unsigned chunks = pch;
         const InstMat mat = pmat;
         // phase 0: stage the gathered item in LDS; ids travel with the
         // particles (output positions s .. s+L-1 are contiguous, so every
@@ -830,6 +849,12 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
             linear_to_block<DIM>(P, (uint32_t)key, org);
         else
             unblock_key<DIM>(P, key, org, &inst);
+        // owner part of the block's sort key (stayers keep it)
+        const uint32_t own =
+            ((uint32_t)inst << P.blk_bits) |
+            (DIM == 3 ? ((uint32_t)org[2] * (uint32_t)P.nblk[1] + (uint32_t)org[1]) * (uint32_t)P.nblk[0] +
+                            (uint32_t)org[0]
+                      : (uint32_t)org[1] * (uint32_t)P.nblk[0] + (uint32_t)org[0]);
 #pragma unroll
         for (int a = 0; a < 3; ++a) org[a] *= BLK;
         const float dt = mat.dt;
@@ -922,8 +947,26 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
                 // same float64 arithmetic as k_bin on the stored float32 value);
                 // every particle of an item shares the owner block's instance
                 unsigned bad = 0;
-                out.keys[o] = bin_key<DIM>(P, xn, (uint32_t)inst, &bad);
+                const uint32_t nk = bin_key<DIM>(P, xn, (uint32_t)inst, &bad);
+                out.keys[o] = nk;
                 if (bad) raise_flag(P.ctr, bad);
+                if (out.movers) {
+                    const bool stay = (nk >> (2 * DIM)) == own;
+                    if (stay) atomicAdd(&scnt[nk & (NC - 1)], 1u);
+                    // movers of the wave's active lanes: one claim per wave
+                    const unsigned long long mv = __ballot(!stay);
+                    if (mv) {
+                        const int leader = __ffsll((long long)mv) - 1;
+                        const int lane = __lane_id();
+                        unsigned base = 0u;
+                        if (lane == leader) base = atomicAdd((unsigned*)&P.ctr->rs_n_mov, (unsigned)__popcll(mv));
+                        base = (unsigned)__shfl((int)base, leader);
+                        if (!stay) {
+                            const unsigned slot = base + (unsigned)__popcll(mv & ((1ull << lane) - 1ull));
+                            if (slot < (unsigned)n) out.movers[slot] = (uint32_t)o;
+                        }
+                    }
+                }
             }
 #pragma unroll
             for (int a = 0; a < DIM; ++a)
@@ -946,6 +989,15 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
             if (!finite) raise_flag(P.ctr, MPM_FLAG_NAN);
         }
         __syncthreads();
+        if (out.movers && threadIdx.x < NC) {
+            const unsigned c = scnt[threadIdx.x];
+            unsigned* row = P.rs_stay + (size_t)cur.blk * NC + threadIdx.x;
+            if (chunks == 1u)
+                *row = c;
+            else if (c)
+                atomicAdd(row, c);
+            scnt[threadIdx.x] = 0u;  // ordered before the next item's counting by the barriers between
+        }
         fetch_data();  // in flight during phase 2
         // phase 2: constitutive update (its register live range is separate)
 #pragma unroll 1
@@ -1005,9 +1057,9 @@ hipError_t launch_grid_update(const DevParams& P, long long n_nodes_host, int gr
 hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, const uint32_t* id_in,
                       const uint32_t* inst_in, float* x_out, float* v_out, float* C_out, float* F_out, float* tau_out,
                       uint32_t* id_out, uint32_t* inst_out, int n, const uint32_t* osrc, int block_size,
-                      int grid_blocks, hipStream_t s, uint32_t* keys_out) {
+                      int grid_blocks, hipStream_t s, uint32_t* keys_out, uint32_t* movers_out) {
     G2PIn in{x_in, F_in, id_in, inst_in};
-    G2POut out{x_out, v_out, C_out, F_out, tau_out, id_out, inst_out, keys_out};
+    G2POut out{x_out, v_out, C_out, F_out, tau_out, id_out, inst_out, keys_out, keys_out ? movers_out : nullptr};
     if (2 * block_size < P.chunk) return hipErrorInvalidValue;  // work items must fit the LDS staging
     switch (block_size * 4 + P.dim) {
         case 64 * 4 + 3: k_g2p<3, 64><<<grid_blocks, 64, 0, s>>>(P, in, out, n, osrc); break;

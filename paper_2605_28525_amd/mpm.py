@@ -408,11 +408,14 @@ class ParticleSet:
     def ids(self) -> np.ndarray:
         return self.id.detach().cpu().numpy().view(np.uint32)
 
-    def view(self) -> mpm_particles:
+    def view(self, with_id: bool = True) -> mpm_particles:
+        """The ``mpm_particles`` of this set; without the id array the library
+        carries no identities (the order from mpm_get_order still holds)."""
         p = mpm_particles()
         p.n = self.n
         p.x, p.v, p.C = self.x.data_ptr(), self.v.data_ptr(), self.C.data_ptr()
-        p.F, p.tau, p.id = self.F.data_ptr(), self.tau.data_ptr(), self.id.data_ptr()
+        p.F, p.tau = self.F.data_ptr(), self.tau.data_ptr()
+        p.id = self.id.data_ptr() if with_id else None
         p.inst = self.inst.data_ptr() if self.inst is not None else None
         return p
 
@@ -433,6 +436,7 @@ class Simulation:
                                                hash_capacity_log2=hash_capacity_log2, flags=flags)
             dim = w.dim
         self.ctx = mpm_create(self.params)
+        self.carry_id = True   # pass the id arrays to the library (particles keep their identity)
         self.a = ParticleSet.from_arrays(w.state(), device=device, inst=inst)
         self.b = ParticleSet(dim, w.n, device, with_inst=inst is not None)
 
@@ -444,7 +448,7 @@ class Simulation:
         self.a.id.copy_(torch.from_numpy(ids))
 
     def step(self, n_steps: int = 1, stream=None):
-        mpm_step(self.ctx, self.a.view(), self.b.view(), n_steps, stream)
+        mpm_step(self.ctx, self.a.view(self.carry_id), self.b.view(self.carry_id), n_steps, stream)
         if n_steps % 2 == 1:
             self.a, self.b = self.b, self.a
 

@@ -287,13 +287,16 @@ SLIDE_MU = float(np.tan(np.deg2rad(15.0)))   # Coulomb coefficient of the slidin
 
 
 def sliding_block(theta_deg: float, seed: int = 21, dx: float = 0.02, block_cells=(10, 5, 5),
-                  E: float = 5.0e4, rho: float = 1000.0) -> Workload:
+                  E: float = 5.0e5, rho: float = 1000.0) -> Workload:
     """Elastic block released at rest on a plane inclined at ``theta_deg`` about the
     y axis: terrain z = 0.6 m - x tan(theta) over a 40x16x40-cell grid at dx = 0.02 m,
     Coulomb friction mu = tan 15 deg.  The block, 0.2 x 0.1 x 0.1 m (10x5x5 cells
     of dx along slope, across and normal), holds 8 particles per dx^3, stratified-
     jittered in the slope's own frame, the lowest ones within dx/2 above the plane;
-    its upslope face starts 0.18 m down the plane from its x = 0 edge.
+    its upslope face starts 0.18 m down the plane from its x = 0 edge.  E = 5e5 Pa
+    (nu = 0.3, rho = 1000 kg/m^3): stiff enough that the block's elastic settling
+    after its release moves it by millimetres, so that it behaves as the rigid
+    block of the closed form.
     ``meta``: the downslope unit vector and the slope angle."""
     th = np.deg2rad(theta_deg)
     rng = np.random.default_rng(seed)

@@ -1,6 +1,7 @@
 """GPU at the landslide's full size, in the launch configuration bench.py times
 (20,000,000 particles, 2048 x 2048 x 256 cells, block capacity 2^18, shape
-chosen by mpm_autotune), after 10 steps.
+chosen by mpm_autotune), after 10 steps and after 2500 steps (half of the
+configuration's 5000, the slide spread out and accelerated to about 20 m/s).
 
 Properties of the whole step that hold at any size: the status word is clear,
 the output is a permutation of the input carrying the ids, every output is
@@ -33,14 +34,15 @@ def _base(x, dx):
     return np.floor(s).astype(np.int64)
 
 
-def test_landslide_full_size():
+@pytest.mark.parametrize("steps_before", [10, 2500])
+def test_landslide_full_size(steps_before):
     from paper_2605_28525_amd import mpm as M
     w = wl.landslide()
     n, d, dx = w.n, w.dim, w.dx
-    print("CASE landslide full size", n, flush=True)
+    print("CASE landslide full size", n, "after", steps_before, "steps", flush=True)
     sim = M.Simulation(w, block_capacity=1 << 18)
     try:
-        sim.step(10)
+        sim.step(steps_before)
         M.mpm_autotune(sim.ctx, sim.a.view(), sim.b.view())
         parts = gpu_step_parts(sim)
     finally:
