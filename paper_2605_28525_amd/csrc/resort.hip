@@ -334,7 +334,6 @@ __global__ __launch_bounds__(WG) void k_rs_place(DevParams P, const uint32_t* __
     __shared__ unsigned run[WG / 64][64];
     __shared__ uint32_t sk[WG / 64][KEYS ? RS_STAGE : 1], sv[WG / 64][RS_STAGE];
     const int lane = __lane_id(), w = threadIdx.x >> 6;
-    const unsigned long long lt = (1ull << lane) - 1ull;
     const int nb = min(P.ctr->nb, P.block_cap);
     const int stride = gridDim.x * (WG / 64);
     int s_n = 0, c_n = 0;
@@ -378,11 +377,11 @@ __global__ __launch_bounds__(WG) void k_rs_place(DevParams P, const uint32_t* __
                 const int i = i0 + r * 64 + lane;
                 const bool stay = i < end && (k[r] >> CB) == owner;
                 const uint32_t cell = k[r] & (NC - 1);
-                const unsigned long long m = match_bits<CB>(cell, stay);
                 if (stay) {
-                    const unsigned b0 = run[w][cell];
-                    const unsigned pos = b0 + (unsigned)__popcll(m & lt);
-                    if ((m & lt) == 0ull) run[w][cell] = b0 + (unsigned)__popcll(m);
+                    // next position of the cell: an LDS atomic on its counter
+                    // (lanes hitting one counter are served one after another,
+                    // so any order of them is a valid placement)
+                    const unsigned pos = atomicAdd(&run[w][cell], 1u);
                     if (staged && pos - base < tot) {
                         if (KEYS) sk[w][pos - base] = k[r];
                         sv[w][pos - base] = (uint32_t)i;
