@@ -98,12 +98,14 @@ typedef struct mpm_ctx mpm_ctx;
                                     sparse build of a context without MPM_FLAG_ADJOINT
                                     that follows a build of the same number of
                                     particles re-sorts incrementally: particles that
-                                    keep their owner block keep their order, the
+                                    keep their owner block stay in its range, the
                                     others are routed through the previous build's
                                     hash table.  Either way each owner block's
                                     particles are contiguous with base cells
-                                    ascending; block order and the order of movers
-                                    inside a cell differ between the two. */
+                                    ascending; block order and the order of the
+                                    particles inside a cell differ between the
+                                    two (the re-sort's order inside a cell is not
+                                    fixed from run to run). */
 #define MPM_FLAG_DETERMINISTIC_ORDER 8
                                  /* Phi in ascending order of the Eq. 22 block key
                                     (lexicographic (i, j, k), instance first in an

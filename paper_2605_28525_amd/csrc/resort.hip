@@ -26,10 +26,11 @@
 //            after the previous blocks;
 //   offsets  per entry, particles per base cell = stayers + movers; exclusive
 //            scans over the entries (first position) and over the cells;
-//   place    one wave per previous block: stayers keep their relative order
-//            (per-cell ranks from a wave-wide match); then one thread per
-//            mover: movers go after the stayers of their cell, in the order
-//            their atomic slot claims land;
+//   place    one wave per previous block: each stayer takes the next
+//            position of its cell from an LDS counter (an atomic, so stayers
+//            of one cell land in any order); then one thread per mover:
+//            movers go after the stayers of their cell, in the order their
+//            atomic slot claims land;
 //   reset    the per-entry mover counts and the second table are cleared for
 //            the next build, and the block hash for the insertion that
 //            follows.
