@@ -71,6 +71,7 @@ struct mpm_ctx {
     uint32_t* nh_cnt = nullptr;
     int* nh_idx = nullptr;
     uint32_t* nh_owner = nullptr;
+    uint32_t* rs_new = nullptr;
     int* h_entry = nullptr;
     int* b_entry = nullptr;
     uint32_t* order = nullptr;
@@ -153,6 +154,7 @@ void free_capacity_buffers(mpm_ctx* c) {
     dfree(c->nh_cnt);
     dfree(c->nh_idx);
     dfree(c->nh_owner);
+    dfree(c->rs_new);
     dfree(c->h_entry);
     dfree(c->b_entry);
     dfree(c->det.keys);
@@ -308,6 +310,7 @@ void fill_params(mpm_ctx* c) {
     P.nh_cnt = c->nh_cnt;
     P.nh_idx = c->nh_idx;
     P.nh_owner = c->nh_owner;
+    P.rs_new = c->rs_new;
     P.h_entry = c->h_entry;
     P.b_entry = c->b_entry;
     fill_material(c);
@@ -382,6 +385,7 @@ int alloc_capacity_buffers(mpm_ctx* c) {
         e = e ? e : dalloc(&c->nh_cnt, H * NPB);
         e = e ? e : dalloc(&c->nh_idx, H);
         e = e ? e : dalloc(&c->nh_owner, H);
+        e = e ? e : dalloc(&c->rs_new, cap);
         e = e ? e : dalloc(&c->h_entry, H);
         e = e ? e : dalloc(&c->b_entry, cap);
     }

@@ -385,8 +385,8 @@ __global__ __launch_bounds__(WG) void k_block_setup(DevParams P) {
         if (P.rs_stay) {
             // for the next incremental re-sort, when a G2P bins its output:
             // the owner part of the block's sort key, and cleared per-cell
-            // stayer counts where G2P will not store them whole (no particle,
-            // or several work items adding theirs)
+            // stayer counts and entry total where G2P will not store them
+            // whole (no particle, or several work items adding theirs)
             if (j == 0) {
                 bool in_range = inst < max(P.n_inst, 1);
 #pragma unroll
@@ -400,8 +400,10 @@ __global__ __launch_bounds__(WG) void k_block_setup(DevParams P) {
                 }
                 P.rs_oldblk[b] = owner;
             }
-            if (chunks != 1u)
+            if (chunks != 1u) {
                 for (int c = j; c < NC; c += LPB) P.rs_stay[(size_t)b * NC + c] = 0u;
+                if (j == 0) P.rs_cnt[b] = 0u;
+            }
         }
     }
     if (P.rs_stay && blockIdx.x == 0 && threadIdx.x == 0) P.ctr->rs_n_mov = 0;

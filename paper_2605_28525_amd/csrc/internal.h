@@ -111,15 +111,16 @@ struct DevParams {
     // incremental re-sort (resort.hip): per entry (previous block, then new
     // block) and base cell, NC = 4^d columns
     uint32_t* rs_stay;    // stayers per previous block and cell
-    uint32_t* rs_in;      // movers per entry and cell, then the movers placed so far
+    uint32_t* rs_in;      // movers per entry and cell (counted down to zero as they are placed)
     uint32_t* rs_off;     // first sorted position per entry and cell
-    unsigned* rs_cnt;     // particles per entry
+    unsigned* rs_cnt;     // particles per entry (stayers from G2P or the count pass, plus movers)
     unsigned* rs_start;   // first sorted position per entry
     uint32_t* rs_oldblk;  // owner-block part of the sort key of each entry (~0: empty previous block)
     uint64_t* nh_keys;    // second hash table (same size as the block table): blocks
     uint32_t* nh_cnt;     //   with no previous slot, their movers per cell,
     int* nh_idx;          //   their entry index
     uint32_t* nh_owner;   //   and the owner-block part of their sort key
+    uint32_t* rs_new;     // second-table slots in the order of their claims (block_cap entries)
     int* h_entry;         // re-sort entry of each hash slot's owner block (-1: none)
     int* b_entry;         // re-sort entry of each compact block (-1: none): its cell
                           // ranges are the entry's row of rs_off

@@ -161,9 +161,11 @@ __device__ __forceinline__ void jacobi_sym(float (*A)[3], float (*U)[3]) {
 // (a few cache lines per wave instruction, each used in part).  G2P therefore
 // stores a block's particles rank-major: the first particle of every non-empty
 // cell (cells in order), then every second particle, and so on for ranks below
-// IL_ROUNDS; particles of higher rank follow cell by cell.  The next sort is
+// IL_ROUNDS; particles of higher rank follow cell by cell.  The radix sort is
 // stable, so a cell that keeps its particles hands them back to its P2G lane
-// in the same rank order, and consecutive lanes load consecutive addresses.
+// in the same rank order, and consecutive lanes load consecutive addresses;
+// the incremental re-sort may permute a cell's particles among its ranks,
+// which keeps a wave's loads inside the block's range of the set.
 constexpr int IL_ROUNDS = 32;
 
 template <int DIM>

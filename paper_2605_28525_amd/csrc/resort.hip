@@ -15,25 +15,28 @@
 //   list     the movers of each block are written, in segment order, at the
 //            block's exclusive prefix of the mover counts;
 //            (inside mpm_step the G2P that wrote the positions does count and
-//            list itself, see k_g2p: stayer counts per block and cell, the
-//            owner part of each block from the build before, movers appended
-//            in any order; both passes are then skipped)
+//            list itself, see k_g2p: stayer counts per block and cell and
+//            their sum, the owner part of each block from the build before,
+//            movers appended in any order; both passes are then skipped)
 //   route    one thread per mover: its new block is looked up in the previous
-//            hash table and the block's per-cell mover count incremented, or,
-//            for a block without a previous slot, a slot of a second hash
-//            table is claimed and counted;
-//   new      compaction of the second table: its blocks become the entries
-//            after the previous blocks;
-//   offsets  per entry, particles per base cell = stayers + movers; exclusive
-//            scans over the entries (first position) and over the cells;
-//   place    one wave per previous block: each stayer takes the next
-//            position of its cell from an LDS counter (an atomic, so stayers
-//            of one cell land in any order); then one thread per mover:
-//            movers go after the stayers of their cell, in the order their
-//            atomic slot claims land;
-//   reset    the per-entry mover counts and the second table are cleared for
-//            the next build, and the block hash for the insertion that
-//            follows.
+//            hash table and the block's per-cell mover count and particle
+//            count incremented, or, for a block without a previous slot, a
+//            slot of a second hash table is claimed (the claiming thread
+//            appends it to a list) and counted;
+//   new      one wave per listed slot: the second table's blocks become the
+//            entries after the previous blocks, in claim order;
+//   totals   (only without the G2P's counting) particles per entry = stayers
+//            + movers; then an exclusive scan over the entries gives each
+//            entry's first position;
+//   place    one wave per entry: first positions of its cells (a wave scan of
+//            stayers + movers per cell); for a previous block each stayer
+//            then takes the next position of its cell from an LDS counter (an
+//            atomic, so stayers of one cell land in any order); then one
+//            thread per mover: movers go after the stayers of their cell, each
+//            taking the position its atomic decrement of the cell's mover
+//            count names (which leaves the counts at zero for the next build);
+//   reset    the second table is cleared for the next build, and the block
+//            hash for the insertion that follows.
 // Cost: two reads of the new keys and one write of keys and values, against
 // 2-4 full read/write passes of the radix sort.  The per-block kernels only
 // stream keys; the dependent lookups of the few movers run one per thread, so
@@ -70,15 +73,18 @@ __device__ __forceinline__ uint64_t owner_block_key(const DevParams& P, uint32_t
     return block_key<DIM>(P, bc[0], bc[1], bc[2], inst);
 }
 
-// Second table: same size, hash and probing as the block table.
-__device__ int nh_insert(const DevParams& P, uint64_t K) {
+// Second table: same size, hash and probing as the block table.  *claimed is
+// set for the one caller whose CAS stored the key.
+__device__ int nh_insert(const DevParams& P, uint64_t K, bool* claimed) {
     unsigned s = (unsigned)mix64(K) & P.h_mask_bits;
+    *claimed = false;
     for (int r = 0; r < P.n_probe; ++r) {
         const uint64_t cur = __hip_atomic_load(&P.nh_keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (cur == K) return (int)s;
         if (cur == EMPTY_KEY) {
             const uint64_t old = atomicCAS((unsigned long long*)&P.nh_keys[s], (unsigned long long)EMPTY_KEY,
                                            (unsigned long long)K);
+            *claimed = old == EMPTY_KEY;
             if (old == EMPTY_KEY || old == K) return (int)s;
         }
         s = (s + 1) & P.h_mask_bits;
@@ -205,11 +211,18 @@ __global__ __launch_bounds__(WG) void k_rs_route(DevParams P, const uint32_t* __
         const int phi = hash_lookup(P, K);
         if (phi >= 0) {
             atomicAdd(&P.rs_in[(size_t)phi * NC + cell], 1u);
+            atomicAdd(&P.rs_cnt[phi], 1u);
         } else {
-            const int slot = nh_insert(P, K);
+            bool claimed;
+            const int slot = nh_insert(P, K, &claimed);
             if (slot >= 0) {
                 atomicAdd(&P.nh_cnt[(size_t)slot * NC + cell], 1u);
                 P.nh_owner[slot] = k >> CB;  // the same value from every mover of the block
+                if (claimed) {
+                    // the slot joins the list of new blocks (claim order)
+                    const int j = atomicAdd(&P.ctr->rs_n_new, 1);
+                    if (j < P.block_cap) P.rs_new[j] = (uint32_t)slot;
+                }
             } else {
                 raise_flag(P.ctr, MPM_FLAG_OVERFLOW);
             }
@@ -217,65 +230,39 @@ __global__ __launch_bounds__(WG) void k_rs_route(DevParams P, const uint32_t* __
     }
 }
 
-// new: occupied slots of the second table, counted per tile ...
-__global__ __launch_bounds__(WG) void k_rs_new_count(DevParams P, int H, unsigned* __restrict__ partials) {
-    __shared__ unsigned lds[WG / 64];
-    const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
-    unsigned s = 0;
-#pragma unroll
-    for (int j = 0; j < SCAN_ITEMS; ++j) {
-        const int idx = base + j;
-        if (idx < H && P.nh_keys[idx] != EMPTY_KEY) ++s;
-    }
-    unsigned tot;
-    wg_excl_scan(s, lds, &tot);
-    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
-}
-
-// ... then numbered after the previous blocks (slot order), with their mover
-// counts moved into the entry rows.
+// new: one wave per block that the route claimed in the second table, in claim
+// order; block j becomes entry nb + j, with its mover counts (cleared in the
+// table) as the entry's row and their sum as its particle count.
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_rs_new_write(DevParams P, int H, const unsigned* __restrict__ partials,
-                                                     int tiles) {
+__global__ __launch_bounds__(WG) void k_rs_new_write(DevParams P) {
     constexpr int NC = 1 << (2 * DIM);
-    __shared__ unsigned lds[WG / 64];
-    unsigned before, total;
-    tile_offset(partials, blockIdx.x, tiles, lds, &before, &total);
-    if (blockIdx.x == 0 && threadIdx.x == 0) P.ctr->rs_n_new = total;
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
     const int nb = min(P.ctr->nb, P.block_cap);
     const int max_ent = 2 * P.block_cap;
-    const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
-    bool occ[SCAN_ITEMS];
-    unsigned s = 0;
-#pragma unroll
-    for (int j = 0; j < SCAN_ITEMS; ++j) {
-        const int idx = base + j;
-        occ[j] = idx < H && P.nh_keys[idx] != EMPTY_KEY;
-        s += occ[j];
-    }
-    unsigned tot;
-    unsigned j = wg_excl_scan(s, lds, &tot) + before;
-    bool over = false;
-#pragma unroll
-    for (int q = 0; q < SCAN_ITEMS; ++q) {
-        if (!occ[q]) continue;
-        const int slot = base + q;
-        const int e = nb + (int)j;
+    const int n_new = P.ctr->rs_n_new;
+    const int listed = min(n_new, P.block_cap);
+    bool over = n_new > listed;
+    for (int j = blockIdx.x * (WG / 64) + w; j < listed; j += gridDim.x * (WG / 64)) {
+        const uint32_t slot = P.rs_new[j];
+        const int e = nb + j;
         uint32_t* src = &P.nh_cnt[(size_t)slot * NC];
+        const unsigned c = lane < NC ? src[lane] : 0u;
+        if (lane < NC) src[lane] = 0u;
+        const unsigned tot = wave_incl_scan(c);
         if (e < max_ent) {
-            P.nh_idx[slot] = e;
-            P.rs_oldblk[e] = P.nh_owner[slot];
-            uint32_t* dst = &P.rs_in[(size_t)e * NC];
-            for (int c = 0; c < NC; ++c) dst[c] = src[c];
+            if (lane < NC) P.rs_in[(size_t)e * NC + lane] = c;
+            if (lane == 63) {
+                P.nh_idx[slot] = e;
+                P.rs_oldblk[e] = P.nh_owner[slot];
+                P.rs_cnt[e] = tot;
+            }
         } else {
-            P.nh_idx[slot] = -1;
+            if (lane == 0) P.nh_idx[slot] = -1;
             over = true;
         }
-        for (int c = 0; c < NC; ++c) src[c] = 0u;
-        ++j;
     }
     if (over) raise_flag(P.ctr, MPM_FLAG_OVERFLOW);
-    if (blockIdx.x == 0 && threadIdx.x == 0) P.ctr->rs_n_ent = min(nb + P.ctr->rs_n_new, max_ent);
+    if (blockIdx.x == 0 && threadIdx.x == 0) P.ctr->rs_n_ent = min(nb + listed, max_ent);
 }
 
 // Particles of entry e in base cell `lane` (0 for lanes >= NC).
@@ -287,7 +274,9 @@ __device__ __forceinline__ unsigned entry_cell_count(const DevParams& P, int e, 
     return st + P.rs_in[(size_t)e * NC + lane];
 }
 
-// offsets, first half: particles per entry (one wave per entry).
+// totals: particles per entry (one wave per entry), when no G2P counted the
+// stayers (the route has added the movers of the previous blocks to counts
+// that this pass replaces).
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_rs_entry_count(DevParams P) {
     const int lane = __lane_id(), w = threadIdx.x >> 6;
@@ -299,32 +288,17 @@ __global__ __launch_bounds__(WG) void k_rs_entry_count(DevParams P) {
     }
 }
 
-// offsets, second half: first position per entry and cell; the mover counts
-// become the counters of movers placed.
-template <int DIM>
-__global__ __launch_bounds__(WG) void k_rs_offsets(DevParams P) {
-    constexpr int NC = 1 << (2 * DIM);
-    const int lane = __lane_id(), w = threadIdx.x >> 6;
-    const int nb = min(P.ctr->nb, P.block_cap);
-    const int ne = P.ctr->rs_n_ent;
-    for (int e = blockIdx.x * (WG / 64) + w; e < ne; e += gridDim.x * (WG / 64)) {
-        const unsigned v = entry_cell_count<DIM>(P, e, nb, lane);
-        const unsigned ex = wave_incl_scan(v) - v;
-        if (lane < NC) {
-            P.rs_off[(size_t)e * NC + lane] = P.rs_start[e] + ex;
-            P.rs_in[(size_t)e * NC + lane] = 0u;
-        }
-    }
-}
-
 constexpr int RS_STAGE = 768;  // particles of a block whose output is staged in LDS (larger: direct stores);
                                 // 25 KB of LDS per workgroup, six workgroups per compute unit
 constexpr uint32_t RS_EMPTY = 0xFFFFFFFFu;  // staging slot left to a mover (indices are < 2^30)
 
-// place, stayers: one wave per previous block, segment in the previous order.
-// The block's output range (stayers and the movers that join it) is staged in
-// LDS and written out contiguously; the metadata of the wave's next block is
-// loaded while the current one is placed.
+// place, stayers: one wave per entry.  The wave first turns the entry's cell
+// counts (stayers and movers) and its first position into the first position
+// of every cell (rs_off); for a previous block it then walks the block's
+// segment in the previous order and places the stayers.  The block's output
+// range (stayers and the movers that join it) is staged in LDS and written out
+// contiguously; the metadata of the wave's next entry is loaded while the
+// current one is placed.
 // KEYS: the sorted keys are written too (keys_out); without them the staging
 // holds values only, half the LDS.
 template <int DIM, bool KEYS>
@@ -336,29 +310,34 @@ __global__ __launch_bounds__(WG) void k_rs_place(DevParams P, const uint32_t* __
     __shared__ uint32_t sk[WG / 64][KEYS ? RS_STAGE : 1], sv[WG / 64][RS_STAGE];
     const int lane = __lane_id(), w = threadIdx.x >> 6;
     const int nb = min(P.ctr->nb, P.block_cap);
+    const int ne = P.ctr->rs_n_ent;
     const int stride = gridDim.x * (WG / 64);
     int s_n = 0, c_n = 0;
-    unsigned base_n = 0u, tot_n = 0u, off_n = 0u;
+    unsigned base_n = 0u, tot_n = 0u, st_n = 0u, in_n = 0u;
     uint32_t owner_n = 0u;
     auto fetch = [&](int e) {
         c_n = 0;
-        if (e < nb) {
+        if (e < ne) {
             asm volatile("" : "+v"(e));  // same in every lane; keeps the values in vector registers
-            s_n = P.b_start[e];
-            c_n = P.b_count[e];
+            const bool prev = e < nb;
+            s_n = prev ? P.b_start[e] : 0;
+            c_n = prev ? P.b_count[e] : 0;
             owner_n = P.rs_oldblk[e];
             base_n = P.rs_start[e];
             tot_n = P.rs_cnt[e];
-            off_n = lane < NC ? P.rs_off[(size_t)e * NC + lane] : 0u;
+            st_n = prev && lane < NC ? P.rs_stay[(size_t)e * NC + lane] : 0u;
+            in_n = lane < NC ? P.rs_in[(size_t)e * NC + lane] : 0u;
         }
     };
     bool bad = false;
     fetch(blockIdx.x * (WG / 64) + w);
-    for (int e = blockIdx.x * (WG / 64) + w; e < nb; e += stride) {
+    for (int e = blockIdx.x * (WG / 64) + w; e < ne; e += stride) {
         const int s = s_n, c = c_n;
         const uint32_t owner = owner_n;
-        const unsigned base = base_n, tot = tot_n, off = off_n;
+        const unsigned base = base_n, tot = tot_n, cv = st_n + in_n;
         fetch(e + stride);
+        const unsigned off = base + wave_incl_scan(cv) - cv;
+        if (lane < NC) P.rs_off[(size_t)e * NC + lane] = off;
         if (c <= 0) continue;
         const bool staged = tot <= (unsigned)RS_STAGE;
         if (staged)
@@ -439,8 +418,11 @@ __global__ __launch_bounds__(WG) void k_rs_place_movers(DevParams P, const uint3
             bad = true;
             continue;
         }
-        const unsigned pos = b0 + atomicAdd(&P.rs_in[(size_t)e2 * NC + cell], 1u);
-        if (pos < (unsigned)n) {
+        // the cell's movers still to place, this one included: the last of
+        // them takes the first position after the stayers
+        const unsigned left = atomicSub(&P.rs_in[(size_t)e2 * NC + cell], 1u);
+        const unsigned pos = b0 + left - 1u;
+        if (left != 0u && pos < (unsigned)n) {
             if (keys_out) keys_out[pos] = k;
             vals_out[pos] = i;
         } else {
@@ -450,28 +432,24 @@ __global__ __launch_bounds__(WG) void k_rs_place_movers(DevParams P, const uint3
     if (bad) raise_flag(P.ctr, MPM_FLAG_OVERFLOW);
 }
 
-// reset: mover counters of every entry and the second table's keys.
+// reset: the second table's keys and entry indices (the movers' placement
+// has counted every entry's mover counts back to zero).
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_rs_reset(DevParams P, unsigned H) {
-    constexpr int NC = 1 << (2 * DIM);
-    const long long rows = (long long)P.ctr->rs_n_ent * NC;
-    const long long all = rows > (long long)H ? rows : (long long)H;
-    for (long long t = (long long)blockIdx.x * WG + threadIdx.x; t < all; t += (long long)gridDim.x * WG) {
-        if (t < rows) P.rs_in[t] = 0u;
-        if (t < (long long)H) {
-            P.nh_keys[t] = EMPTY_KEY;
-            // the block hash, which the re-sort was the last to read, is
-            // cleared here for the insertion that follows (Algorithm 5's
-            // initialisation)
-            P.h_keys[t] = EMPTY_KEY;
-            P.h_mask[t] = 0ull;
-            P.h_start[t] = -1;
-            P.h_end[t] = -1;
-            P.h_entry[t] = -1;
-        }
+    for (long long t = (long long)blockIdx.x * WG + threadIdx.x; t < (long long)H; t += (long long)gridDim.x * WG) {
+        P.nh_keys[t] = EMPTY_KEY;
+        P.nh_idx[t] = -1;
+        // the block hash, which the re-sort was the last to read, is cleared
+        // here for the insertion that follows (Algorithm 5's initialisation)
+        P.h_keys[t] = EMPTY_KEY;
+        P.h_mask[t] = 0ull;
+        P.h_start[t] = -1;
+        P.h_end[t] = -1;
+        P.h_entry[t] = -1;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         P.ctr->rs_n_mov = 0;
+        P.ctr->rs_n_new = 0;
         P.ctr->nb = 0;
         P.ctr->n_touched = 0;
         P.ctr->n_work = 0;
@@ -488,8 +466,12 @@ __global__ __launch_bounds__(WG) void k_rs_init(DevParams P, unsigned H) {
     for (long long t = (long long)blockIdx.x * WG + threadIdx.x; t < all; t += (long long)gridDim.x * WG) {
         if (t < rows) P.rs_in[t] = 0u;
         if (t < hrows) P.nh_cnt[t] = 0u;
-        if (t < (long long)H) P.nh_keys[t] = EMPTY_KEY;
+        if (t < (long long)H) {
+            P.nh_keys[t] = EMPTY_KEY;
+            P.nh_idx[t] = -1;
+        }
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) P.ctr->rs_n_new = 0;
 }
 
 namespace {
@@ -515,7 +497,6 @@ hipError_t launch_resort(const DevParams& P, const uint32_t* keys_new, uint32_t*
     const int gw = grid_for_waves(P.block_cap);
     const int ge = grid_for_waves(2ll * P.block_cap);
     const int gm = (int)std::min<long long>(((long long)n + WG - 1) / WG, 2048);  // grid-stride over the movers
-    const int htiles = (int)((H + SCAN_TILE - 1) / SCAN_TILE);
     hipError_t e = hipSuccess;
     if (!counted) {
         if (P.dim == 3)
@@ -534,32 +515,33 @@ hipError_t launch_resort(const DevParams& P, const uint32_t* keys_new, uint32_t*
         k_rs_route<3><<<gm, WG, 0, s>>>(P, keys_new, movers, n);
     else
         k_rs_route<2><<<gm, WG, 0, s>>>(P, keys_new, movers, n);
-    k_rs_new_count<<<htiles, WG, 0, s>>>(P, (int)H, partials);
-    if (P.dim == 3) {
-        k_rs_new_write<3><<<htiles, WG, 0, s>>>(P, (int)H, partials, htiles);
-        k_rs_entry_count<3><<<ge, WG, 0, s>>>(P);
-    } else {
-        k_rs_new_write<2><<<htiles, WG, 0, s>>>(P, (int)H, partials, htiles);
-        k_rs_entry_count<2><<<ge, WG, 0, s>>>(P);
+    const int gn = 256;  // workgroups, grid-stride over the new blocks (a few hundred per step)
+    if (P.dim == 3)
+        k_rs_new_write<3><<<gn, WG, 0, s>>>(P);
+    else
+        k_rs_new_write<2><<<gn, WG, 0, s>>>(P);
+    if (!counted) {
+        if (P.dim == 3)
+            k_rs_entry_count<3><<<ge, WG, 0, s>>>(P);
+        else
+            k_rs_entry_count<2><<<ge, WG, 0, s>>>(P);
     }
     e = scan_exclusive(P.rs_cnt, P.rs_start, 2 * P.block_cap, &P.ctr->rs_n_ent, partials, nullptr, s);
     if (e != hipSuccess) return e;
     if (P.dim == 3) {
-        k_rs_offsets<3><<<ge, WG, 0, s>>>(P);
         if (keys_out)
-            k_rs_place<3, true><<<gw, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n);
+            k_rs_place<3, true><<<ge, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n);
         else
-            k_rs_place<3, false><<<gw, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n);
+            k_rs_place<3, false><<<ge, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n);
         k_rs_place_movers<3><<<gm, WG, 0, s>>>(P, keys_new, movers, keys_out, vals_out, n);
-        k_rs_reset<3><<<4096, WG, 0, s>>>(P, H);
+        k_rs_reset<3><<<grid_for_waves((long long)H / 64), WG, 0, s>>>(P, H);
     } else {
-        k_rs_offsets<2><<<ge, WG, 0, s>>>(P);
         if (keys_out)
-            k_rs_place<2, true><<<gw, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n);
+            k_rs_place<2, true><<<ge, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n);
         else
-            k_rs_place<2, false><<<gw, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n);
+            k_rs_place<2, false><<<ge, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n);
         k_rs_place_movers<2><<<gm, WG, 0, s>>>(P, keys_new, movers, keys_out, vals_out, n);
-        k_rs_reset<2><<<4096, WG, 0, s>>>(P, H);
+        k_rs_reset<2><<<grid_for_waves((long long)H / 64), WG, 0, s>>>(P, H);
     }
     return hipGetLastError();
 }

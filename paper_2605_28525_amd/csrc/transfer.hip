@@ -707,10 +707,10 @@ struct G2POut {
 // sort key).  With out.movers as well it does the counting of the next
 // incremental re-sort for the block of each item: the particles whose new key
 // keeps the block's owner ("stayers") are counted per base cell in LDS and
-// the counts stored to the block's row of rs_stay (added, for blocks split
-// over several items, to the row the build cleared); the others ("movers")
-// are appended to out.movers at a position claimed once per wave from the
-// counter rs_n_mov.
+// the counts stored to the block's row of rs_stay and their sum to rs_cnt
+// (added, for blocks split over several items, to what the build cleared);
+// the others ("movers") are appended to out.movers at a position claimed once
+// per wave from the counter rs_n_mov.
 template <int DIM, int GS>
 __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, int n,
                                             const uint32_t* __restrict__ osrc) {
@@ -989,14 +989,25 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
             if (!finite) raise_flag(P.ctr, MPM_FLAG_NAN);
         }
         __syncthreads();
-        if (out.movers && threadIdx.x < NC) {
-            const unsigned c = scnt[threadIdx.x];
-            unsigned* row = P.rs_stay + (size_t)cur.blk * NC + threadIdx.x;
-            if (chunks == 1u)
-                *row = c;
-            else if (c)
-                atomicAdd(row, c);
-            scnt[threadIdx.x] = 0u;  // ordered before the next item's counting by the barriers between
+        if (out.movers && threadIdx.x < 64) {
+            // the first wave stores the item's stayer counts and their sum
+            // (the particles of the block's entry, before the movers arrive)
+            const unsigned c = threadIdx.x < NC ? scnt[threadIdx.x] : 0u;
+            if (threadIdx.x < NC) {
+                unsigned* row = P.rs_stay + (size_t)cur.blk * NC + threadIdx.x;
+                if (chunks == 1u)
+                    *row = c;
+                else if (c)
+                    atomicAdd(row, c);
+                scnt[threadIdx.x] = 0u;  // ordered before the next item's counting by the barriers between
+            }
+            const unsigned tot = wave_incl_scan(c);
+            if (threadIdx.x == 63) {
+                if (chunks == 1u)
+                    P.rs_cnt[cur.blk] = tot;
+                else if (tot)
+                    atomicAdd(&P.rs_cnt[cur.blk], tot);
+            }
         }
         fetch_data();  // in flight during phase 2
         // phase 2: constitutive update (its register live range is separate)
