@@ -231,14 +231,17 @@ __global__ __launch_bounds__(WG) void k_hash_insert_entries(DevParams P) {
     const int lane = __lane_id(), w = threadIdx.x >> 6;
     const int ne = P.ctr->rs_n_ent;
     for (int e = blockIdx.x * (WG / 64) + w; e < ne; e += gridDim.x * (WG / 64)) {
+        // every load of the entry issued at once (none waits for the count)
         const unsigned tot = P.rs_cnt[e];
+        const unsigned first = P.rs_start[e];
+        const unsigned off_raw = lane < NC ? P.rs_off[(size_t)e * NC + lane] : 0u;
+        const uint32_t owner = P.rs_oldblk[e];
         if (tot == 0u) continue;
-        const unsigned first = P.rs_start[e], end = first + tot;
-        const unsigned off = lane < NC ? P.rs_off[(size_t)e * NC + lane] : end;
+        const unsigned end = first + tot;
+        const unsigned off = lane < NC ? off_raw : end;
         const unsigned next = __shfl_down(off, 1);
         const bool occupied = lane < NC && (lane == NC - 1 ? end : next) > off;
         const uint64_t occ = (uint64_t)__ballot(occupied);
-        const uint32_t owner = P.rs_oldblk[e];
         const uint32_t bl = owner & ((1u << P.blk_bits) - 1u);
         const int inst = (int)(owner >> P.blk_bits);
         int bc[3];
@@ -264,12 +267,13 @@ __global__ __launch_bounds__(WG) void k_hash_insert_entries(DevParams P) {
 __global__ __launch_bounds__(WG) void k_compact_count(DevParams P, int H, unsigned* __restrict__ partials) {
     __shared__ unsigned lds[WG / 64];
     const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    // all loads in flight at once: clamped index, masked result
+    uint64_t key[SCAN_ITEMS];
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) key[j] = P.h_keys[min(base + j, H - 1)];
     unsigned s = 0;
 #pragma unroll
-    for (int j = 0; j < SCAN_ITEMS; ++j) {
-        const int idx = base + j;
-        if (idx < H && P.h_keys[idx] != EMPTY_KEY) ++s;
-    }
+    for (int j = 0; j < SCAN_ITEMS; ++j) s += (base + j < H && key[j] != EMPTY_KEY) ? 1u : 0u;
     unsigned tot;
     wg_excl_scan(s, lds, &tot);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
@@ -278,17 +282,33 @@ __global__ __launch_bounds__(WG) void k_compact_count(DevParams P, int H, unsign
 __global__ __launch_bounds__(WG) void k_compact_write(DevParams P, int H, const unsigned* __restrict__ partials,
                                                       int tiles, int* __restrict__ slot_of) {
     __shared__ unsigned lds[WG / 64];
-    unsigned before, total;
-    tile_offset(partials, blockIdx.x, tiles, lds, &before, &total);
+    // Loads first: the keys, then the fields of the occupied slots, all in
+    // flight while the tile sums are read and scanned (the barriers of those
+    // scans would otherwise hold them back).
     const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    uint64_t key[SCAN_ITEMS], mask[SCAN_ITEMS];
+    int st[SCAN_ITEMS], en[SCAN_ITEMS], ent[SCAN_ITEMS];
     bool occ[SCAN_ITEMS];
     unsigned s = 0;
 #pragma unroll
     for (int j = 0; j < SCAN_ITEMS; ++j) {
         const int idx = base + j;
-        occ[j] = idx < H && P.h_keys[idx] != EMPTY_KEY;
-        s += occ[j];
+        key[j] = idx < H ? P.h_keys[idx] : EMPTY_KEY;
     }
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        const int idx = base + j;
+        occ[j] = key[j] != EMPTY_KEY;
+        s += occ[j];
+        if (occ[j]) {
+            mask[j] = P.h_mask[idx];
+            st[j] = P.h_start[idx];
+            en[j] = P.h_end[idx];
+            ent[j] = P.b_entry ? P.h_entry[idx] : -1;
+        }
+    }
+    unsigned before, total;
+    tile_offset(partials, blockIdx.x, tiles, lds, &before, &total);
     unsigned tot;
     unsigned phi = wg_excl_scan(s, lds, &tot) + before;
     bool over = false;
@@ -297,14 +317,13 @@ __global__ __launch_bounds__(WG) void k_compact_write(DevParams P, int H, const 
         if (!occ[j]) continue;
         const int idx = base + j;
         if ((int)phi < P.block_cap) {
-            P.b_keys[phi] = P.h_keys[idx];
-            P.b_mask[phi] = P.h_mask[idx];
-            const int st = P.h_start[idx];
-            P.b_start[phi] = st;
-            P.b_count[phi] = st >= 0 ? P.h_end[idx] - st : 0;
+            P.b_keys[phi] = key[j];
+            P.b_mask[phi] = mask[j];
+            P.b_start[phi] = st[j];
+            P.b_count[phi] = st[j] >= 0 ? en[j] - st[j] : 0;
             P.h_vals[idx] = (int)phi;
             if (slot_of) slot_of[phi] = idx;
-            if (P.b_entry) P.b_entry[phi] = P.h_entry[idx];
+            if (P.b_entry) P.b_entry[phi] = ent[j];
         } else {
             P.h_vals[idx] = -1;
             over = true;
@@ -365,8 +384,12 @@ __global__ __launch_bounds__(WG) void k_block_setup(DevParams P) {
     for (long long t = (long long)blockIdx.x * WG + threadIdx.x; t < total; t += (long long)gridDim.x * WG) {
         const int b = (int)(t / LPB), j = (int)(t % LPB);
         const int d = j % NB;
+        // the block's count is loaded beside its key, not after the lookups
+        const uint64_t bkey = P.b_keys[b];
+        int bcount = P.b_count[b];
+        asm volatile("" : "+v"(bcount));
         int bc[3], inst;
-        unblock_key<DIM>(P, P.b_keys[b], bc, &inst);
+        unblock_key<DIM>(P, bkey, bc, &inst);
         if (j < NB) {
             P.b_nbr[b * NB + d] =
                 d == 0 ? b
@@ -380,7 +403,7 @@ __global__ __launch_bounds__(WG) void k_block_setup(DevParams P) {
                                                                   bc[2] - ((d >> 2) & 1), inst));
             P.b_lo[b * NB + d] = (lo >= 0 && P.b_count[lo] > 0) ? lo : -1;
         }
-        const unsigned chunks = (unsigned)((P.b_count[b] + P.chunk - 1) / P.chunk);
+        const unsigned chunks = (unsigned)((bcount + P.chunk - 1) / P.chunk);
         if (j == 0) P.b_chunks[b] = chunks;
         if (P.rs_stay) {
             // for the next incremental re-sort, when a G2P bins its output:

@@ -278,11 +278,14 @@ __device__ __forceinline__ InstMat material(const DevParams& P, int inst) {
 
 // Compact index of block key K in the block hash table (Eqs. 23-25), -1 if
 // the key has no slot or its block did not fit the capacity.
+// The slot's value is loaded beside its key, so a hit costs one round trip.
 __device__ __forceinline__ int hash_lookup(const DevParams& P, uint64_t K) {
     unsigned s = (unsigned)mix64(K) & P.h_mask_bits;
     for (int r = 0; r < P.n_probe; ++r) {
         const uint64_t cur = P.h_keys[s];
-        if (cur == K) return P.h_vals[s];
+        int val = P.h_vals[s];
+        asm volatile("" : "+v"(val));  // keeps the load beside the key's, not behind the compare
+        if (cur == K) return val;
         if (cur == EMPTY_KEY) return -1;
         s = (s + 1) & P.h_mask_bits;
     }

@@ -403,24 +403,22 @@ __global__ __launch_bounds__(WG) void k_rs_place_movers(DevParams P, const uint3
         const uint32_t cell = k & (NC - 1);
         const uint64_t K = owner_block_key<DIM>(P, k >> CB);
         int e2 = hash_lookup(P, K);
-        unsigned b0 = 0u;
-        if (e2 >= 0) {
-            b0 = P.rs_off[(size_t)e2 * NC + cell] + P.rs_stay[(size_t)e2 * NC + cell];
-        } else {
+        const bool prev = e2 >= 0;
+        if (!prev) {
             const int slot = nh_lookup(P, K);
             e2 = slot >= 0 ? P.nh_idx[slot] : -1;
-            if (e2 >= 0 && e2 < ne)
-                b0 = P.rs_off[(size_t)e2 * NC + cell];
-            else
-                e2 = -1;
+            if (e2 >= ne) e2 = -1;
         }
         if (e2 < 0) {
             bad = true;
             continue;
         }
+        const size_t r = (size_t)e2 * NC + cell;
         // the cell's movers still to place, this one included: the last of
-        // them takes the first position after the stayers
-        const unsigned left = atomicSub(&P.rs_in[(size_t)e2 * NC + cell], 1u);
+        // them takes the first position after the stayers (the decrement and
+        // the loads of the cell's offsets are in flight together)
+        const unsigned left = atomicSub(&P.rs_in[r], 1u);
+        const unsigned b0 = P.rs_off[r] + (prev ? P.rs_stay[r] : 0u);
         const unsigned pos = b0 + left - 1u;
         if (left != 0u && pos < (unsigned)n) {
             if (keys_out) keys_out[pos] = k;

@@ -17,12 +17,14 @@ __global__ __launch_bounds__(WG) void k_scan_reduce(const unsigned* __restrict__
     // partials of the tiles below it)
     if (blockIdx.x > 0 && blockIdx.x * SCAN_TILE >= nn) return;
     const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    // every load issued before the first is consumed: the index is clamped
+    // into range and the value masked, rather than the load guarded
+    unsigned v[SCAN_ITEMS];
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) v[j] = in[max(min(base + j, nn - 1), 0)];
     unsigned s = 0;
 #pragma unroll
-    for (int j = 0; j < SCAN_ITEMS; ++j) {
-        int idx = base + j;
-        if (idx < nn) s += in[idx];
-    }
+    for (int j = 0; j < SCAN_ITEMS; ++j) s += base + j < nn ? v[j] : 0u;
     unsigned tot;
     wg_excl_scan(s, lds, &tot);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
@@ -38,18 +40,21 @@ __global__ __launch_bounds__(WG) void k_scan_down(const unsigned* __restrict__ i
     // written then
     const int live = n_dev ? max(1, min(tiles, (nn + SCAN_TILE - 1) / SCAN_TILE)) : tiles;
     if (blockIdx.x >= live) return;
-    unsigned before, total;
-    tile_offset(partials, blockIdx.x, live, lds, &before, &total);
-    if (blockIdx.x == 0 && threadIdx.x == 0 && total_out) *total_out = total;
+    // the tile's values are loaded before the tile sums are read and scanned
+    // (the barriers of that scan would otherwise hold them back)
     const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
     unsigned v[SCAN_ITEMS];
-    unsigned s = 0;
 #pragma unroll
     for (int j = 0; j < SCAN_ITEMS; ++j) {
         int idx = base + j;
         v[j] = idx < nn ? in[idx] : 0u;
-        s += v[j];
     }
+    unsigned before, total;
+    tile_offset(partials, blockIdx.x, live, lds, &before, &total);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && total_out) *total_out = total;
+    unsigned s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) s += v[j];
     unsigned tot;
     unsigned run = wg_excl_scan(s, lds, &tot) + before;
 #pragma unroll
