@@ -372,16 +372,16 @@ int mpm_graph_launch(mpm_ctx* ctx, int times, void* stream);
 int mpm_graph_release(mpm_ctx* ctx);
 
 /* Launch shape of the transfer kernels: particles per work item `chunk`
- * (64..512, used by G2P and the reverse kernels), G2P workgroup size
- * `g2p_block` (64, 128 or 256; chunk <= 2 g2p_block) and the persistent
- * workgroup counts of the P2G and G2P launches.  0 keeps a value.  Takes
- * effect on the next build; a captured graph keeps the shape it was recorded
- * with.  MPM_ERR_ARG for values out of range. */
+ * (64..768, used by G2P and the reverse kernels), G2P workgroup size
+ * `g2p_block` (64, 128 or 256; chunk <= 2 g2p_block, or 3 g2p_block at 256)
+ * and the persistent workgroup counts of the P2G and G2P launches.  0 keeps a
+ * value.  Takes effect on the next build; a captured graph keeps the shape it
+ * was recorded with.  MPM_ERR_ARG for values out of range. */
 int mpm_set_tuning(mpm_ctx* ctx, int chunk, int g2p_block, int p2g_workgroups, int g2p_workgroups);
 
 /* Autotuner: for every candidate launch shape ((g2p_block, chunk) in {(64,
- * 64), (64, 128), (128, 128), (128, 256), (256, 256), (256, 512)} x persistent
- * workgroups in {1024, 2048, 4096, 8192}) runs one warm-up and 3 timed steps
+ * 64), (64, 128), (128, 128), (128, 256), (256, 256), (256, 512), (256, 768)}
+ * x persistent workgroups in {1024, 2048, 4096, 8192}) runs one warm-up and 5 timed steps
  * that read a and write b (a is left unchanged; b ends one step ahead of a),
  * keeps the fastest P2G workgroup count and the fastest G2P shape, and
  * reports them in chosen[4] = {chunk, g2p_block, p2g_workgroups,

@@ -24,12 +24,12 @@ struct mpm_ctx {
     int block_cap = 0;
     int H_log2 = 0;
     int work_cap = 0;
-    int chunk = 512;
+    int chunk = 768;
     int max_particles = 0;
     bool dense = false;
     int p2g_wgs = 2048;     // persistent workgroups of the P2G launch
     int g2p_wgs = 2048;     // persistent workgroups of the G2P launch
-    int g2p_block = 256;    // threads per G2P workgroup (work items of at most twice as many particles)
+    int g2p_block = 256;    // threads per G2P workgroup (work items of at most g2p_max_items of it)
     int n_inst = 1;
     int blk_bits = 0;
     InstMat* inst = nullptr;  // device table of per-instance constants (ensembles)
@@ -1121,7 +1121,7 @@ int mpm_set_tuning(mpm_ctx* c, int chunk, int g2p_block, int p2g_workgroups, int
         return MPM_ERR_ARG;
     const int new_chunk = chunk ? chunk : c->chunk;
     const int new_block = g2p_block ? g2p_block : c->g2p_block;
-    if (new_chunk > 2 * new_block) return MPM_ERR_ARG;
+    if (new_chunk > g2p_max_items(new_block)) return MPM_ERR_ARG;
     if (new_chunk != c->chunk) {
         c->chunk = c->P.chunk = new_chunk;
         c->built = false;  // work items of the last build used the old size
@@ -1136,9 +1136,10 @@ int mpm_autotune(mpm_ctx* c, const mpm_particles* a, const mpm_particles* b, int
     if (!c || !particles_ok(c, a, true) || !b || b->n != a->n) return MPM_ERR_ARG;
     hipStream_t s = (hipStream_t)stream;
     // (G2P workgroup size, particles per work item) pairs, persistent workgroup counts
-    static const int shapes[][2] = {{64, 64}, {64, 128}, {128, 128}, {128, 256}, {256, 256}, {256, 512}};
+    static const int shapes[][2] = {{64, 64},   {64, 128},  {128, 128}, {128, 256},
+                                    {256, 256}, {256, 512}, {256, 768}};
     static const int wgs[] = {1024, 2048, 4096, 8192};
-    constexpr int NS = 6, NW = 4, REPS = 3;
+    constexpr int NS = 7, NW = 4, REPS = 5;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     int st = MPM_OK;
     for (int i = 0; i < 4 && st == MPM_OK; ++i)

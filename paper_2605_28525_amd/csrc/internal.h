@@ -32,7 +32,11 @@ constexpr int SORT_TILE = WG * SORT_ITEMS;     // 4096 keys per tile
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = WG * SCAN_ITEMS;     // 2048 values per scan tile
 constexpr int MIN_CHUNK = 64;                  // smallest particles-per-work-item setting
-constexpr int MAX_CHUNK = 512;                 // largest (G2P stages a work item in LDS)
+constexpr int MAX_CHUNK = 768;                 // largest (G2P stages a work item in LDS)
+// Particles a G2P workgroup of gs threads stages per work item: three per
+// thread at 256 threads (a full 4^3 block of 8-per-cell material, slightly
+// compressed, stays one item), two per thread below.
+constexpr int g2p_max_items(int gs) { return (gs == 256 ? 3 : 2) * gs; }
 
 struct DevCounters {
     int nb;          // active blocks (compact count, <= capacity)

@@ -701,7 +701,7 @@ struct G2POut {
     uint32_t* movers;  // optional (with keys): the next incremental re-sort's counting, see k_g2p
 };
 
-// GS threads per workgroup, work items of at most 2 GS particles.
+// GS threads per workgroup, work items of at most g2p_max_items(GS) particles.
 //
 // With out.keys the kernel also bins each new position (the next build's
 // sort key).  With out.movers as well it does the counting of the next
@@ -719,7 +719,7 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
     constexpr int DD = DIM * DIM;
     constexpr int VSY = 20, VSZ = DIM == 3 ? 120 : 0;  // padded float4 tile: row / plane strides
     __shared__ float4 vt[DIM == 3 ? 6 * VSZ : 6 * VSY];
-    constexpr int MAXI = 2 * GS;
+    constexpr int MAXI = g2p_max_items(GS);
     __shared__ float xs[DIM][MAXI];
     __shared__ float fs[DD][MAXI];
     constexpr int NC = 1 << (2 * DIM);
@@ -1071,7 +1071,7 @@ hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, 
                       int grid_blocks, hipStream_t s, uint32_t* keys_out, uint32_t* movers_out) {
     G2PIn in{x_in, F_in, id_in, inst_in};
     G2POut out{x_out, v_out, C_out, F_out, tau_out, id_out, inst_out, keys_out, keys_out ? movers_out : nullptr};
-    if (2 * block_size < P.chunk) return hipErrorInvalidValue;  // work items must fit the LDS staging
+    if (g2p_max_items(block_size) < P.chunk) return hipErrorInvalidValue;  // work items must fit the LDS staging
     switch (block_size * 4 + P.dim) {
         case 64 * 4 + 3: k_g2p<3, 64><<<grid_blocks, 64, 0, s>>>(P, in, out, n, osrc); break;
         case 128 * 4 + 3: k_g2p<3, 128><<<grid_blocks, 128, 0, s>>>(P, in, out, n, osrc); break;

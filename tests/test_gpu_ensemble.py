@@ -198,7 +198,8 @@ def test_autotune_leaves_input_and_steps_correctly():
     try:
         before = t.a.to_arrays()
         chunk, g2p_block, p2g_wg, g2p_wg = M.mpm_autotune(t.ctx, t.a.view(), t.b.view())
-        assert (g2p_block, chunk) in ((64, 64), (64, 128), (128, 128), (128, 256), (256, 256), (256, 512))
+        assert (g2p_block, chunk) in ((64, 64), (64, 128), (128, 128), (128, 256), (256, 256), (256, 512),
+                                      (256, 768))
         assert p2g_wg in (1024, 2048, 4096, 8192) and g2p_wg in (1024, 2048, 4096, 8192)
         after = t.a.to_arrays()
         for k in FIELDS:
@@ -262,7 +263,7 @@ def test_g2p_launch_shapes_agree():
                 assert np.array_equal(o[k], outs[0][k]), k
         ids = np.arange(w.n)
         ref = None
-        for blk, chunk in ((256, 512), (64, 64), (64, 128), (128, 256), (256, 256)):
+        for blk, chunk in ((256, 512), (64, 64), (64, 128), (128, 256), (256, 256), (256, 768)):
             M.mpm_set_tuning(sim.ctx, chunk, blk, 0, 0)
             M.mpm_step(sim.ctx, a, b, 1)
             assert M.mpm_get_status(sim.ctx)[0] == 0
