@@ -27,8 +27,8 @@ struct mpm_ctx {
     int chunk = 768;
     int max_particles = 0;
     bool dense = false;
-    int p2g_wgs = 2048;     // persistent workgroups of the P2G launch
-    int g2p_wgs = 2048;     // persistent workgroups of the G2P launch
+    int p2g_wgs = 8192;     // persistent workgroups of the P2G launch
+    int g2p_wgs = 8192;     // persistent workgroups of the G2P launch
     int g2p_block = 256;    // threads per G2P workgroup (work items of at most g2p_max_items of it)
     int n_inst = 1;
     int blk_bits = 0;
@@ -325,7 +325,8 @@ int alloc_capacity_buffers(mpm_ctx* c) {
     const size_t cap = (size_t)c->block_cap;
     // room for the smallest work-item size mpm_set_tuning accepts
     c->work_cap = c->block_cap + c->max_particles / MIN_CHUNK + 1;
-    int scan_n = std::max({radix_hist_size(c->max_particles), radix_hist_size(c->block_cap), (int)H,
+    // (the hash compaction keeps two tile sums per tile of the table)
+    int scan_n = std::max({radix_hist_size(c->max_particles), radix_hist_size(c->block_cap), (int)(2 * H),
                            2 * c->block_cap, 1});
     // the incremental re-sort serves hash-built sparse contexts whose particle
     // order may depend on earlier builds

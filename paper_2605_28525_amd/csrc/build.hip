@@ -264,23 +264,53 @@ __global__ __launch_bounds__(WG) void k_hash_insert_entries(DevParams P) {
     }
 }
 
-__global__ __launch_bounds__(WG) void k_compact_count(DevParams P, int H, unsigned* __restrict__ partials) {
+// Work items of a block holding cnt particles (none for a block that only
+// holds stencil nodes).
+__device__ __forceinline__ unsigned block_chunks(const DevParams& P, int cnt) {
+    return cnt > 0 ? (unsigned)((cnt + P.chunk - 1) / P.chunk) : 0u;
+}
+
+// Compaction, first pass: occupied slots per tile of the hash table
+// (partials[tile]) and, with `items`, the work items of their blocks
+// (partials[tiles + tile]).
+__global__ __launch_bounds__(WG) void k_compact_count(DevParams P, int H, unsigned* __restrict__ partials, int tiles,
+                                                      bool items) {
     __shared__ unsigned lds[WG / 64];
     const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
     // all loads in flight at once: clamped index, masked result
     uint64_t key[SCAN_ITEMS];
 #pragma unroll
     for (int j = 0; j < SCAN_ITEMS; ++j) key[j] = P.h_keys[min(base + j, H - 1)];
-    unsigned s = 0;
+    unsigned s = 0, w = 0;
+    int st[SCAN_ITEMS], en[SCAN_ITEMS];
 #pragma unroll
-    for (int j = 0; j < SCAN_ITEMS; ++j) s += (base + j < H && key[j] != EMPTY_KEY) ? 1u : 0u;
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        const bool occ = base + j < H && key[j] != EMPTY_KEY;
+        s += occ ? 1u : 0u;
+        st[j] = -1;
+        en[j] = -1;
+        if (items && occ) {
+            st[j] = P.h_start[base + j];
+            en[j] = P.h_end[base + j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) w += st[j] >= 0 ? block_chunks(P, en[j] - st[j]) : 0u;
     unsigned tot;
     wg_excl_scan(s, lds, &tot);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+    if (items) {
+        wg_excl_scan(w, lds, &tot);
+        if (threadIdx.x == 0) partials[tiles + blockIdx.x] = tot;
+    }
 }
 
+// Compaction, second pass: Phi in slot order and the block tables; with
+// `items` also the work items of each block, at the exclusive prefix of the
+// item counts in slot order (which is Phi order), so no separate scan of the
+// per-block counts is needed.
 __global__ __launch_bounds__(WG) void k_compact_write(DevParams P, int H, const unsigned* __restrict__ partials,
-                                                      int tiles, int* __restrict__ slot_of) {
+                                                      int tiles, int* __restrict__ slot_of, bool items) {
     __shared__ unsigned lds[WG / 64];
     // Loads first: the keys, then the fields of the occupied slots, all in
     // flight while the tile sums are read and scanned (the barriers of those
@@ -300,6 +330,8 @@ __global__ __launch_bounds__(WG) void k_compact_write(DevParams P, int H, const 
         const int idx = base + j;
         occ[j] = key[j] != EMPTY_KEY;
         s += occ[j];
+        st[j] = -1;
+        en[j] = -1;
         if (occ[j]) {
             mask[j] = P.h_mask[idx];
             st[j] = P.h_start[idx];
@@ -307,33 +339,55 @@ __global__ __launch_bounds__(WG) void k_compact_write(DevParams P, int H, const 
             ent[j] = P.b_entry ? P.h_entry[idx] : -1;
         }
     }
-    unsigned before, total;
+    unsigned wsum = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) wsum += st[j] >= 0 ? block_chunks(P, en[j] - st[j]) : 0u;
+    unsigned before, total, wbefore = 0, wtotal = 0;
     tile_offset(partials, blockIdx.x, tiles, lds, &before, &total);
+    if (items) tile_offset(partials + tiles, blockIdx.x, tiles, lds, &wbefore, &wtotal);
     unsigned tot;
     unsigned phi = wg_excl_scan(s, lds, &tot) + before;
+    unsigned w = items ? wg_excl_scan(wsum, lds, &tot) + wbefore : 0u;
     bool over = false;
 #pragma unroll
     for (int j = 0; j < SCAN_ITEMS; ++j) {
         if (!occ[j]) continue;
         const int idx = base + j;
+        const int cnt = st[j] >= 0 ? en[j] - st[j] : 0;
+        const unsigned chunks = block_chunks(P, cnt);
         if ((int)phi < P.block_cap) {
             P.b_keys[phi] = key[j];
             P.b_mask[phi] = mask[j];
             P.b_start[phi] = st[j];
-            P.b_count[phi] = st[j] >= 0 ? en[j] - st[j] : 0;
+            P.b_count[phi] = cnt;
             P.h_vals[idx] = (int)phi;
             if (slot_of) slot_of[phi] = idx;
             if (P.b_entry) P.b_entry[phi] = ent[j];
+            if (items) {
+                P.b_chunks[phi] = chunks;
+                for (unsigned k = 0; k < chunks; ++k) {
+                    if (w + k >= (unsigned)P.work_cap) {
+                        over = true;
+                        break;
+                    }
+                    P.w_block[w + k] = (int)phi;
+                    P.w_start[w + k] = st[j] + (int)k * P.chunk;
+                    P.w_end[w + k] = min(st[j] + ((int)k + 1) * P.chunk, en[j]);
+                }
+            }
         } else {
             P.h_vals[idx] = -1;
             over = true;
         }
+        w += chunks;
         ++phi;
     }
     if (over) raise_flag(P.ctr, MPM_FLAG_OVERFLOW);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         P.ctr->n_touched = total;
         P.ctr->nb = min((int)total, P.block_cap);
+        // items of blocks past the capacity were not written: no work then
+        if (items) P.ctr->n_work = total <= (unsigned)P.block_cap ? (int)wtotal : 0;
     }
 }
 
@@ -546,7 +600,10 @@ hipError_t launch_build_sparse(const DevParams& P, const uint32_t* skeys, int n,
     const int tiles = ((int)H + SCAN_TILE - 1) / SCAN_TILE;
     const int gb = grid_for(P.block_cap, 2048);
     const int gs = grid_for(2ll * (1 << P.dim) * P.block_cap, 8192);  // k_block_setup: 2^(d+1) lanes per block
-    k_compact_count<<<tiles, WG, 0, s>>>(P, (int)H, partials);
+    // without the key order, Phi is slot order and the compaction also writes
+    // the work items
+    const bool items = det == nullptr;
+    k_compact_count<<<tiles, WG, 0, s>>>(P, (int)H, partials, tiles, items);
     if (det) {
         // compaction in slot order into the alternate tables, then the blocks
         // sorted by key and gathered into the block tables
@@ -555,7 +612,7 @@ hipError_t launch_build_sparse(const DevParams& P, const uint32_t* skeys, int n,
         Pa.b_mask = det->mask;
         Pa.b_start = det->start;
         Pa.b_count = det->count;
-        k_compact_write<<<tiles, WG, 0, s>>>(Pa, (int)H, partials, tiles, det->slot);
+        k_compact_write<<<tiles, WG, 0, s>>>(Pa, (int)H, partials, tiles, det->slot, false);
         const int kb = P.blk_bits + (P.n_inst > 1 ? 6 : 0);
         const uint32_t sentinel = kb >= 32 ? 0xFFFFFFFFu : ((1u << kb) - 1u);
         if (P.dim == 3)
@@ -568,7 +625,7 @@ hipError_t launch_build_sparse(const DevParams& P, const uint32_t* skeys, int n,
         if (e != hipSuccess) return e;
         k_det_apply<<<gb, WG, 0, s>>>(P, *det, vo);
     } else {
-        k_compact_write<<<tiles, WG, 0, s>>>(P, (int)H, partials, tiles, nullptr);
+        k_compact_write<<<tiles, WG, 0, s>>>(P, (int)H, partials, tiles, nullptr, true);
     }
     if (P.dim == 3)
         k_block_setup<3><<<gs, WG, 0, s>>>(P);
@@ -577,7 +634,7 @@ hipError_t launch_build_sparse(const DevParams& P, const uint32_t* skeys, int n,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // no grid clear: the second P2G pass writes every node of every active block
-    return launch_work_items(P, partials, s);
+    return items ? hipSuccess : launch_work_items(P, partials, s);
 }
 
 // Work items: exclusive scan of the per-block chunk counts, then the items.
