@@ -24,7 +24,7 @@ struct mpm_ctx {
     int block_cap = 0;
     int H_log2 = 0;
     int work_cap = 0;
-    int chunk = 768;
+    int chunk = 512;
     int max_particles = 0;
     bool dense = false;
     int p2g_wgs = 8192;     // persistent workgroups of the P2G launch
