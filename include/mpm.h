@@ -382,7 +382,8 @@ int mpm_set_tuning(mpm_ctx* ctx, int chunk, int g2p_block, int p2g_workgroups, i
 /* Autotuner: for every candidate launch shape ((g2p_block, chunk) in {(64,
  * 64), (64, 128), (128, 128), (128, 256), (256, 256), (256, 512), (256, 768)}
  * x persistent workgroups in {1024, 2048, 4096, 8192}) runs one warm-up and 5 timed steps
- * that read a and write b (a is left unchanged; b ends one step ahead of a),
+ * that read a and write b (a is left unchanged; b ends one step ahead of a;
+ * G2P as inside mpm_step, binning and counting for a next build),
  * keeps the fastest P2G workgroup count and the fastest G2P shape, and
  * reports them in chosen[4] = {chunk, g2p_block, p2g_workgroups,
  * g2p_workgroups} (host ints, may be NULL).  Synchronises the stream. */

@@ -1161,7 +1161,14 @@ int mpm_autotune(mpm_ctx* c, const mpm_particles* a, const mpm_particles* b, int
                 if (st == MPM_OK && hipEventRecord(ev[1], s) != hipSuccess) st = MPM_ERR_HIP;
                 if (st == MPM_OK) st = mpm_grid_update(c, s);
                 if (st == MPM_OK && hipEventRecord(ev[2], s) != hipSuccess) st = MPM_ERR_HIP;
-                if (st == MPM_OK) st = mpm_g2p(c, a, b, s);
+                if (st == MPM_OK) {
+                    // G2P as inside mpm_step: it also bins and counts for the
+                    // next build (which the next trial's build ignores)
+                    const bool next_reuse = would_reuse(c, b->n);
+                    uint32_t* keys_out = !c->adjoint && a->n > 0 ? next_bin_buffer(c, next_reuse) : nullptr;
+                    uint32_t* movers_out = keys_out && next_reuse ? c->movers : nullptr;
+                    st = g2p_impl(c, a, b, s, keys_out, movers_out);
+                }
                 if (st == MPM_OK && hipEventRecord(ev[3], s) != hipSuccess) st = MPM_ERR_HIP;
                 if (st == MPM_OK && hipEventSynchronize(ev[3]) != hipSuccess) st = MPM_ERR_HIP;
                 if (st != MPM_OK || r == 0) continue;  // the first repetition warms up
