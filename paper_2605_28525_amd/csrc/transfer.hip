@@ -988,27 +988,7 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
                 }
             if (!finite) raise_flag(P.ctr, MPM_FLAG_NAN);
         }
-        __syncthreads();
-        if (out.movers && threadIdx.x < 64) {
-            // the first wave stores the item's stayer counts and their sum
-            // (the particles of the block's entry, before the movers arrive)
-            const unsigned c = threadIdx.x < NC ? scnt[threadIdx.x] : 0u;
-            if (threadIdx.x < NC) {
-                unsigned* row = P.rs_stay + (size_t)cur.blk * NC + threadIdx.x;
-                if (chunks == 1u)
-                    *row = c;
-                else if (c)
-                    atomicAdd(row, c);
-                scnt[threadIdx.x] = 0u;  // ordered before the next item's counting by the barriers between
-            }
-            const unsigned tot = wave_incl_scan(c);
-            if (threadIdx.x == 63) {
-                if (chunks == 1u)
-                    P.rs_cnt[cur.blk] = tot;
-                else if (tot)
-                    atomicAdd(&P.rs_cnt[cur.blk], tot);
-            }
-        }
+        // no barrier: phase 2 reads only the trial F its own thread wrote
         fetch_data();  // in flight during phase 2
         // phase 2: constitutive update (its register live range is separate)
 #pragma unroll 1
@@ -1034,6 +1014,26 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
             if (flags) raise_flag(P.ctr, flags);
         }
         __syncthreads();
+        if (out.movers && threadIdx.x < 64) {
+            // the first wave stores the item's stayer counts and their sum
+            // (the particles of the block's entry, before the movers arrive)
+            const unsigned c = threadIdx.x < NC ? scnt[threadIdx.x] : 0u;
+            if (threadIdx.x < NC) {
+                unsigned* row = P.rs_stay + (size_t)cur.blk * NC + threadIdx.x;
+                if (chunks == 1u)
+                    *row = c;
+                else if (c)
+                    atomicAdd(row, c);
+                scnt[threadIdx.x] = 0u;  // ordered before the next item's counting by the barrier of its phase 0
+            }
+            const unsigned tot = wave_incl_scan(c);
+            if (threadIdx.x == 63) {
+                if (chunks == 1u)
+                    P.rs_cnt[cur.blk] = tot;
+                else if (tot)
+                    atomicAdd(&P.rs_cnt[cur.blk], tot);
+            }
+        }
         w += G;
         cur = nxt;
         nxt = nn;
