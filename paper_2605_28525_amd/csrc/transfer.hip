@@ -911,8 +911,15 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
                         U4[a] += wy * S2[a];
                     }
                     // keep the LDS gathers of one row in flight at a time
-                    // (bounds register pressure, hence raises occupancy)
+                    // (bounds register pressure, hence raises occupancy), and
+                    // finish the row's sums here: without the empty asm the
+                    // compiler sinks the B and grad v terms below the stores
+                    // of x and v, which keeps all 27 nodal velocities live
+                    // (215 instead of 150 VGPRs: two waves per SIMD, not three)
                     __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a)
+                        asm volatile("" : "+v"(U0[a]), "+v"(U1[a]), "+v"(U2[a]), "+v"(U3[a]), "+v"(U4[a]));
                 }
                 const float wz = DIM == 3 ? wt[2][kz] : 1.f;
 #pragma unroll
