@@ -37,8 +37,8 @@ METRIC = "particle-steps/s (sparse vs dense, 1 GPU); adjoint/forward step time r
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="landslide", choices=["landslide", "collapse_3d"])
     ap.add_argument("--dense-steps", type=int, default=10)
     ap.add_argument("--no-dense", action="store_true")
