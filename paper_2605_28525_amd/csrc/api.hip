@@ -763,13 +763,21 @@ int mpm_sparse_build(mpm_ctx* c, const mpm_particles* p, void* stream) {
     return sparse_build(c, p, (hipStream_t)stream, false);
 }
 
-int mpm_p2g(mpm_ctx* c, const mpm_particles* p, void* stream) {
+namespace {
+// mpm_p2g; with `update` (sparse grids) P2G's second pass also applies the grid
+// update, so the grid holds velocities afterwards.
+int p2g_impl(mpm_ctx* c, const mpm_particles* p, hipStream_t s, bool update) {
     if (!c || !particles_ok(c, p, true)) return MPM_ERR_ARG;
     if (!c->built || p->n != c->built_n) return MPM_ERR_STATE;
     if (p->n == 0) return MPM_OK;
     const int wgs = std::min(c->p2g_wgs, c->work_cap);
     return hip_status(
-        launch_p2g(c->P, p->x, p->v, p->C, p->tau, p->n, c->order, c->skeys, c->osrc, wgs, (hipStream_t)stream));
+        launch_p2g(c->P, p->x, p->v, p->C, p->tau, p->n, c->order, c->skeys, c->osrc, wgs, s, update));
+}
+}  // namespace
+
+int mpm_p2g(mpm_ctx* c, const mpm_particles* p, void* stream) {
+    return p2g_impl(c, p, (hipStream_t)stream, false);
 }
 
 int mpm_grid_update(mpm_ctx* c, void* stream) {
@@ -814,8 +822,13 @@ int mpm_step(mpm_ctx* c, const mpm_particles* a, const mpm_particles* b, int n_s
     bool keys_ready = false;  // the previous step's G2P binned the positions it wrote
     for (int k = 0; k < n_steps; ++k) {
         int st = sparse_build(c, cur, s, keys_ready);
-        if (st == MPM_OK) st = mpm_p2g(c, cur, stream);
-        if (st == MPM_OK) st = mpm_grid_update(c, stream);
+        // on a sparse grid the grid update runs inside P2G's second pass (the
+        // grid between the two is not visible to the caller here; reverse-mode
+        // contexts keep the separate calls their tape repeats); with zero
+        // particles the grid update still runs on its own
+        const bool fuse_update = !c->dense && !c->adjoint && cur->n > 0;
+        if (st == MPM_OK) st = p2g_impl(c, cur, s, fuse_update);
+        if (st == MPM_OK && !fuse_update) st = mpm_grid_update(c, stream);
         // Between two steps of this call nothing else touches the positions,
         // so G2P bins them as it writes them.  Not in reverse-mode contexts,
         // whose tape records each build as mpm_sparse_build makes it.

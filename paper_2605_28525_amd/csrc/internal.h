@@ -437,8 +437,11 @@ hipError_t launch_build_sparse(const DevParams& P, const uint32_t* skeys, int n,
                                hipStream_t s, bool from_resort = false, const DetTables* det = nullptr);
 hipError_t launch_build_dense(const DevParams& P, const uint32_t* skeys, int n, int n_blocks, unsigned* partials,
                               hipStream_t s);
+// update: the grid update (Eqs. 8-12) is applied in P2G's second pass (sparse
+// grids), which then leaves velocities instead of momenta in the grid.
 hipError_t launch_p2g(const DevParams& P, const float* x, const float* v, const float* C, const float* tau, int n,
-                      const uint32_t* order, const uint32_t* skeys, uint32_t* osrc, int grid_blocks, hipStream_t s);
+                      const uint32_t* order, const uint32_t* skeys, uint32_t* osrc, int grid_blocks, hipStream_t s,
+                      bool update = false);
 hipError_t launch_grid_update(const DevParams& P, long long n_nodes_host, int grid_blocks, hipStream_t s);
 hipError_t launch_g2p(const DevParams& P, const float* x_in, const float* F_in, const uint32_t* id_in,
                       const uint32_t* inst_in, float* x_out, float* v_out, float* C_out, float* F_out, float* tau_out,

@@ -318,50 +318,35 @@ __global__ __launch_bounds__(64) void k_p2g_cell(DevParams P, const float* __res
     }
 }
 
-// P2G, second pass on a sparse grid: node n of block b receives the tile
-// entries that cover it, from b's own tile and from the tiles of the lower
-// neighbours b - d (d in {0,1}^d) whose 6-node tiles reach n (local index < 2
-// on every axis where d is set).  One wave per block, one lane per node; each
-// tile node is read once in total, and the sum is written (no atomics).
-template <int DIM>
-__global__ __launch_bounds__(WG) void k_p2g_gather(DevParams P) {
-    using T = Tile<DIM>;
-    const int lane = __lane_id(), w = threadIdx.x >> 6;
-    const int nb = min(P.ctr->nb, P.block_cap);
-    const int I = lane & 3, J = (lane >> 2) & 3, K = DIM == 3 ? (lane >> 4) & 3 : 0;
-    for (int b = blockIdx.x * (WG / 64) + w; b < nb; b += gridDim.x * (WG / 64)) {
-        int src[T::NB];  // the block and its lower neighbours that own particles, else -1
-#pragma unroll
-        for (int d = 0; d < T::NB; ++d) src[d] = P.b_lo[(size_t)b * T::NB + d];
-        float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-        for (int d = 0; d < T::NB; ++d) {
-            const int dx = d & 1, dy = (d >> 1) & 1, dz = (d >> 2) & 1;
-            const bool reach = (!dx || I < 2) && (!dy || J < 2) && (DIM == 2 || !dz || K < 2);
-            if (src[d] >= 0 && reach && lane < T::NPB) {
-                const int t = T::store_index(I + 4 * dx, J + 4 * dy, K + 4 * dz);
-                const float4 g = P.tiles[(size_t)src[d] * T::N + t];
-                sum.x += g.x;
-                sum.y += g.y;
-                sum.z += g.z;
-                sum.w += g.w;
-            }
-        }
-        if (lane < T::NPB) P.grid[(size_t)b * T::NPB + lane] = sum;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // grid update with boundary conditions
-template <int DIM>
-__device__ __forceinline__ void terrain_bc(const DevParams& P, int i, int j, int k, float* vel) {
+
+// Terrain heights a node's condition reads: at (i, j) and its four axis
+// neighbours (clamped to the heightmap), as h[0] (i, j), h[1] (i-1), h[2]
+// (i+1), h[3] (j-1), h[4] (j+1).  Loaded unconditionally, so that a caller
+// can issue them long before the node's velocity is known.
+__device__ __forceinline__ void terrain_heights(const DevParams& P, int i, int j, float* h) {
     const int nx = P.cells[0] + 1, ny = P.cells[1] + 1;
+    const int ic = min(max(i, 0), nx - 1), jc = min(max(j, 0), ny - 1);
+    const int il = max(ic - 1, 0), ih = min(ic + 1, nx - 1);
+    const int jl = max(jc - 1, 0), jh = min(jc + 1, ny - 1);
     const float* H = P.heightmap;
-    if (!((double)k * P.dx <= (double)H[(size_t)i * ny + j])) return;
+    h[0] = H[(size_t)ic * ny + jc];
+    h[1] = H[(size_t)il * ny + jc];
+    h[2] = H[(size_t)ih * ny + jc];
+    h[3] = H[(size_t)ic * ny + jl];
+    h[4] = H[(size_t)ic * ny + jh];
+}
+
+// Coulomb friction against the terrain level set (the node below the surface
+// height h[0], normal from central differences of the heights).
+__device__ __forceinline__ void terrain_bc(const DevParams& P, int i, int j, int k, const float* h, float* vel) {
+    const int nx = P.cells[0] + 1, ny = P.cells[1] + 1;
+    if (!((double)k * P.dx <= (double)h[0])) return;
     const int il = max(i - 1, 0), ih = min(i + 1, nx - 1);
     const int jl = max(j - 1, 0), jh = min(j + 1, ny - 1);
-    const float hx = (H[(size_t)ih * ny + j] - H[(size_t)il * ny + j]) / ((float)(ih - il) * P.dxf);
-    const float hy = (H[(size_t)i * ny + jh] - H[(size_t)i * ny + jl]) / ((float)(jh - jl) * P.dxf);
+    const float hx = (h[2] - h[1]) / ((float)(ih - il) * P.dxf);
+    const float hy = (h[4] - h[3]) / ((float)(jh - jl) * P.dxf);
     const float inv = 1.f / sqrtf(hx * hx + hy * hy + 1.f);
     const float n0 = -hx * inv, n1 = -hy * inv, n2 = inv;
     const float vn = vel[0] * n0 + vel[1] * n1 + vel[2] * n2;
@@ -378,46 +363,120 @@ __device__ __forceinline__ void terrain_bc(const DevParams& P, int i, int j, int
     }
 }
 
+// Eqs. 8-12 for one node: v = p / m + dt g, then the terrain and wall
+// conditions; records the pre-condition velocity u where an adjoint context
+// keeps it.  gv = (p, m); h: the node's terrain heights (3D with terrain).
+template <int DIM>
+__device__ __forceinline__ float4 node_update(const DevParams& P, size_t s, const int* node, float dtn, float4 gv,
+                                              const float* h) {
+    const float m = gv.w;
+    float vel[3] = {0.f, 0.f, 0.f};
+    if (m > 0.f) {
+        vel[0] = gv.x / m + dtn * P.g[0];
+        vel[1] = gv.y / m + dtn * P.g[1];
+        if (DIM == 3) vel[2] = gv.z / m + dtn * P.g[2];
+        if (P.grid_u) P.grid_u[s] = make_float4(vel[0], vel[1], vel[2], m);
+        if (DIM == 3 && P.has_terrain && node[0] <= P.cells[0] && node[1] <= P.cells[1])
+            terrain_bc(P, node[0], node[1], node[2], h, vel);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const bool on = side == 0 ? node[a] < P.bound : node[a] > P.cells[a] - P.bound;
+                if (!on) continue;
+                const int kind = P.bc[a][side];
+                if (kind == MPM_BC_STICKY) {
+                    vel[0] = vel[1] = vel[2] = 0.f;
+                } else if (kind == MPM_BC_SLIP) {
+                    vel[a] = 0.f;
+                } else if (kind == MPM_BC_SEPARATE) {
+                    vel[a] = side == 0 ? fmaxf(vel[a], 0.f) : fminf(vel[a], 0.f);
+                }
+            }
+        }
+    } else if (P.grid_u) {
+        P.grid_u[s] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    return make_float4(vel[0], vel[1], vel[2], m);
+}
+
+// What the update of node `lane` of compact block b needs besides the node's
+// mass and momentum: its grid coordinates, the block instance's time step and
+// the terrain heights around it (all issued at once; the heights unconditionally).
+template <int DIM>
+__device__ __forceinline__ void node_update_inputs(const DevParams& P, int b, int lane, int* node, float* dtn,
+                                                   float* h) {
+    int bc[3], inst;
+    block_coords<DIM>(P, b, bc, &inst);
+    *dtn = P.n_inst > 1 ? P.inst[inst].dt : P.dt;
+    node[0] = bc[0] * BLK + (lane & 3);
+    node[1] = bc[1] * BLK + ((lane >> 2) & 3);
+    node[2] = DIM == 3 ? bc[2] * BLK + ((lane >> 4) & 3) : 0;
+    if (DIM == 3 && P.has_terrain) terrain_heights(P, node[0], node[1], h);
+}
+
+// P2G, second pass on a sparse grid: node n of block b receives the tile
+// entries that cover it, from b's own tile and from the tiles of the lower
+// neighbours b - d (d in {0,1}^d) whose 6-node tiles reach n (local index < 2
+// on every axis where d is set).  One wave per block, one lane per node; each
+// tile node is read once in total, and the sum is written (no atomics).
+// UPDATE (inside mpm_step): the node's grid update follows at once and the
+// velocity is written instead of the momentum; the block key, time step and
+// terrain heights the update needs are loaded beside the tile reads, so the
+// wave's chain of dependent loads is no longer than the gather's own.
+template <int DIM, bool UPDATE>
+__global__ __launch_bounds__(WG) void k_p2g_gather(DevParams P) {
+    using T = Tile<DIM>;
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
+    const int nb = min(P.ctr->nb, P.block_cap);
+    const int I = lane & 3, J = (lane >> 2) & 3, K = DIM == 3 ? (lane >> 4) & 3 : 0;
+    for (int b = blockIdx.x * (WG / 64) + w; b < nb; b += gridDim.x * (WG / 64)) {
+        int src[T::NB];  // the block and its lower neighbours that own particles, else -1
+#pragma unroll
+        for (int d = 0; d < T::NB; ++d) src[d] = P.b_lo[(size_t)b * T::NB + d];
+        int node[3] = {0, 0, 0};
+        float dtn = P.dt, h[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        if (UPDATE) node_update_inputs<DIM>(P, b, lane, node, &dtn, h);
+        float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int d = 0; d < T::NB; ++d) {
+            const int dx = d & 1, dy = (d >> 1) & 1, dz = (d >> 2) & 1;
+            const bool reach = (!dx || I < 2) && (!dy || J < 2) && (DIM == 2 || !dz || K < 2);
+            if (src[d] >= 0 && reach && lane < T::NPB) {
+                const int t = T::store_index(I + 4 * dx, J + 4 * dy, K + 4 * dz);
+                const float4 g = P.tiles[(size_t)src[d] * T::N + t];
+                sum.x += g.x;
+                sum.y += g.y;
+                sum.z += g.z;
+                sum.w += g.w;
+            }
+        }
+        if (lane < T::NPB) {
+            const size_t s = (size_t)b * T::NPB + lane;
+            P.grid[s] = UPDATE ? node_update<DIM>(P, s, node, dtn, sum, h) : sum;
+        }
+    }
+}
+
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_grid_update(DevParams P, long long n_nodes_host) {
     constexpr int NPB = Tile<DIM>::NPB;
     const long long n_nodes = n_nodes_host >= 0 ? n_nodes_host : (long long)P.ctr->nb * NPB;
     for (long long s = (long long)blockIdx.x * WG + threadIdx.x; s < n_nodes; s += (long long)gridDim.x * WG) {
         const float4 gv = P.grid[s];
-        const float m = gv.w;
-        float vel[3] = {0.f, 0.f, 0.f};
-        if (m > 0.f) {
+        float4 out = make_float4(0.f, 0.f, 0.f, gv.w);
+        if (gv.w > 0.f || P.grid_u) {
             const int b = (int)(s / NPB), l = (int)(s % NPB);
             int bc[3], inst;
             block_coords<DIM>(P, b, bc, &inst);
             const float dtn = P.n_inst > 1 ? P.inst[inst].dt : P.dt;
-            vel[0] = gv.x / m + dtn * P.g[0];
-            vel[1] = gv.y / m + dtn * P.g[1];
-            if (DIM == 3) vel[2] = gv.z / m + dtn * P.g[2];
-            if (P.grid_u) P.grid_u[s] = make_float4(vel[0], vel[1], vel[2], m);
-            int node[3] = {bc[0] * BLK + (l & 3), bc[1] * BLK + ((l >> 2) & 3), DIM == 3 ? bc[2] * BLK + (l >> 4) : 0};
-            if (DIM == 3 && P.has_terrain && node[0] <= P.cells[0] && node[1] <= P.cells[1])
-                terrain_bc<DIM>(P, node[0], node[1], node[2], vel);
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-#pragma unroll
-                for (int side = 0; side < 2; ++side) {
-                    const bool on = side == 0 ? node[a] < P.bound : node[a] > P.cells[a] - P.bound;
-                    if (!on) continue;
-                    const int kind = P.bc[a][side];
-                    if (kind == MPM_BC_STICKY) {
-                        vel[0] = vel[1] = vel[2] = 0.f;
-                    } else if (kind == MPM_BC_SLIP) {
-                        vel[a] = 0.f;
-                    } else if (kind == MPM_BC_SEPARATE) {
-                        vel[a] = side == 0 ? fmaxf(vel[a], 0.f) : fminf(vel[a], 0.f);
-                    }
-                }
-            }
-        } else if (P.grid_u) {
-            P.grid_u[s] = make_float4(0.f, 0.f, 0.f, 0.f);
+            const int node[3] = {bc[0] * BLK + (l & 3), bc[1] * BLK + ((l >> 2) & 3),
+                                 DIM == 3 ? bc[2] * BLK + (l >> 4) : 0};
+            float h[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+            if (DIM == 3 && P.has_terrain && gv.w > 0.f) terrain_heights(P, node[0], node[1], h);
+            out = node_update<DIM>(P, (size_t)s, node, dtn, gv, h);
         }
-        P.grid[s] = make_float4(vel[0], vel[1], vel[2], m);
+        P.grid[s] = out;
     }
 }
 
@@ -1048,7 +1107,8 @@ __global__ __launch_bounds__(GS) void k_g2p(DevParams P, G2PIn in, G2POut out, i
 }
 
 hipError_t launch_p2g(const DevParams& P, const float* x, const float* v, const float* C, const float* tau, int n,
-                      const uint32_t* order, const uint32_t* skeys, uint32_t* osrc, int grid_blocks, hipStream_t s) {
+                      const uint32_t* order, const uint32_t* skeys, uint32_t* osrc, int grid_blocks, hipStream_t s,
+                      bool update) {
     const int g = P.dense ? 65536 : grid_blocks * 4;
     if (P.dim == 3)
         k_p2g_cell<3><<<g, 64, 0, s>>>(P, x, v, C, tau, n, order, skeys, osrc);
@@ -1056,10 +1116,17 @@ hipError_t launch_p2g(const DevParams& P, const float* x, const float* v, const 
         k_p2g_cell<2><<<g, 64, 0, s>>>(P, x, v, C, tau, n, order, skeys, osrc);
     if (!P.dense) {
         const int gg = (int)std::min<long long>(((long long)P.block_cap + 3) / 4, 16384);  // one wave per block
-        if (P.dim == 3)
-            k_p2g_gather<3><<<gg, WG, 0, s>>>(P);
-        else
-            k_p2g_gather<2><<<gg, WG, 0, s>>>(P);
+        if (P.dim == 3) {
+            if (update)
+                k_p2g_gather<3, true><<<gg, WG, 0, s>>>(P);
+            else
+                k_p2g_gather<3, false><<<gg, WG, 0, s>>>(P);
+        } else {
+            if (update)
+                k_p2g_gather<2, true><<<gg, WG, 0, s>>>(P);
+            else
+                k_p2g_gather<2, false><<<gg, WG, 0, s>>>(P);
+        }
     }
     return hipGetLastError();
 }
