@@ -228,32 +228,30 @@ def landslide(seed_terrain: int = 2, seed_particles: int = 102, window=None,
     """Synthetic landslide: 2048x2048x256 cells at dx = 1 m, a 250x250 m footprint,
     40 m thick, 8 ppc (20,000,000 particles) released on the slope at rest.
 
-    ``window=((i0, i1), (j0, j1))`` restricts the potential domain to that range of
-    node columns of the same terrain (cell counts i1-i0, j1-j0; height kept), with
-    ``footprint`` given in the window's own cell indices.
+    ``h`` (1, 2 or 4) coarsens the same slide to dx = h metres: the terrain
+    sampled at every h-th node, 256 / h cells high, the default footprint and
+    thickness divided by h (rounded to whole cells), 8 ppc, dt = h ms.
 
-    ``h`` (1, 2 or 4; whole domain only) coarsens the same slide to dx = h metres:
-    the terrain sampled at every h-th node, the footprint and thickness divided
-    by h (rounded to whole cells), 8 ppc, dt = h ms.
+    ``window=((i0, i1), (j0, j1))`` restricts the potential domain to that range
+    of node columns of the (coarsened) terrain (cell counts i1-i0, j1-j0; height
+    kept), with ``footprint`` and ``thickness`` given in the window's own cells.
     """
-    dx = 1.0
-    hm_full, theta = landslide_terrain((2048, 2048), dx, seed_terrain)
-    if h != 1:
-        if window is not None or h not in (2, 4):
-            raise ValueError("h must be 1, 2 or 4, on the whole domain")
-        (a0, a1), (b0, b1) = footprint
-        footprint = ((round(a0 / h), round(a1 / h)), (round(b0 / h), round(b1 / h)))
-        thickness = round(thickness / h)
-        hm = np.ascontiguousarray(hm_full[::h, ::h])
+    if h not in (1, 2, 4):
+        raise ValueError("h must be 1, 2 or 4")
+    hm_full, theta = landslide_terrain((2048, 2048), 1.0, seed_terrain)
+    hm_h = hm_full if h == 1 else np.ascontiguousarray(hm_full[::h, ::h])
+    dx = float(h)
+    if window is None:
+        hm = hm_h
         cells = (2048 // h, 2048 // h, 256 // h)
-        dx = float(h)
-    elif window is None:
-        hm = hm_full
-        cells = (2048, 2048, 256)
+        if h != 1:
+            (a0, a1), (b0, b1) = footprint
+            footprint = ((round(a0 / h), round(a1 / h)), (round(b0 / h), round(b1 / h)))
+            thickness = round(thickness / h)
     else:
         (i0, i1), (j0, j1) = window
-        hm = np.ascontiguousarray(hm_full[i0:i1 + 1, j0:j1 + 1])
-        cells = (i1 - i0, j1 - j0, 256)
+        hm = np.ascontiguousarray(hm_h[i0:i1 + 1, j0:j1 + 1])
+        cells = (i1 - i0, j1 - j0, 256 // h)
     rng = np.random.default_rng(seed_particles)
     (fi0, fi1), (fj0, fj1) = footprint
     # lowest cell of each column lies on or above the terrain at all four corner nodes
@@ -262,9 +260,9 @@ def landslide(seed_terrain: int = 2, seed_particles: int = 102, window=None,
     k0 = np.ceil(corner.astype(np.float64) / dx).astype(np.int64)
     x = stratified_columns((fi0, fi1), (fj0, fj1), k0, thickness, dx, 2, rng)
     vol = dx ** 3 / 8
-    name = "landslide" if window is None else "landslide_crop"
-    if h != 1:
-        name = f"landslide_h{h}"
+    name = "landslide" if h == 1 else f"landslide_h{h}"
+    if window is not None:
+        name += "_crop"
     w = Workload(name=name, dim=3, dx=dx, cells=cells,
                  gravity=(0.0, 0.0, -9.81), dt=1e-3 * h, steps=5000, ppc=8, p_vol0=vol,
                  p_mass=2000.0 * vol, model="dp", E=5.0e7, nu=0.3, rho=2000.0, friction_deg=32.0,

@@ -15,7 +15,8 @@ whose contributing particles all lie in the window (and away from the
 window's faces) are compared with the GPU's grid, node by node (mass,
 momentum, updated velocity, and the active node masks of the blocks there),
 and particles whose 27 nodes are all such nodes with the GPU's output, at the
-parity tolerance.
+parity tolerance.  The landslide coarsened to dx = 4 m and 2 m gets the same
+window comparison after 10 steps.
 """
 import numpy as np
 import pytest
@@ -34,45 +35,29 @@ def _base(x, dx):
     return np.floor(s).astype(np.int64)
 
 
-@pytest.mark.parametrize("steps_before", [10, 2500])
-def test_landslide_full_size(steps_before):
-    from paper_2605_28525_amd import mpm as M
-    w = wl.landslide()
+def check_window(w, parts, i0, j0, width, h=1):
+    """One step of a window of the slide on the FP64 oracle against the GPU's
+    step: every particle whose base node lies in the window (shifted to its
+    origin, an exact shift by whole cells), stepped on the same terrain crop;
+    nodes whose contributing particles all lie in the window compared node by
+    node (mass, momentum, updated velocity, active node masks of the blocks
+    there), and particles whose 27 nodes are all such nodes.  Returns the
+    errors and counts."""
+    I0, J0, W = i0, j0, width
     n, d, dx = w.n, w.dim, w.dx
-    print("CASE landslide full size", n, "after", steps_before, "steps", flush=True)
-    sim = M.Simulation(w, block_capacity=1 << 18)
-    try:
-        sim.step(steps_before)
-        M.mpm_autotune(sim.ctx, sim.a.view(), sim.b.view())
-        parts = gpu_step_parts(sim)
-    finally:
-        sim.close()
-    assert parts["status"][0] == 0, parts["status"]
     sin, sout = parts["state_in"], parts["state_out"]
     order = parts["order"].astype(np.int64)
-    assert np.array_equal(np.sort(order), np.arange(n)), "order is not a permutation"
-    assert np.array_equal(parts["ids_out"], parts["ids_in"][order]), "ids not carried"
-    for f in ("x", "v", "C", "F", "tau"):
-        assert np.isfinite(sout[f]).all(), f
     g1 = parts["grid_p2g"].reshape(-1, 4).astype(np.float64)
     g2 = parts["grid_upd"].reshape(-1, 4)
-    m_tot = n * float(w.p_mass)
-    assert abs(g1[:, 3].sum() - m_tot) <= 1e-5 * m_tot, (g1[:, 3].sum(), m_tot)
-    v_in = sin["v"].astype(np.float64)
-    mom = float(w.p_mass) * v_in.sum(axis=1)
-    scale = float(w.p_mass) * np.abs(v_in).sum()
-    assert np.all(np.abs(g1[:, :d].sum(axis=0) - mom) <= 1e-5 * scale), (g1[:, :d].sum(axis=0), mom)
-
-    # the window, on the oracle
     b_in = _base(sin["x"], dx)
     sel = np.nonzero((b_in[0] >= I0 + 3) & (b_in[0] < I0 + W - 3) &
                      (b_in[1] >= J0 + 3) & (b_in[1] < J0 + W - 3))[0]
-    ww = wl.landslide(window=((I0, I0 + W), (J0, J0 + W)), footprint=((0, 1), (0, 1)), thickness=1)
+    ww = wl.landslide(h=h, window=((I0, I0 + W), (J0, J0 + W)), footprint=((0, 1), (0, 1)), thickness=1)
     sub = {k: np.ascontiguousarray(sin[k][:, sel]) for k in ("x", "v", "C", "F", "tau")}
     sub["x"] = sub["x"].copy()
     sub["x"][0] = (sin["x"][0, sel].astype(np.float64) - I0 * dx).astype(np.float32)
     sub["x"][1] = (sin["x"][1, sel].astype(np.float64) - J0 * dx).astype(np.float32)
-    # the shift is exact (integer multiples of dx = 1 m), so base nodes shift by (I0, J0)
+    # the shift is exact (whole cells), so base nodes shift by (I0, J0)
     assert np.array_equal(_base(sub["x"], dx)[0], b_in[0, sel] - I0)
     for k, a in sub.items():
         setattr(ww, k, a)
@@ -126,6 +111,39 @@ def test_landslide_full_size(steps_before):
     errs["tau"] = assert_field("particle tau", sout["tau"][:, o_sel], ref["tau"][:, k_sel], RTOL, atol=tau_floor(w))
     errs["particles"] = int(len(o_sel))
     print(errs)
+    return errs
+
+
+@pytest.mark.parametrize("steps_before", [10, 2500])
+def test_landslide_full_size(steps_before):
+    from paper_2605_28525_amd import mpm as M
+    w = wl.landslide()
+    n, d, dx = w.n, w.dim, w.dx
+    print("CASE landslide full size", n, "after", steps_before, "steps", flush=True)
+    sim = M.Simulation(w, block_capacity=1 << 18)
+    try:
+        sim.step(steps_before)
+        M.mpm_autotune(sim.ctx, sim.a.view(), sim.b.view())
+        parts = gpu_step_parts(sim)
+    finally:
+        sim.close()
+    assert parts["status"][0] == 0, parts["status"]
+    sin, sout = parts["state_in"], parts["state_out"]
+    order = parts["order"].astype(np.int64)
+    assert np.array_equal(np.sort(order), np.arange(n)), "order is not a permutation"
+    assert np.array_equal(parts["ids_out"], parts["ids_in"][order]), "ids not carried"
+    for f in ("x", "v", "C", "F", "tau"):
+        assert np.isfinite(sout[f]).all(), f
+    g1 = parts["grid_p2g"].reshape(-1, 4).astype(np.float64)
+    g2 = parts["grid_upd"].reshape(-1, 4)
+    m_tot = n * float(w.p_mass)
+    assert abs(g1[:, 3].sum() - m_tot) <= 1e-5 * m_tot, (g1[:, 3].sum(), m_tot)
+    v_in = sin["v"].astype(np.float64)
+    mom = float(w.p_mass) * v_in.sum(axis=1)
+    scale = float(w.p_mass) * np.abs(v_in).sum()
+    assert np.all(np.abs(g1[:, :d].sum(axis=0) - mom) <= 1e-5 * scale), (g1[:, :d].sum(axis=0), mom)
+
+    errs = check_window(w, parts, I0, J0, W)
     assert errs["particles"] > 100000 and errs["nodes"] > 10000 and errs["blocks"] > 100
 
 
@@ -208,13 +226,20 @@ def test_collapse_3d_full_size_properties():
     assert np.all(np.abs(g1[:, :d].sum(axis=0) - mom) <= 1e-5 * float(w.p_mass) * np.abs(v_in).sum())
 
 
+# window origin (block multiples) and width in coarse cells, and the least
+# particles, nodes and blocks compared
+COARSE_WINDOWS = {4: (20, 240, 24, (10000, 2000, 20)), 2: (40, 480, 32, (50000, 8000, 100))}
+
+
 @pytest.mark.parametrize("h", [4, 2])
 def test_landslide_coarse(h):
     """The landslide coarsened to dx = 4 m (312,480 particles, 512 x 512 x 64
     cells) and 2 m (2,480,000 particles, 1024 x 1024 x 128 cells), the
-    resolution sweep of the bench: whole-step properties after 10 steps, and
-    the sparse and the dense grid giving the same positions after 10 steps
-    (within 4 float32 ulps of the largest coordinate)."""
+    resolution sweep of the bench: whole-step properties after 10 steps, the
+    sparse and the dense grid giving the same positions after 10 steps
+    (within 4 float32 ulps of the largest coordinate), and the next step of a
+    window of the slide against the FP64 oracle, node by node and particle by
+    particle (check_window)."""
     from paper_2605_28525_amd import mpm as M
     w = wl.landslide(h=h)
     n, d = w.n, w.dim
@@ -250,3 +275,8 @@ def test_landslide_coarse(h):
     ulp = float(np.spacing(np.float32(np.max(np.abs(xs[M.MPM_GRID_SPARSE])))))
     print("sparse - dense max |dx|", diff, "ulp", ulp, flush=True)
     assert diff <= 4 * ulp, (diff, ulp)
+    # one step of a window of the coarse slide against the oracle (window in
+    # coarse cells, inside the release footprint)
+    i0, j0, width, need = COARSE_WINDOWS[h]
+    errs = check_window(w, parts, i0, j0, width, h=h)
+    assert errs["particles"] > need[0] and errs["nodes"] > need[1] and errs["blocks"] > need[2], errs
