@@ -23,7 +23,8 @@ import pytest
 
 from oracle import mpm as om
 from paper_2605_28525_amd import workloads as wl
-from parity_util import RTOL, assert_field, block_coords_of, gpu_step_parts, grid_nodes, oracle_reference, tau_floor
+from parity_util import (RTOL, assert_field, block_coords_of, compare_step, gpu_step_parts, grid_nodes,
+                         oracle_reference, tau_floor)
 
 pytestmark = pytest.mark.gpu
 
@@ -196,12 +197,14 @@ def test_ensemble_full_size():
         batch.close()
 
 
-def test_collapse_3d_full_size_properties():
+def test_collapse_3d_full_size():
     """The 3D column collapse at full size (2,097,152 particles, 512 x 128 x 128
-    cells; the 1/8-scale copy is compared with the oracle in the parity tests):
-    one step after 10 in the benchmarked configuration, checked by the
+    cells): one step after 10 in the benchmarked configuration, checked by the
     whole-step properties (status, permutation and ids, finite outputs, grid
-    mass and momentum)."""
+    mass and momentum) and against the FP64 oracle's step from the same state
+    over the whole domain (active blocks and node masks bit-exact, every node
+    and every particle at the parity tolerance; about 1.5 minutes of oracle
+    time on the host)."""
     from paper_2605_28525_amd import mpm as M
     w = wl.collapse_3d()
     n, d = w.n, w.dim
@@ -224,6 +227,8 @@ def test_collapse_3d_full_size_properties():
     v_in = parts["state_in"]["v"].astype(np.float64)
     mom = float(w.p_mass) * v_in.sum(axis=1)
     assert np.all(np.abs(g1[:, :d].sum(axis=0) - mom) <= 1e-5 * float(w.p_mass) * np.abs(v_in).sum())
+    print("oracle step of the whole collapse ...", flush=True)
+    print(compare_step(w, parts), flush=True)
 
 
 # window origin (block multiples) and width in coarse cells, and the least
