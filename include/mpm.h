@@ -237,8 +237,10 @@ int mpm_g2p(mpm_ctx* ctx, const mpm_particles* in, const mpm_particles* out, voi
  * n_steps is even and in b when it is odd.  Between two steps of one call,
  * G2P also bins the positions it writes (the float64 arithmetic of the build's
  * binning on the same float32 values), so the next build skips its binning
- * pass; the results are those of the four calls made one after the other
- * (contexts with MPM_FLAG_ADJOINT bin in every build). */
+ * pass, and on a sparse grid P2G's second pass applies the grid update (the
+ * momenta between the two are never stored); the results are those of the
+ * four calls made one after the other (contexts with MPM_FLAG_ADJOINT bin in
+ * every build and keep the separate grid update). */
 int mpm_step(mpm_ctx* ctx, const mpm_particles* a, const mpm_particles* b, int n_steps, void* stream);
 
 /* Synchronises `stream` and returns the sticky MPM_FLAG_* word in *flags;

@@ -17,14 +17,20 @@
 //                   with a compare-and-swap on EMPTY (Algorithm 6), and ORs the
 //                   node mask into the slot.  The owner run boundaries of the
 //                   sorted order are recorded per slot.
+//   (after an incremental re-sort the insertion runs per re-sort entry
+//   instead, k_hash_insert_entries, from the entry's per-cell table)
 //   compaction      prefix scan over occupied slots -> Phi in slot order; block
 //                   keys, masks and owner segments in Phi order; overflow when
 //                   more than block_capacity slots are occupied (the counter
-//                   check of Algorithm 6).
-//   block setup     upper- and lower-neighbour compact indices (so P2G/G2P never probe),
-//                   chunking of owner segments into work items (the dense
-//                   baseline also clears its grid; the sparse P2G writes
-//                   every node of every active block).
+//                   check of Algorithm 6); the same scan numbers the work
+//                   items (owner segments in chunks) in Phi order and writes
+//                   them, except for the key-ordered Phi, whose items follow
+//                   from a scan of per-block counts after the reordering.
+//   block setup     upper- and lower-neighbour compact indices (so P2G/G2P
+//                   never probe) and the per-block state the next incremental
+//                   re-sort's counting in G2P needs (the dense baseline also
+//                   clears its grid; the sparse P2G writes every node of every
+//                   active block).
 #include "internal.h"
 #include "../../include/mpm.h"
 

@@ -9,12 +9,14 @@
 //   P2G: one wave per owner block accumulates the mass and momentum of the
 //        block's particles into an LDS tile and stores the tile to its own slot
 //        in HBM; a second pass gives each node the sum of the (at most 2^d)
-//        tiles that cover it.  No global atomics, and node sums do not depend
-//        on scheduling.  (The dense baseline flushes its tiles with global
-//        float atomics instead, at most 4 per non-zero tile node.)
+//        tiles that cover it (inside mpm_step it also applies the grid
+//        update).  No global atomics, and node sums do not depend on
+//        scheduling.  (The dense baseline flushes its tiles with global float
+//        atomics instead, at most 4 per non-zero tile node.)
 //   G2P: a workgroup stages the tile's updated nodal velocities in LDS, then each
 //        thread gathers its 3^d nodes, updates the particle and writes it to its
-//        sorted position (structure-of-arrays, coalesced).
+//        output position (structure-of-arrays, coalesced; the layout P2G
+//        recorded for the next P2G's lanes).
 //
 // Weights: with s = x/dx - 1/2 in float64, b = floor(s), t = s - b and u = 1 - t
 // (both rounded once to float32, so small weights keep their relative accuracy)
