@@ -454,8 +454,10 @@ int build_once(mpm_ctx* c, const mpm_particles* p, hipStream_t s, bool reuse, bo
         }
         // keys_ready: the G2P that binned also counted stayers and listed movers.
         // The sorted keys are not written: P2G reads each block's cell ranges
-        // from the re-sort's table, and the next re-sort reads no previous key.
-        e = launch_resort(c->P, fresh, nullptr, vo, c->movers, n, 1u << c->H_log2, c->partials, s, keys_ready);
+        // from the re-sort's table, and the next re-sort reads no previous key,
+        // so the previous keys' buffer holds the movers' targets instead.
+        e = launch_resort(c->P, fresh, nullptr, vo, c->movers, prev, n, 1u << c->H_log2, c->partials, s,
+                          keys_ready);
         if (e != hipSuccess) return MPM_ERR_HIP;
         ko = prev;
     } else {

@@ -489,7 +489,10 @@ __global__ __launch_bounds__(WG) void k_block_setup(DevParams P) {
             }
         }
     }
-    if (P.rs_stay && blockIdx.x == 0 && threadIdx.x == 0) P.ctr->rs_n_mov = 0;
+    if (P.rs_stay && blockIdx.x == 0 && threadIdx.x == 0) {
+        P.ctr->rs_n_mov = 0;  // the movers the next G2P lists
+        P.ctr->rs_n_new = 0;  // the new blocks the next re-sort's route claims
+    }
 }
 
 __global__ __launch_bounds__(WG) void k_work_write(DevParams P) {

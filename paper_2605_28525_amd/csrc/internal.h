@@ -415,9 +415,10 @@ int radix_hist_size(int n);
 hipError_t launch_bin(const DevParams& P, const float* x, const uint32_t* inst, int n, uint32_t* keys, hipStream_t s);
 // keys_out may be null: the sorted keys are then not written (after an
 // incremental re-sort nothing reads them; P2G takes the cell ranges from the
-// re-sort's per-entry table)
+// re-sort's per-entry table).  movers and tgt: n entries each (the mover list
+// and each mover's target, which the route records for the placement).
 hipError_t launch_resort(const DevParams& P, const uint32_t* keys_new, uint32_t* keys_out, uint32_t* vals_out,
-                         uint32_t* movers, int n, unsigned H, unsigned* partials, hipStream_t s,
+                         uint32_t* movers, uint32_t* tgt, int n, unsigned H, unsigned* partials, hipStream_t s,
                          bool counted = false);
 hipError_t launch_resort_init(const DevParams& P, unsigned H, hipStream_t s);
 // Buffers of the ascending-key Phi order (MPM_FLAG_DETERMINISTIC_ORDER): block

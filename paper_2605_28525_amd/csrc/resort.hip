@@ -22,7 +22,8 @@
 //            hash table and the block's per-cell mover count and particle
 //            count incremented, or, for a block without a previous slot, a
 //            slot of a second hash table is claimed (the claiming thread
-//            appends it to a list) and counted;
+//            appends it to a list) and counted; the mover's target (entry
+//            or slot) is recorded for the placement;
 //   new      one wave per listed slot: the second table's blocks become the
 //            entries after the previous blocks, in claim order;
 //   totals   (only without the G2P's counting) particles per entry = stayers
@@ -35,8 +36,9 @@
 //            thread per mover: movers go after the stayers of their cell, each
 //            taking the position its atomic decrement of the cell's mover
 //            count names (which leaves the counts at zero for the next build);
-//   reset    the second table is cleared for the next build, and the block
-//            hash for the insertion that follows.
+//            the stayer pass also clears the tables the route has finished
+//            with: the block hash for the insertion that follows and the
+//            second table's keys for the next build.
 // Cost: two reads of the new keys and one write of keys and values, against
 // 2-4 full read/write passes of the radix sort.  The per-block kernels only
 // stream keys; the dependent lookups of the few movers run one per thread, so
@@ -199,9 +201,15 @@ __global__ __launch_bounds__(WG) void k_rs_list(DevParams P, const uint32_t* __r
 }
 
 // route: one thread per mover.
+// Target of a mover, recorded by the route for the placement: its previous
+// entry, or (RS_TGT_NEW | slot) a slot of the second table, or RS_TGT_NONE.
+constexpr uint32_t RS_TGT_NEW = 0x80000000u;
+constexpr uint32_t RS_TGT_NONE = 0xFFFFFFFFu;
+
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_rs_route(DevParams P, const uint32_t* __restrict__ keys_new,
-                                                 const uint32_t* __restrict__ movers, int n) {
+                                                 const uint32_t* __restrict__ movers, uint32_t* __restrict__ tgt,
+                                                 int n) {
     constexpr int CB = 2 * DIM, NC = 1 << CB;
     const int m = min(P.ctr->rs_n_mov, n);
     for (int t = blockIdx.x * WG + threadIdx.x; t < m; t += gridDim.x * WG) {
@@ -209,9 +217,11 @@ __global__ __launch_bounds__(WG) void k_rs_route(DevParams P, const uint32_t* __
         const uint32_t cell = k & (NC - 1);
         const uint64_t K = owner_block_key<DIM>(P, k >> CB);
         const int phi = hash_lookup(P, K);
+        uint32_t target = RS_TGT_NONE;
         if (phi >= 0) {
             atomicAdd(&P.rs_in[(size_t)phi * NC + cell], 1u);
             atomicAdd(&P.rs_cnt[phi], 1u);
+            target = (uint32_t)phi;
         } else {
             bool claimed;
             const int slot = nh_insert(P, K, &claimed);
@@ -223,10 +233,12 @@ __global__ __launch_bounds__(WG) void k_rs_route(DevParams P, const uint32_t* __
                     const int j = atomicAdd(&P.ctr->rs_n_new, 1);
                     if (j < P.block_cap) P.rs_new[j] = (uint32_t)slot;
                 }
+                target = RS_TGT_NEW | (uint32_t)slot;
             } else {
                 raise_flag(P.ctr, MPM_FLAG_OVERFLOW);
             }
         }
+        tgt[t] = target;
     }
 }
 
@@ -304,7 +316,7 @@ constexpr uint32_t RS_EMPTY = 0xFFFFFFFFu;  // staging slot left to a mover (ind
 template <int DIM, bool KEYS>
 __global__ __launch_bounds__(WG) void k_rs_place(DevParams P, const uint32_t* __restrict__ keys_new,
                                                  uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
-                                                 int n) {
+                                                 int n, unsigned H) {
     constexpr int CB = 2 * DIM, NC = 1 << CB;
     __shared__ unsigned run[WG / 64][64];
     __shared__ uint32_t sk[WG / 64][KEYS ? RS_STAGE : 1], sv[WG / 64][RS_STAGE];
@@ -385,28 +397,44 @@ __global__ __launch_bounds__(WG) void k_rs_place(DevParams P, const uint32_t* __
         }
     }
     if (bad) raise_flag(P.ctr, MPM_FLAG_OVERFLOW);
+    // The tables the route has finished with are cleared here, behind the
+    // placement's latency-bound work: the block hash for the insertion that
+    // follows (Algorithm 5's initialisation) and the second table's keys for
+    // the next re-sort.  (The movers' placement reads the route's recorded
+    // targets, not the tables.)
+    for (long long t = (long long)blockIdx.x * WG + threadIdx.x; t < (long long)H; t += (long long)gridDim.x * WG) {
+        P.nh_keys[t] = EMPTY_KEY;
+        P.h_keys[t] = EMPTY_KEY;
+        P.h_mask[t] = 0ull;
+        P.h_start[t] = -1;
+        P.h_end[t] = -1;
+        P.h_entry[t] = -1;
+    }
 }
 
 // place, movers: one thread per mover, after the stayers of its cell.
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_rs_place_movers(DevParams P, const uint32_t* __restrict__ keys_new,
                                                         const uint32_t* __restrict__ movers,
+                                                        const uint32_t* __restrict__ tgt,
                                                         uint32_t* __restrict__ keys_out,
                                                         uint32_t* __restrict__ vals_out, int n) {
     constexpr int CB = 2 * DIM, NC = 1 << CB;
     const int m = min(P.ctr->rs_n_mov, n);
     const int ne = P.ctr->rs_n_ent;
+    const int nb = min(P.ctr->nb, P.block_cap);
     bool bad = false;
     for (int t = blockIdx.x * WG + threadIdx.x; t < m; t += gridDim.x * WG) {
         const uint32_t i = movers[t];
         const uint32_t k = keys_new[i];
         const uint32_t cell = k & (NC - 1);
-        const uint64_t K = owner_block_key<DIM>(P, k >> CB);
-        int e2 = hash_lookup(P, K);
-        const bool prev = e2 >= 0;
-        if (!prev) {
-            const int slot = nh_lookup(P, K);
-            e2 = slot >= 0 ? P.nh_idx[slot] : -1;
+        const uint32_t target = tgt[t];  // the route's lookup, so no table is probed again
+        const bool prev = (target & RS_TGT_NEW) == 0u;
+        int e2 = -1;
+        if (prev) {
+            e2 = (int)target < nb ? (int)target : -1;
+        } else if (target != RS_TGT_NONE) {
+            e2 = P.nh_idx[target & ~RS_TGT_NEW];
             if (e2 >= ne) e2 = -1;
         }
         if (e2 < 0) {
@@ -428,30 +456,6 @@ __global__ __launch_bounds__(WG) void k_rs_place_movers(DevParams P, const uint3
         }
     }
     if (bad) raise_flag(P.ctr, MPM_FLAG_OVERFLOW);
-}
-
-// reset: the second table's keys and entry indices (the movers' placement
-// has counted every entry's mover counts back to zero).
-template <int DIM>
-__global__ __launch_bounds__(WG) void k_rs_reset(DevParams P, unsigned H) {
-    for (long long t = (long long)blockIdx.x * WG + threadIdx.x; t < (long long)H; t += (long long)gridDim.x * WG) {
-        P.nh_keys[t] = EMPTY_KEY;
-        P.nh_idx[t] = -1;
-        // the block hash, which the re-sort was the last to read, is cleared
-        // here for the insertion that follows (Algorithm 5's initialisation)
-        P.h_keys[t] = EMPTY_KEY;
-        P.h_mask[t] = 0ull;
-        P.h_start[t] = -1;
-        P.h_end[t] = -1;
-        P.h_entry[t] = -1;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        P.ctr->rs_n_mov = 0;
-        P.ctr->rs_n_new = 0;
-        P.ctr->nb = 0;
-        P.ctr->n_touched = 0;
-        P.ctr->n_work = 0;
-    }
 }
 
 // Initial state of the buffers the re-sort expects between builds.
@@ -491,7 +495,8 @@ hipError_t launch_resort_init(const DevParams& P, unsigned H, hipStream_t s) {
 // previous block and cell, the owner part of each previous block and the
 // mover list (in any order) with its length; count and list are skipped.
 hipError_t launch_resort(const DevParams& P, const uint32_t* keys_new, uint32_t* keys_out, uint32_t* vals_out,
-                         uint32_t* movers, int n, unsigned H, unsigned* partials, hipStream_t s, bool counted) {
+                         uint32_t* movers, uint32_t* tgt, int n, unsigned H, unsigned* partials, hipStream_t s,
+                         bool counted) {
     const int gw = grid_for_waves(P.block_cap);
     const int ge = grid_for_waves(2ll * P.block_cap);
     const int gm = (int)std::min<long long>(((long long)n + WG - 1) / WG, 2048);  // grid-stride over the movers
@@ -510,9 +515,9 @@ hipError_t launch_resort(const DevParams& P, const uint32_t* keys_new, uint32_t*
             k_rs_list<2><<<gw, WG, 0, s>>>(P, keys_new, movers, n);
     }
     if (P.dim == 3)
-        k_rs_route<3><<<gm, WG, 0, s>>>(P, keys_new, movers, n);
+        k_rs_route<3><<<gm, WG, 0, s>>>(P, keys_new, movers, tgt, n);
     else
-        k_rs_route<2><<<gm, WG, 0, s>>>(P, keys_new, movers, n);
+        k_rs_route<2><<<gm, WG, 0, s>>>(P, keys_new, movers, tgt, n);
     const int gn = 256;  // workgroups, grid-stride over the new blocks (a few hundred per step)
     if (P.dim == 3)
         k_rs_new_write<3><<<gn, WG, 0, s>>>(P);
@@ -528,18 +533,16 @@ hipError_t launch_resort(const DevParams& P, const uint32_t* keys_new, uint32_t*
     if (e != hipSuccess) return e;
     if (P.dim == 3) {
         if (keys_out)
-            k_rs_place<3, true><<<ge, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n);
+            k_rs_place<3, true><<<ge, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n, H);
         else
-            k_rs_place<3, false><<<ge, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n);
-        k_rs_place_movers<3><<<gm, WG, 0, s>>>(P, keys_new, movers, keys_out, vals_out, n);
-        k_rs_reset<3><<<grid_for_waves((long long)H / 64), WG, 0, s>>>(P, H);
+            k_rs_place<3, false><<<ge, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n, H);
+        k_rs_place_movers<3><<<gm, WG, 0, s>>>(P, keys_new, movers, tgt, keys_out, vals_out, n);
     } else {
         if (keys_out)
-            k_rs_place<2, true><<<ge, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n);
+            k_rs_place<2, true><<<ge, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n, H);
         else
-            k_rs_place<2, false><<<ge, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n);
-        k_rs_place_movers<2><<<gm, WG, 0, s>>>(P, keys_new, movers, keys_out, vals_out, n);
-        k_rs_reset<2><<<grid_for_waves((long long)H / 64), WG, 0, s>>>(P, H);
+            k_rs_place<2, false><<<ge, WG, 0, s>>>(P, keys_new, keys_out, vals_out, n, H);
+        k_rs_place_movers<2><<<gm, WG, 0, s>>>(P, keys_new, movers, tgt, keys_out, vals_out, n);
     }
     return hipGetLastError();
 }
