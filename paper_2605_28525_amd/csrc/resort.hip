@@ -94,17 +94,6 @@ __device__ int nh_insert(const DevParams& P, uint64_t K, bool* claimed) {
     return -1;
 }
 
-__device__ int nh_lookup(const DevParams& P, uint64_t K) {
-    unsigned s = (unsigned)mix64(K) & P.h_mask_bits;
-    for (int r = 0; r < P.n_probe; ++r) {
-        const uint64_t cur = P.nh_keys[s];
-        if (cur == K) return (int)s;
-        if (cur == EMPTY_KEY) return -1;
-        s = (s + 1) & P.h_mask_bits;
-    }
-    return -1;
-}
-
 }  // namespace
 
 constexpr int RS_BATCH = 8;  // 64-particle chunks of a segment whose keys are loaded together
