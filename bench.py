@@ -625,8 +625,8 @@ def cpu_full_runs():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design "
-                                   "(see DESIGN.md), not an implemented path", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the step runs on one GPU only: sharding it over several GPUs is "
+                                   "designed but not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
     from paper_2605_28525_amd import mpm as M

@@ -82,7 +82,7 @@ def _check_step_adjoint(w, st, seed):
     try:
         pin = M.ParticleSet.from_arrays(st)
         M.mpm_sparse_build(ctx, pin.view())
-        M.mpm_p2g(ctx, pin.view())  # records the G2P output permutation of this build
+        M.mpm_p2g(ctx, pin.view())  # records the G2P output permutation of this block set
         order = torch.zeros(n, dtype=torch.int32, device="cuda")
         M.mpm_get_order(ctx, order, n)
         o = order.cpu().numpy().astype(np.int64)
